@@ -1,0 +1,190 @@
+/*
+ * tmqcd.h - C interface of the MI355X (gfx950) twisted-mass Wilson library.
+ *
+ * Operation (Bach, Lindenstruth, Philipsen, Pinke, "Lattice QCD based on
+ * OpenCL", arXiv:1209.5942, section 2.1, the definition of D_tm):
+ *
+ *   M = D_tm^+ = A - kappa*H,   A = 1 + i*2*kappa*mu*gamma5,
+ *   (H psi)(x) = sum_mu [ b+_mu(x) (1 - gamma_mu) U_mu(x)       psi(x + mu)
+ *                       + b-_mu(x) (1 + gamma_mu) U_mu(x - mu)^+ psi(x - mu) ]
+ *
+ * The paper prints the hopping prefactor as kappa/2; this library uses kappa
+ * (with kappa = 1/(2(am + 4)) the free massless operator then has its zero mode
+ * at kappa = 1/8).  b+_mu(x) = bc_mu if x_mu = L_mu - 1 and 1 otherwise;
+ * b-_mu(x) = conj(bc_mu) if x_mu = 0 and 1 otherwise: the boundary phase sits
+ * only on hops that cross the lattice boundary.  The paper's Dslash is -kappa*H.
+ *
+ * Conventions
+ *   - Site index s = x + Lx*(y + Ly*(z + Lz*t)), x fastest; direction
+ *     mu = 0,1,2,3 <-> x,y,z,t.  Parity (x+y+z+t) mod 2, even = 0.  A field on
+ *     one parity ("half field") is indexed by h = s >> 1.  All four extents must
+ *     be even and >= 2.
+ *   - Gamma matrices (the paper fixes only their anticommutator): chiral basis
+ *     gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] for k = x,y,z,
+ *     gamma_t = [[0, -1], [-1, 0]], gamma5 = gamma_x gamma_y gamma_z gamma_t
+ *     = diag(-1, -1, +1, +1).  Spin index 0..3 in this basis.
+ *   - Canonical (user-visible) layouts, complex128 = two doubles (re, im):
+ *       gauge   U[V][4][3][3]   U[s][mu][a][b] = (U_mu(s))_ab, the link s -> s+mu
+ *       spinor  psi[V][4][3]    full field, or psi[Vh][4][3] for one parity
+ *       multi-RHS fields are [nrhs][...] with the single-field layout inside
+ *       force   dSdw[V][4][8]   float64, coefficient of T^a = lambda^a / 2
+ *   - Packed (device) layouts are opaque; their sizes come from the *_bytes
+ *     queries.  Internally fields are structure-of-arrays over sites with a
+ *     16-byte base type, links split by the parity of their origin site (the
+ *     paper's storage-format section).  A packed full spinor holds the even
+ *     half followed by the odd half.
+ *
+ * Ownership and streams
+ *   - Every pointer argument that names a field is a DEVICE pointer owned by
+ *     the caller; the library never allocates device memory.  Scratch memory
+ *     comes from the caller's workspace `ws` of `ws_bytes` bytes, sized by
+ *     tmqcd_workspace_bytes.  Problem, option and stats structs are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     tmqcd_pack_*, tmqcd_unpack_spinor, tmqcd_dslash and tmqcd_force are
+ *     stream-ordered and return without waiting.  tmqcd_cg synchronises the
+ *     stream (it reads residuals back) and returns when the solve has ended.
+ *   - No exceptions cross the interface; functions return TMQCD_OK (0) or a
+ *     negative error code.  Arguments are validated on the host before any HIP
+ *     call, so every argument error is reported without touching the device.
+ *     The library keeps no state between calls other than the last HIP error
+ *     code of the calling thread.
+ */
+#ifndef TMQCD_H
+#define TMQCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define TMQCD_OK           0
+#define TMQCD_EINVAL      -1  /* bad extent, NULL pointer, unknown op/prec/recon, nrhs out of range */
+#define TMQCD_EALIAS      -2  /* output overlaps an input it may not overlap */
+#define TMQCD_EALIGN      -3  /* a device pointer is not 256-byte aligned */
+#define TMQCD_ENOCONV     -4  /* max_iter reached; x holds the last iterate, stats are filled */
+#define TMQCD_EBREAKDOWN  -5  /* NaN/Inf residual or p^+ A p <= 0 in CG */
+#define TMQCD_EHIP        -6  /* a HIP call failed; see tmqcd_last_hip_error() */
+#define TMQCD_EWORKSPACE  -7  /* ws is NULL or smaller than tmqcd_workspace_bytes() */
+
+/* ---- problem description --------------------------------------------------- */
+typedef struct {
+    int32_t dims[4];   /* Lx, Ly, Lz, Lt: each even and >= 2 */
+    double kappa;      /* hopping parameter */
+    double mu;         /* twisted mass a*mu (dimensionless) */
+    double bc[4][2];   /* boundary phase (re, im) of direction mu; (1,0) periodic, (-1,0) antiperiodic */
+} tmqcd_problem;
+
+/* storage precisions; arithmetic is FP64 for TMQCD_F64 and FP32 otherwise */
+#define TMQCD_F64 0
+#define TMQCD_F32 1
+#define TMQCD_F16 2   /* IEEE half: links unscaled (|U_ab| <= 1), spinors with one FP32 scale per site */
+
+/* link storage: all 18 reals, or the first two rows (12 reals) with the third
+ * rebuilt as conj(row1 x row2), exact for det U = 1 (the paper's REC12) */
+#define TMQCD_RECON18 0
+#define TMQCD_RECON12 1
+
+/* spinor subsets */
+#define TMQCD_FULL 0
+#define TMQCD_EVEN 1
+#define TMQCD_ODD  2
+
+/* operators for tmqcd_dslash (the paper's section 2.1; even-odd preconditioning
+ * as the Schur complement on even sites) */
+#define TMQCD_DSLASH_EO     0  /* even <- odd:  out_e = -kappa H_eo in_o  */
+#define TMQCD_DSLASH_OE     1  /* odd <- even:  out_o = -kappa H_oe in_e  */
+#define TMQCD_M             2  /* full:  M = A - kappa H                      */
+#define TMQCD_MDAG          3  /* full:  M^+ = A^+ - kappa H^+                */
+#define TMQCD_MDAGM         4  /* full:  M^+ M                                */
+#define TMQCD_MHAT          5  /* even:  Mhat = A_ee - kappa^2 H_eo A_oo^{-1} H_oe */
+#define TMQCD_MHATDAG       6  /* even:  Mhat^+                               */
+#define TMQCD_MHATDAGMHAT   7  /* even:  Mhat^+ Mhat                          */
+
+/* ---- size queries (host only, never fail: 0 means invalid arguments) -------- */
+size_t tmqcd_gauge_bytes(const tmqcd_problem* prob, int prec, int recon);
+size_t tmqcd_spinor_bytes(const tmqcd_problem* prob, int prec, int subset, int nrhs);
+/* Workspace for tmqcd_dslash (op), tmqcd_cg (op = TMQCD_MDAGM or
+ * TMQCD_MHATDAGMHAT) and tmqcd_force (op = -1).  prec_mask: bit (1 << prec) for
+ * every storage precision the call will use (for CG: F64 and the inner one). */
+size_t tmqcd_workspace_bytes(const tmqcd_problem* prob, int op, int prec_mask, int nrhs);
+
+/* ---- layout conversion (the paper's transparent AoS <-> SoA conversion) ----- */
+/* Pack a canonical complex128 gauge field U_canon[V][4][3][3] (device) into the
+ * packed layout of (prec, recon).  Rounds to nearest even on down-conversion. */
+int tmqcd_pack_gauge(const tmqcd_problem* prob, const void* U_canon, void* U_packed,
+                     int prec, int recon, void* stream);
+/* Pack canonical complex128 spinors [nrhs][n][4][3] (n = V for TMQCD_FULL, V/2
+ * otherwise) into the packed layout of prec.  in_canon and out_packed must not
+ * overlap. */
+int tmqcd_pack_spinor(const tmqcd_problem* prob, const void* in_canon, void* out_packed,
+                      int prec, int subset, int nrhs, void* stream);
+/* Inverse of tmqcd_pack_spinor: packed -> canonical complex128. */
+int tmqcd_unpack_spinor(const tmqcd_problem* prob, const void* in_packed, void* out_canon,
+                        int prec, int subset, int nrhs, void* stream);
+
+/* ---- the operator ------------------------------------------------------------ */
+/* out = op(in) for nrhs packed fields of precision prec (in and out: the subset
+ * the op acts on - odd input/even output for DSLASH_EO, even/odd for DSLASH_OE,
+ * full for M*, even for MHAT*).  U_packed must be packed with (prec, recon).
+ * out must not overlap in.  nrhs in [1, 16]; nrhs > 1 reuses each link load
+ * across the right-hand sides. */
+int tmqcd_dslash(const tmqcd_problem* prob, const void* U_packed, const void* in, void* out,
+                 int op, int prec, int recon, int nrhs, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- the solver: CG on M^+M (full) or Mhat^+ Mhat (even sites) -------------- */
+typedef struct {
+    double  tol;             /* stop when ||b - A x||_2 / ||b||_2 <= tol, recomputed in FP64 */
+    int32_t max_iter;        /* cap on (inner) CG iterations */
+    int32_t op;              /* TMQCD_MDAGM or TMQCD_MHATDAGMHAT */
+    int32_t inner_prec;      /* TMQCD_F64: plain FP64 CG; TMQCD_F32 / TMQCD_F16: mixed precision */
+    int32_t recon;           /* link storage of every U_packed[] given */
+    double  reliable_delta;  /* mixed: reliable update when the residual fell by this factor (0 -> 0.1) */
+    int32_t check_every;     /* iterations queued between host residual checks (0 -> 8) */
+    int32_t x_is_zero;       /* 1: ignore the contents of x and start from x0 = 0 */
+} tmqcd_cg_opts;
+
+typedef struct {
+    int32_t iters;             /* CG iterations (inner iterations for mixed precision) */
+    int32_t reliable_updates;  /* FP64 residual recomputations inside the solve */
+    int32_t converged;         /* 1 if the true residual met tol */
+    int32_t hop_launches;      /* hop kernels launched (for bandwidth accounting) */
+    double  true_rel_residual; /* ||b - A x|| / ||b|| in FP64 at exit */
+    double  iter_rel_residual; /* recursively updated residual at exit */
+    double  seconds;           /* host wall time of the call */
+} tmqcd_cg_stats;
+
+/* Solve A x = b, A = op.  b and x are packed FP64 fields (full for MDAGM, even
+ * for MHATDAGMHAT); x may not overlap b.  U_packed[p] is the gauge field packed
+ * at precision p (index TMQCD_F64/F32/F16) with opts->recon; U_packed[TMQCD_F64]
+ * is always required, U_packed[inner_prec] for mixed precision; unused entries
+ * may be NULL.  Mixed precision runs the inner CG with FP32 or FP16 Dslash
+ * storage and FP64 reductions, and restarts it with an FP64 residual b - A x
+ * whenever the iterated residual dropped by reliable_delta (defect correction
+ * with reliable updates).  Returns TMQCD_ENOCONV if max_iter was reached. */
+int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const void* b, void* x,
+             const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes,
+             void* stream);
+
+/* ---- the fermion force -------------------------------------------------------- */
+/* dSdw[V][4][8] (device, float64, canonical): the gradient of
+ * S_f = phi^+ (M^+ M)^{-1} phi with respect to w^a for U_mu(x) -> exp(i w^a T^a) U_mu(x),
+ * given X = (M^+ M)^{-1} phi and Y = M X as packed FP64 full fields (the paper's
+ * force section: the fermion force needs one inversion and only the hopping
+ * part of M depends on U).  U_packed: FP64, RECON18 or RECON12.
+ * G^a = -2 kappa Im Tr[T^a (b+ Q1 - conj(b+) Q2)],
+ * Q1 = sum_spin [(1 - gamma_mu) U_mu(x) X(x+mu)] (x) Y(x)^+,
+ * Q2 = sum_spin X(x) (x) [U_mu(x) (1 + gamma_mu) Y(x+mu)]^+. */
+int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X,
+                const void* Y, double* dSdw, void* stream);
+
+/* ---- diagnostics ------------------------------------------------------------- */
+const char* tmqcd_error_string(int code);
+int tmqcd_last_hip_error(void);   /* hipError_t of the last failed HIP call in this thread */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMQCD_H */

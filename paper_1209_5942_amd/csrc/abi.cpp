@@ -1,0 +1,243 @@
+// The C interface: host-side argument validation (no HIP call before every
+// argument has been checked), dispatch to the operator and solver code, and
+// error reporting.  See include/tmqcd.h for the contract of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "device.h"
+#include "internal.h"
+#include "ops.h"
+#include "tmqcd.h"
+
+using namespace tmqcd;
+
+namespace {
+
+constexpr int kMaxRhs = 16;
+
+bool valid_problem(const tmqcd_problem* p) {
+    if (!p) return false;
+    int64_t v = 1;
+    for (int i = 0; i < 4; ++i) {
+        const int d = p->dims[i];
+        if (d < 2 || (d & 1)) return false;
+        v *= d;
+        if (v > (int64_t)1 << 32) return false;   // half volume must fit in int32 site indices
+    }
+    if (!std::isfinite(p->kappa) || !std::isfinite(p->mu)) return false;
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(p->bc[i][0]) || !std::isfinite(p->bc[i][1])) return false;
+    return true;
+}
+bool valid_prec(int p) { return p == TMQCD_F64 || p == TMQCD_F32 || p == TMQCD_F16; }
+bool valid_recon(int r) { return r == TMQCD_RECON18 || r == TMQCD_RECON12; }
+bool valid_subset(int s) { return s == TMQCD_FULL || s == TMQCD_EVEN || s == TMQCD_ODD; }
+bool valid_op(int op) { return op >= TMQCD_DSLASH_EO && op <= TMQCD_MHATDAGMHAT; }
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+bool overlap(const void* a, int64_t na, const void* b, int64_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + (uintptr_t)nb && y < x + (uintptr_t)na;
+}
+
+int in_subset(int op) {
+    switch (op) {
+        case TMQCD_DSLASH_EO: return TMQCD_ODD;
+        case TMQCD_DSLASH_OE: return TMQCD_EVEN;
+        case TMQCD_M:
+        case TMQCD_MDAG:
+        case TMQCD_MDAGM: return TMQCD_FULL;
+    }
+    return TMQCD_EVEN;
+}
+int out_subset(int op) {
+    switch (op) {
+        case TMQCD_DSLASH_EO: return TMQCD_EVEN;
+        case TMQCD_DSLASH_OE: return TMQCD_ODD;
+        case TMQCD_M:
+        case TMQCD_MDAG:
+        case TMQCD_MDAGM: return TMQCD_FULL;
+    }
+    return TMQCD_EVEN;
+}
+
+int hip_fail(hipError_t e) {
+    g_last_hip_error = (int)e;
+    return TMQCD_EHIP;
+}
+
+int64_t cg_workspace(const Geom& g, int op, int prec_mask) {
+    int64_t need = carve_cg(g, op, TMQCD_F64, nullptr).total;
+    if (prec_mask & (1 << TMQCD_F32)) {
+        const int64_t t = carve_cg(g, op, TMQCD_F32, nullptr).total;
+        need = t > need ? t : need;
+    }
+    if (prec_mask & (1 << TMQCD_F16)) {
+        const int64_t t = carve_cg(g, op, TMQCD_F16, nullptr).total;
+        need = t > need ? t : need;
+    }
+    return need;
+}
+
+int64_t dslash_workspace(const Geom& g, int op, int prec_mask) {
+    int64_t need = 0;
+    for (int p = 0; p < 3; ++p)
+        if (prec_mask & (1 << p)) {
+            const int64_t t = dslash_tmp_bytes(g, op, p);
+            need = t > need ? t : need;
+        }
+    return need;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tmqcd_gauge_bytes(const tmqcd_problem* prob, int prec, int recon) {
+    if (!valid_problem(prob) || !valid_prec(prec) || !valid_recon(recon)) return 0;
+    return (size_t)gauge_bytes(make_geom(*prob), prec, recon);
+}
+
+size_t tmqcd_spinor_bytes(const tmqcd_problem* prob, int prec, int subset, int nrhs) {
+    if (!valid_problem(prob) || !valid_prec(prec) || !valid_subset(subset) || nrhs < 1 || nrhs > kMaxRhs) return 0;
+    return (size_t)(nrhs * field_bytes(make_geom(*prob), prec, subset));
+}
+
+size_t tmqcd_workspace_bytes(const tmqcd_problem* prob, int op, int prec_mask, int nrhs) {
+    if (!valid_problem(prob) || nrhs < 1 || nrhs > kMaxRhs) return 0;
+    if (op == -1) return 256;   // the force needs no workspace
+    if (!valid_op(op) || (prec_mask & ~7) || prec_mask == 0) return 0;
+    const Geom g = make_geom(*prob);
+    int64_t need = dslash_workspace(g, op, prec_mask);
+    if (op == TMQCD_MDAGM || op == TMQCD_MHATDAGMHAT) {
+        const int64_t t = cg_workspace(g, op, prec_mask);
+        need = t > need ? t : need;
+    }
+    return (size_t)(need > 256 ? need : 256);
+}
+
+int tmqcd_pack_gauge(const tmqcd_problem* prob, const void* U_canon, void* U_packed, int prec, int recon,
+                     void* stream) {
+    if (!valid_problem(prob) || !valid_prec(prec) || !valid_recon(recon) || !U_canon || !U_packed) return TMQCD_EINVAL;
+    if (!aligned(U_canon, 16) || !aligned(U_packed, kAlignBytes)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    if (overlap(U_canon, 2 * g.vh * 4 * 9 * 16, U_packed, gauge_bytes(g, prec, recon))) return TMQCD_EALIAS;
+    const hipError_t e = launch_pack_gauge(g, U_canon, U_packed, prec, recon, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+static int pack_common(const tmqcd_problem* prob, const void* canon, const void* packed, int prec, int subset,
+                       int nrhs) {
+    if (!valid_problem(prob) || !valid_prec(prec) || !valid_subset(subset) || nrhs < 1 || nrhs > kMaxRhs || !canon ||
+        !packed)
+        return TMQCD_EINVAL;
+    if (!aligned(canon, 16) || !aligned(packed, kAlignBytes)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int64_t n = subset == TMQCD_FULL ? 2 * g.vh : g.vh;
+    if (overlap(canon, nrhs * n * 12 * 16, packed, nrhs * field_bytes(g, prec, subset))) return TMQCD_EALIAS;
+    return TMQCD_OK;
+}
+
+int tmqcd_pack_spinor(const tmqcd_problem* prob, const void* in_canon, void* out_packed, int prec, int subset,
+                      int nrhs, void* stream) {
+    const int rc = pack_common(prob, in_canon, out_packed, prec, subset, nrhs);
+    if (rc != TMQCD_OK) return rc;
+    const hipError_t e =
+        launch_pack_spinor(make_geom(*prob), in_canon, out_packed, prec, subset, nrhs, false, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_unpack_spinor(const tmqcd_problem* prob, const void* in_packed, void* out_canon, int prec, int subset,
+                        int nrhs, void* stream) {
+    const int rc = pack_common(prob, out_canon, in_packed, prec, subset, nrhs);
+    if (rc != TMQCD_OK) return rc;
+    const hipError_t e =
+        launch_pack_spinor(make_geom(*prob), out_canon, const_cast<void*>(in_packed), prec, subset, nrhs, true,
+                           (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_dslash(const tmqcd_problem* prob, const void* U_packed, const void* in, void* out, int op, int prec,
+                 int recon, int nrhs, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_problem(prob) || !valid_op(op) || !valid_prec(prec) || !valid_recon(recon) || nrhs < 1 ||
+        nrhs > kMaxRhs || !U_packed || !in || !out)
+        return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes) || !aligned(in, kAlignBytes) || !aligned(out, kAlignBytes))
+        return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int64_t fin = field_bytes(g, prec, in_subset(op)), fout = field_bytes(g, prec, out_subset(op));
+    if (overlap(in, nrhs * fin, out, nrhs * fout)) return TMQCD_EALIAS;
+    const int64_t need = dslash_tmp_bytes(g, op, prec);
+    if (need > 0) {
+        if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
+        if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+        if (overlap(ws, need, in, nrhs * fin) || overlap(ws, need, out, nrhs * fout)) return TMQCD_EALIAS;
+    }
+    const OpCtx c = make_ctx(*prob, prec, recon, U_packed, (hipStream_t)stream);
+    for (int k = 0; k < nrhs; ++k) {
+        const hipError_t e = apply_operator(c, op, static_cast<const char*>(in) + k * fin,
+                                            static_cast<char*>(out) + k * fout, static_cast<char*>(ws));
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return TMQCD_OK;
+}
+
+int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const void* b, void* x,
+             const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_problem(prob) || !U_packed || !b || !x || !opts || !stats) return TMQCD_EINVAL;
+    const tmqcd_cg_opts& o = *opts;
+    if (o.op != TMQCD_MDAGM && o.op != TMQCD_MHATDAGMHAT) return TMQCD_EINVAL;
+    if (!valid_prec(o.inner_prec) || !valid_recon(o.recon) || o.max_iter < 1) return TMQCD_EINVAL;
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol) || o.reliable_delta < 0 || o.reliable_delta >= 1 ||
+        o.check_every < 0)
+        return TMQCD_EINVAL;
+    if (!U_packed[TMQCD_F64] || !U_packed[o.inner_prec]) return TMQCD_EINVAL;
+    if (!aligned(b, kAlignBytes) || !aligned(x, kAlignBytes) || !aligned(U_packed[TMQCD_F64], kAlignBytes) ||
+        !aligned(U_packed[o.inner_prec], kAlignBytes))
+        return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int subset = o.op == TMQCD_MDAGM ? TMQCD_FULL : TMQCD_EVEN;
+    const int64_t fb = field_bytes(g, TMQCD_F64, subset);
+    if (overlap(b, fb, x, fb)) return TMQCD_EALIAS;
+    const int64_t need = carve_cg(g, o.op, o.inner_prec, nullptr).total;
+    if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
+    if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+    if (overlap(ws, need, b, fb) || overlap(ws, need, x, fb)) return TMQCD_EALIAS;
+    return run_cg(*prob, U_packed, b, x, o, *stats, ws, (hipStream_t)stream);
+}
+
+int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X, const void* Y,
+                double* dSdw, void* stream) {
+    if (!valid_problem(prob) || !valid_recon(recon) || !U_packed || !X || !Y || !dSdw) return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes) || !aligned(X, kAlignBytes) || !aligned(Y, kAlignBytes) ||
+        !aligned(dSdw, 16))
+        return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int64_t fb = field_bytes(g, TMQCD_F64, TMQCD_FULL), ob = 2 * g.vh * 4 * 8 * 8;
+    if (overlap(dSdw, ob, X, fb) || overlap(dSdw, ob, Y, fb) || overlap(dSdw, ob, U_packed, gauge_bytes(g, TMQCD_F64, recon)))
+        return TMQCD_EALIAS;
+    Cplx bc[4];
+    for (int i = 0; i < 4; ++i) bc[i] = {prob->bc[i][0], prob->bc[i][1]};
+    const hipError_t e = launch_force(g, U_packed, recon, X, Y, dSdw, bc, prob->kappa, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+const char* tmqcd_error_string(int code) {
+    switch (code) {
+        case TMQCD_OK: return "success";
+        case TMQCD_EINVAL: return "invalid argument (extent, pointer, op, precision, reconstruction or nrhs)";
+        case TMQCD_EALIAS: return "output overlaps an input";
+        case TMQCD_EALIGN: return "device pointer not aligned (256 bytes for packed fields, 16 for canonical)";
+        case TMQCD_ENOCONV: return "CG did not converge within max_iter";
+        case TMQCD_EBREAKDOWN: return "CG breakdown (non-finite residual or p^+ A p <= 0)";
+        case TMQCD_EHIP: return "HIP runtime error (see tmqcd_last_hip_error)";
+        case TMQCD_EWORKSPACE: return "workspace missing or smaller than tmqcd_workspace_bytes";
+    }
+    return "unknown error code";
+}
+
+int tmqcd_last_hip_error(void) { return g_last_hip_error; }
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+// BLAS-1 on packed spinor fields (the paper's "LAPACK" kernels: saxpy and
+// scalar products) with deterministic FP64 reductions, plus the solver-state
+// kernels that keep CG scalars on the device.
+#include "device.h"
+#include "internal.h"
+
+namespace tmqcd {
+namespace {
+
+struct VecK {
+    int64_t stride;
+    int vh;
+    int nhalf;
+    int nblocks;
+};
+
+__device__ __forceinline__ bool site_of(const VecK& v, int i, int& half, int& h) {
+    if (i >= v.nhalf * v.vh) return false;
+    half = i / v.vh;
+    h = i - half * v.vh;
+    return true;
+}
+
+VecK make_veck(const VecSpec& s) {
+    VecK k;
+    k.stride = s.g->stride;
+    k.vh = (int)s.g->vh;
+    k.nhalf = s.nhalf;
+    k.nblocks = (int)((s.nhalf * s.g->vh + kBlock - 1) / kBlock);
+    return k;
+}
+
+template <int PD, int PS>
+__global__ __launch_bounds__(kBlock) void convert_kernel(VecK v, char* dst, int64_t dbytes, const char* src,
+                                                         int64_t sbytes) {
+    int half, h;
+    if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
+    Spinor<double> a;
+    if constexpr (PS == TMQCD_F64) {
+        SpinorIO<TMQCD_F64>::load(a, src + half * sbytes, v.stride, h);
+    } else {
+        Spinor<float> b;
+        SpinorIO<PS>::load(b, src + half * sbytes, v.stride, h);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a.s[s][c] = {(double)b.s[s][c].re, (double)b.s[s][c].im};
+    }
+    if constexpr (PD == TMQCD_F64) {
+        SpinorIO<TMQCD_F64>::store(dst + half * dbytes, v.stride, h, a);
+    } else {
+        Spinor<float> b;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) b.s[s][c] = {(float)a.s[s][c].re, (float)a.s[s][c].im};
+        SpinorIO<PD>::store(dst + half * dbytes, v.stride, h, b);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void norm2_kernel(VecK v, const char* src, int64_t bytes, CgState* st, int slot,
+                                                       double* partials) {
+    int half, h;
+    double red = 0;
+    if (site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) {
+        Spinor<typename Prec<P>::T> a;
+        SpinorIO<P>::load(a, src + half * bytes, v.stride, h);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) red += (double)norm2(a.s[s][c]);
+    }
+    double in[1] = {red}, tot[1];
+    if (grid_reduce<1>(in, tot, partials, &st->counter[2], blockIdx.x, v.nblocks) && threadIdx.x == 0)
+        st->result[slot] = tot[0];
+}
+
+__global__ __launch_bounds__(kBlock) void residual_kernel(VecK v, char* r, const char* b, const char* ax,
+                                                          int64_t bytes, CgState* st, int slot, double* partials) {
+    int half, h;
+    double red = 0;
+    if (site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) {
+        Spinor<double> bv, av;
+        SpinorIO<TMQCD_F64>::load(bv, b + half * bytes, v.stride, h);
+        SpinorIO<TMQCD_F64>::load(av, ax + half * bytes, v.stride, h);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                bv.s[s][c] = bv.s[s][c] - av.s[s][c];
+                red += norm2(bv.s[s][c]);
+            }
+        SpinorIO<TMQCD_F64>::store(r + half * bytes, v.stride, h, bv);
+    }
+    double in[1] = {red}, tot[1];
+    if (grid_reduce<1>(in, tot, partials, &st->counter[3], blockIdx.x, v.nblocks) && threadIdx.x == 0)
+        st->result[slot] = tot[0];
+}
+
+template <int PP, int PR>
+__global__ __launch_bounds__(kBlock) void xpay_kernel(VecK v, char* p, int64_t pbytes, const char* r, int64_t rbytes,
+                                                      const CgState* st, int skip_if_done) {
+    if (skip_if_done && st->done) return;
+    int half, h;
+    if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
+    using T = typename Prec<PP>::T;
+    const T beta = (T)st->beta;
+    Spinor<T> pv, rv;
+    SpinorIO<PP>::load(pv, p + half * pbytes, v.stride, h);
+    SpinorIO<PR>::load(rv, r + half * rbytes, v.stride, h);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pv.s[s][c] = rv.s[s][c] + scale(beta, pv.s[s][c]);
+    SpinorIO<PP>::store(p + half * pbytes, v.stride, h, pv);
+}
+
+template <int PS>
+__global__ __launch_bounds__(kBlock) void accumulate_kernel(VecK v, char* x, int64_t xbytes, char* xs,
+                                                            int64_t sbytes) {
+    int half, h;
+    if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
+    Spinor<double> a;
+    Spinor<float> b;
+    SpinorIO<TMQCD_F64>::load(a, x + half * xbytes, v.stride, h);
+    SpinorIO<PS>::load(b, xs + half * sbytes, v.stride, h);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a.s[s][c] = {a.s[s][c].re + (double)b.s[s][c].re, a.s[s][c].im + (double)b.s[s][c].im};
+            b.s[s][c] = {0.f, 0.f};
+        }
+    SpinorIO<TMQCD_F64>::store(x + half * xbytes, v.stride, h, a);
+    SpinorIO<PS>::store(xs + half * sbytes, v.stride, h, b);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void zero_kernel(VecK v, char* dst, int64_t bytes) {
+    int half, h;
+    if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
+    Spinor<typename Prec<P>::T> a;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.s[s][c] = {0, 0};
+    SpinorIO<P>::store(dst + half * bytes, v.stride, h, a);
+}
+
+__global__ void set_state_kernel(CgState* st, StateInit v) {
+    if (threadIdx.x != 0) return;
+    if (v.set_rr) st->rr = v.rr;
+    if (v.set_rr_prev) st->rr_prev = v.rr_prev;
+    if (v.set_stop) st->stop_rr = v.stop_rr;
+    if (v.set_alpha) st->alpha = v.alpha;
+    if (v.set_beta) st->beta = v.beta;
+    if (v.set_iter) st->iter = v.iter;
+    if (v.set_max_iter) st->max_iter = v.max_iter;
+    if (v.set_done) st->done = v.done;
+    if (v.reset_counters)
+        for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
+}
+
+__global__ void rr_from_result_kernel(CgState* st, int slot, double stop_factor) {
+    if (threadIdx.x != 0) return;
+    const double rr = st->result[slot];
+    st->rr = rr;
+    if (stop_factor > 0) st->stop_rr = stop_factor * rr;
+}
+
+template <template <int> class F, typename... A>
+hipError_t by_prec(int p, A... a) {
+    switch (p) {
+        case TMQCD_F64: return F<TMQCD_F64>::run(a...);
+        case TMQCD_F32: return F<TMQCD_F32>::run(a...);
+        case TMQCD_F16: return F<TMQCD_F16>::run(a...);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_convert(const VecSpec& v, void* dst, int pdst, const void* src, int psrc, hipStream_t s) {
+    const VecK k = make_veck(v);
+    char* d = static_cast<char*>(dst);
+    const char* sr = static_cast<const char*>(src);
+    const int64_t db = half_field_bytes(*v.g, pdst), sb = half_field_bytes(*v.g, psrc);
+#define TMQCD_CONV(A, B)                                                                                       \
+    if (pdst == A && psrc == B) {                                                                              \
+        hipLaunchKernelGGL((convert_kernel<A, B>), dim3(k.nblocks), dim3(kBlock), 0, s, k, d, db, sr, sb);    \
+        return hipGetLastError();                                                                              \
+    }
+    TMQCD_CONV(TMQCD_F64, TMQCD_F64)
+    TMQCD_CONV(TMQCD_F32, TMQCD_F64)
+    TMQCD_CONV(TMQCD_F16, TMQCD_F64)
+    TMQCD_CONV(TMQCD_F64, TMQCD_F32)
+    TMQCD_CONV(TMQCD_F64, TMQCD_F16)
+    TMQCD_CONV(TMQCD_F32, TMQCD_F32)
+    TMQCD_CONV(TMQCD_F16, TMQCD_F32)
+    TMQCD_CONV(TMQCD_F32, TMQCD_F16)
+    TMQCD_CONV(TMQCD_F16, TMQCD_F16)
+#undef TMQCD_CONV
+    return hipErrorInvalidValue;
+}
+
+namespace {
+template <int P>
+struct Norm2Run {
+    static hipError_t run(const VecK k, const char* src, int64_t bytes, CgState* st, int slot, double* partials,
+                          hipStream_t s) {
+        hipLaunchKernelGGL((norm2_kernel<P>), dim3(k.nblocks), dim3(kBlock), 0, s, k, src, bytes, st, slot, partials);
+        return hipGetLastError();
+    }
+};
+template <int P>
+struct ZeroRun {
+    static hipError_t run(const VecK k, char* dst, int64_t bytes, hipStream_t s) {
+        hipLaunchKernelGGL((zero_kernel<P>), dim3(k.nblocks), dim3(kBlock), 0, s, k, dst, bytes);
+        return hipGetLastError();
+    }
+};
+}  // namespace
+
+hipError_t launch_norm2(const VecSpec& v, const void* src, int prec, CgState* st, int slot, double* partials,
+                        hipStream_t s) {
+    return by_prec<Norm2Run>(prec, make_veck(v), static_cast<const char*>(src), half_field_bytes(*v.g, prec), st, slot,
+                             partials, s);
+}
+
+hipError_t launch_zero(const VecSpec& v, void* dst, int prec, hipStream_t s) {
+    return by_prec<ZeroRun>(prec, make_veck(v), static_cast<char*>(dst), half_field_bytes(*v.g, prec), s);
+}
+
+hipError_t launch_residual(const VecSpec& v, void* r, const void* b, const void* ax, CgState* st, int slot,
+                           double* partials, hipStream_t s) {
+    const VecK k = make_veck(v);
+    hipLaunchKernelGGL(residual_kernel, dim3(k.nblocks), dim3(kBlock), 0, s, k, static_cast<char*>(r),
+                       static_cast<const char*>(b), static_cast<const char*>(ax), half_field_bytes(*v.g, TMQCD_F64),
+                       st, slot, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st, bool skip_if_done,
+                       hipStream_t s) {
+    const VecK k = make_veck(v);
+    char* pc = static_cast<char*>(p);
+    const char* rc = static_cast<const char*>(r);
+    const int64_t pb = half_field_bytes(*v.g, pp), rb = half_field_bytes(*v.g, pr);
+    const int skip = skip_if_done ? 1 : 0;
+    if (pp == TMQCD_F64 && pr == TMQCD_F64)
+        hipLaunchKernelGGL((xpay_kernel<TMQCD_F64, TMQCD_F64>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb, rc, rb, st, skip);
+    else if (pp == TMQCD_F32 && pr == TMQCD_F32)
+        hipLaunchKernelGGL((xpay_kernel<TMQCD_F32, TMQCD_F32>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb, rc, rb, st, skip);
+    else if (pp == TMQCD_F16 && pr == TMQCD_F32)
+        hipLaunchKernelGGL((xpay_kernel<TMQCD_F16, TMQCD_F32>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb, rc, rb, st, skip);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const VecSpec& v, void* x64, void* xs, int ps, hipStream_t s) {
+    const VecK k = make_veck(v);
+    const int64_t xb = half_field_bytes(*v.g, TMQCD_F64), sb = half_field_bytes(*v.g, ps);
+    if (ps == TMQCD_F32)
+        hipLaunchKernelGGL((accumulate_kernel<TMQCD_F32>), dim3(k.nblocks), dim3(kBlock), 0, s, k,
+                           static_cast<char*>(x64), xb, static_cast<char*>(xs), sb);
+    else if (ps == TMQCD_F16)
+        hipLaunchKernelGGL((accumulate_kernel<TMQCD_F16>), dim3(k.nblocks), dim3(kBlock), 0, s, k,
+                           static_cast<char*>(x64), xb, static_cast<char*>(xs), sb);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(CgState* st, const StateInit& v, hipStream_t s) {
+    hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(64), 0, s, st, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipStream_t s) {
+    hipLaunchKernelGGL(rr_from_result_kernel, dim3(1), dim3(64), 0, s, st, slot, stop_factor);
+    return hipGetLastError();
+}
+
+}  // namespace tmqcd

@@ -1,0 +1,400 @@
+// Device-side types: complex arithmetic, spinor and SU(3) registers, per-precision
+// site loads/stores of the packed layouts, wavefront reductions.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+
+namespace tmqcd {
+
+// ---------------------------------------------------------------- complex ---
+template <typename T>
+struct C {
+    T re, im;
+};
+template <typename T>
+__device__ __forceinline__ C<T> operator+(C<T> a, C<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ C<T> operator-(C<T> a, C<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ C<T> operator*(C<T> a, C<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ C<T> scale(T s, C<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__device__ __forceinline__ C<T> conj(C<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ C<T> cmul_cj(C<T> a, C<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(C<T> a) { return a.re * a.re + a.im * a.im; }
+// multiply by the phase i^code: 0 -> 1, 1 -> i, 2 -> -1, 3 -> -i
+template <int CODE, typename T>
+__device__ __forceinline__ C<T> mul_i(C<T> z) {
+    constexpr int c = CODE & 3;
+    if constexpr (c == 0) return z;
+    else if constexpr (c == 1) return {-z.im, z.re};
+    else if constexpr (c == 2) return {-z.re, -z.im};
+    else return {z.im, -z.re};
+}
+template <typename T>
+__device__ __forceinline__ C<T> cvt(C<double> z) { return {(T)z.re, (T)z.im}; }
+
+template <typename T>
+struct Spinor {
+    C<T> s[4][3];   // [spin][colour]
+};
+template <typename T>
+struct Half {
+    C<T> s[2][3];
+};
+template <typename T>
+struct Su3 {
+    C<T> m[3][3];
+};
+
+// ----------------------------------------------------- precision traits ---
+template <int P>
+struct Prec {
+    using T = float;   // FP32 and FP16 storage compute in FP32
+};
+template <>
+struct Prec<TMQCD_F64> {
+    using T = double;
+};
+
+// ------------------------------------------------------- spinor site I/O ---
+// `base` points at one packed half field; `stride` is its SoA stride.
+template <int P>
+struct SpinorIO;
+
+template <>
+struct SpinorIO<TMQCD_F64> {
+    using T = double;
+    __device__ __forceinline__ static void load(Spinor<T>& v, const char* base, int64_t stride, int64_t h) {
+        const double2* p = reinterpret_cast<const double2*>(base) + h;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            double2 w = p[k * stride];
+            v.s[k / 3][k % 3] = {w.x, w.y};
+        }
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t stride, int64_t h, const Spinor<T>& v) {
+        double2* p = reinterpret_cast<double2*>(base) + h;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[k * stride] = make_double2(v.s[k / 3][k % 3].re, v.s[k / 3][k % 3].im);
+    }
+};
+
+template <>
+struct SpinorIO<TMQCD_F32> {
+    using T = float;
+    __device__ __forceinline__ static void load(Spinor<T>& v, const char* base, int64_t stride, int64_t h) {
+        const float4* p = reinterpret_cast<const float4*>(base) + h;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            float4 w = p[k * stride];
+            v.s[(2 * k) / 3][(2 * k) % 3] = {w.x, w.y};
+            v.s[(2 * k + 1) / 3][(2 * k + 1) % 3] = {w.z, w.w};
+        }
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t stride, int64_t h, const Spinor<T>& v) {
+        float4* p = reinterpret_cast<float4*>(base) + h;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const C<T> a = v.s[(2 * k) / 3][(2 * k) % 3], b = v.s[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            p[k * stride] = make_float4(a.re, a.im, b.re, b.im);
+        }
+    }
+};
+
+// FP16: 24 halves in three 16-byte units, scaled by a per-site FP32 factor equal
+// to the largest |component|; a site whose components are all zero stores zeros.
+template <>
+struct SpinorIO<TMQCD_F16> {
+    using T = float;
+    union U16 {
+        uint4 u;
+        __half h[8];
+    };
+    __device__ __forceinline__ static void load(Spinor<T>& v, const char* base, int64_t stride, int64_t h) {
+        const uint4* p = reinterpret_cast<const uint4*>(base) + h;
+        const float s = reinterpret_cast<const float*>(base + 48 * stride)[h];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            U16 w;
+            w.u = p[k * stride];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 4 * k + j;
+                v.s[c / 3][c % 3] = {s * __half2float(w.h[2 * j]), s * __half2float(w.h[2 * j + 1])};
+            }
+        }
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t stride, int64_t h, const Spinor<T>& v) {
+        float m = 0.f;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v.s[c / 3][c % 3].re), fabsf(v.s[c / 3][c % 3].im)));
+        const float inv = m > 0.f ? 1.f / m : 0.f;
+        uint4* p = reinterpret_cast<uint4*>(base) + h;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            U16 w;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 4 * k + j;
+                w.h[2 * j] = __float2half_rn(v.s[c / 3][c % 3].re * inv);
+                w.h[2 * j + 1] = __float2half_rn(v.s[c / 3][c % 3].im * inv);
+            }
+            p[k * stride] = w.u;
+        }
+        reinterpret_cast<float*>(base + 48 * stride)[h] = m;
+    }
+};
+
+// --------------------------------------------------------- link site I/O ---
+// `base` points at the whole packed gauge field; the link of direction mu whose
+// origin site has parity `par` and half index h.
+template <typename T>
+__device__ __forceinline__ void rebuild_third_row(Su3<T>& u) {
+    // row 2 = conj(row 0 x row 1), exact for unitary U with det U = 1
+    u.m[2][0] = conj(u.m[0][1] * u.m[1][2] - u.m[0][2] * u.m[1][1]);
+    u.m[2][1] = conj(u.m[0][2] * u.m[1][0] - u.m[0][0] * u.m[1][2]);
+    u.m[2][2] = conj(u.m[0][0] * u.m[1][1] - u.m[0][1] * u.m[1][0]);
+}
+
+template <int P, int R>
+struct LinkIO;
+
+template <int R>
+struct LinkIO<TMQCD_F64, R> {
+    using T = double;
+    static constexpr int kUnits = R == TMQCD_RECON18 ? 9 : 6;
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const double2* p = reinterpret_cast<const double2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < kUnits; ++k) {
+            double2 w = p[k * gstride];
+            u.m[k / 3][k % 3] = {w.x, w.y};
+        }
+        if constexpr (R == TMQCD_RECON12) rebuild_third_row(u);
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        double2* p = reinterpret_cast<double2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < kUnits; ++k) p[k * gstride] = make_double2(u.m[k / 3][k % 3].re, u.m[k / 3][k % 3].im);
+    }
+};
+
+template <>
+struct LinkIO<TMQCD_F32, TMQCD_RECON18> {
+    using T = float;
+    static constexpr int kUnits = 9;
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const float2* p = reinterpret_cast<const float2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            float2 w = p[k * gstride];
+            u.m[k / 3][k % 3] = {w.x, w.y};
+        }
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        float2* p = reinterpret_cast<float2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) p[k * gstride] = make_float2((float)u.m[k / 3][k % 3].re, (float)u.m[k / 3][k % 3].im);
+    }
+};
+
+template <>
+struct LinkIO<TMQCD_F32, TMQCD_RECON12> {
+    using T = float;
+    static constexpr int kUnits = 3;
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const float4* p = reinterpret_cast<const float4*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float4 w = p[k * gstride];
+            u.m[(2 * k) / 3][(2 * k) % 3] = {w.x, w.y};
+            u.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {w.z, w.w};
+        }
+        rebuild_third_row(u);
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        float4* p = reinterpret_cast<float4*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const C<double> a = u.m[(2 * k) / 3][(2 * k) % 3], b = u.m[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            p[k * gstride] = make_float4((float)a.re, (float)a.im, (float)b.re, (float)b.im);
+        }
+    }
+};
+
+template <>
+struct LinkIO<TMQCD_F16, TMQCD_RECON18> {
+    using T = float;
+    static constexpr int kUnits = 9;
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const __half2* p = reinterpret_cast<const __half2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            float2 w = __half22float2(p[k * gstride]);
+            u.m[k / 3][k % 3] = {w.x, w.y};
+        }
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        __half2* p = reinterpret_cast<__half2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            p[k * gstride] = __halves2half2(__float2half_rn((float)u.m[k / 3][k % 3].re),
+                                            __float2half_rn((float)u.m[k / 3][k % 3].im));
+    }
+};
+
+template <>
+struct LinkIO<TMQCD_F16, TMQCD_RECON12> {
+    using T = float;
+    static constexpr int kUnits = 3;
+    union U8 {
+        uint2 u;
+        __half h[4];
+    };
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const uint2* p = reinterpret_cast<const uint2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            U8 w;
+            w.u = p[k * gstride];
+            u.m[(2 * k) / 3][(2 * k) % 3] = {__half2float(w.h[0]), __half2float(w.h[1])};
+            u.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {__half2float(w.h[2]), __half2float(w.h[3])};
+        }
+        rebuild_third_row(u);
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        uint2* p = reinterpret_cast<uint2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const C<double> a = u.m[(2 * k) / 3][(2 * k) % 3], b = u.m[(2 * k + 1) / 3][(2 * k + 1) % 3];
+            U8 w;
+            w.h[0] = __float2half_rn((float)a.re);
+            w.h[1] = __float2half_rn((float)a.im);
+            w.h[2] = __float2half_rn((float)b.re);
+            w.h[3] = __float2half_rn((float)b.im);
+            p[k * gstride] = w.u;
+        }
+    }
+};
+
+// ------------------------------------------------------------ scheduling ---
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Remap so that XCD k works on one contiguous range of logical blocks: the
+// neighbour spinors a block reads are then mostly those its XCD read recently.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_swizzle(int bid, int nblocks) {
+    const int q = nblocks / kNumXcd, rem = nblocks % kNumXcd;
+    const int k = bid % kNumXcd, j = bid / kNumXcd;
+    return k * q + (k < rem ? k : rem) + j;
+}
+
+// ------------------------------------------------------------ reductions ---
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Solver scalars, resident in device memory so that a queue of iterations runs
+// without host round trips.
+struct CgState {
+    double rr;        // |r|^2 of the current residual
+    double rr_prev;   // |r|^2 before the last update
+    double pAp;       // p^+ A p
+    double alpha, beta;
+    double stop_rr;   // the update kernel flags done when rr <= stop_rr
+    int iter;         // iterations completed
+    int max_iter;
+    int done;         // 0 running, 1 reached stop_rr, 2 breakdown, 3 iteration cap
+    int pad;
+    double result[4]; // scratch results of standalone reductions
+    unsigned counter[8];
+};
+enum { kDoneRunning = 0, kDoneStop = 1, kDoneBreakdown = 2, kDoneMaxIter = 3 };
+
+__device__ __forceinline__ double coherent_load(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Deterministic grid reduction of N doubles.  Every block writes its partial
+// sums (in a fixed order) to partials[bid * N + i]; the last block to finish
+// sums them in the fixed order of block index and returns true, with the
+// totals in `tot` for every thread of that block.  The counter is reset for
+// the next use by the block that consumed it.
+template <int N>
+__device__ __forceinline__ bool grid_reduce(double (&v)[N], double (&tot)[N], double* partials,
+                                            unsigned* counter, int bid, int nblocks) {
+    __shared__ double sh[N][kWaves];
+    __shared__ int last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double s = wave_sum(v[i]);
+        if (lane == 0) sh[i][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double s = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) s += sh[i][w];
+            __hip_atomic_store(&partials[(int64_t)bid * N + i], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == (unsigned)nblocks - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] += coherent_load(&partials[(int64_t)b * N + i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double s = wave_sum(acc[i]);
+        if (lane == 0) sh[i][wave] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s += sh[i][w];
+        tot[i] = s;
+    }
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+    return true;
+}
+
+}  // namespace tmqcd

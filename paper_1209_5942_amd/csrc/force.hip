@@ -1,0 +1,194 @@
+// Fermion force: the gradient of S_f = phi^+ (M^+ M)^{-1} phi with respect to
+// the eight su(3) directions of every link (paper: the HMC force section; the
+// derivative of D^{-1} needs one inversion, and only the hopping part of the
+// twisted-mass matrix depends on U).
+//
+// With X = (M^+ M)^{-1} phi and Y = M X, dS_f = 2 kappa Re(Y^+ dH X), which per
+// link U_mu(x) -> exp(i w^a T^a) U_mu(x) gives
+//   G^a = -2 kappa Im Tr[T^a (b+ Q1 - conj(b+) Q2)]
+//   Q1 = sum_spin [(1 - gamma_mu) U X(x+mu)] (x) Y(x)^+
+//   Q2 = sum_spin X(x) (x) [U (1 + gamma_mu) Y(x+mu)]^+
+// One thread per site computes its four links; each output is written once,
+// so no atomics are needed.  The spin projectors are applied as in the hop.
+#include "device.h"
+#include "internal.h"
+
+namespace tmqcd {
+namespace {
+
+constexpr int kPerm[4][2] = {{1, 0}, {1, 0}, {0, 1}, {0, 1}};
+constexpr int kB[4][2] = {{3, 3}, {2, 0}, {3, 1}, {2, 2}};
+constexpr int kBd[4][2] = {{1, 1}, {0, 2}, {1, 3}, {2, 2}};
+
+// (1 + eps gamma_mu) U v = [g ; eps B^+ g] with g = U (v_up + eps B v_dn)
+template <int MU, int EPS>
+__device__ __forceinline__ void proj_mul(Spinor<double>& out, const Su3<double>& u, const Spinor<double>& v) {
+    Half<double> h;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int src = 2 + kPerm[MU][r];
+        const int code = (kB[MU][r] + (EPS > 0 ? 0 : 2)) & 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const C<double> z = v.s[src][c];
+            C<double> bz;
+            switch (code) {
+                case 0: bz = z; break;
+                case 1: bz = {-z.im, z.re}; break;
+                case 2: bz = {-z.re, -z.im}; break;
+                default: bz = {z.im, -z.re}; break;
+            }
+            h.s[r][c] = v.s[r][c] + bz;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            out.s[r][a] = u.m[a][0] * h.s[r][0] + u.m[a][1] * h.s[r][1] + u.m[a][2] * h.s[r][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int src = kPerm[MU][r];
+        const int code = (kBd[MU][r] + (EPS > 0 ? 0 : 2)) & 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const C<double> z = out.s[src][c];
+            C<double> bz;
+            switch (code) {
+                case 0: bz = z; break;
+                case 1: bz = {-z.im, z.re}; break;
+                case 2: bz = {-z.re, -z.im}; break;
+                default: bz = {z.im, -z.re}; break;
+            }
+            out.s[2 + r][c] = bz;
+        }
+    }
+}
+
+struct ForceK {
+    const char* gauge;
+    const char* X;
+    const char* Y;
+    double* out;
+    int64_t stride, gstride, hbytes;
+    int L[4];
+    int lxh, vh, nb_half;
+    C<double> bc[4];
+    double kappa;
+};
+
+template <int R, int MU>
+__device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int nh, bool cross,
+                                          const Spinor<double>& xo, const Spinor<double>& yo, double* g) {
+    const char* Xn = a.X + (int64_t)(1 - par) * a.hbytes;
+    const char* Yn = a.Y + (int64_t)(1 - par) * a.hbytes;
+    Su3<double> u;
+    LinkIO<TMQCD_F64, R>::load(u, a.gauge, a.gstride, par, MU, h);
+    Spinor<double> xn, yn, v1, v2;
+    SpinorIO<TMQCD_F64>::load(xn, Xn, a.stride, nh);
+    SpinorIO<TMQCD_F64>::load(yn, Yn, a.stride, nh);
+    proj_mul<MU, -1>(v1, u, xn);   // (1 - gamma_mu) U X(x+mu)
+    proj_mul<MU, +1>(v2, u, yn);   // U (1 + gamma_mu) Y(x+mu)
+    C<double> b = cross ? a.bc[MU] : C<double>{1.0, 0.0};
+    C<double> q[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C<double> q1 = {0, 0}, q2 = {0, 0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                q1 = q1 + cmul_cj(yo.s[s][j], v1.s[s][i]);   // v1_i conj(Y_j)
+                q2 = q2 + cmul_cj(v2.s[s][j], xo.s[s][i]);   // X_i conj(v2_j)
+            }
+            q[i][j] = b * q1 - conj(b) * q2;
+        }
+    // Im Tr(lambda^a Q) for the eight Gell-Mann matrices
+    const double k = -a.kappa;   // -2 kappa * (1/2) from T^a = lambda^a / 2
+    g[0] = k * (q[1][0].im + q[0][1].im);
+    g[1] = k * (q[0][1].re - q[1][0].re);
+    g[2] = k * (q[0][0].im - q[1][1].im);
+    g[3] = k * (q[2][0].im + q[0][2].im);
+    g[4] = k * (q[0][2].re - q[2][0].re);
+    g[5] = k * (q[2][1].im + q[1][2].im);
+    g[6] = k * (q[1][2].re - q[2][1].re);
+    g[7] = k * (q[0][0].im + q[1][1].im - 2.0 * q[2][2].im) * 0.57735026918962576451;   // 1/sqrt(3)
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void force_kernel(const ForceK a) {
+    const int bid = blockIdx.x;
+    const int par = bid >= a.nb_half ? 1 : 0;
+    const int h = (bid - par * a.nb_half) * kBlock + threadIdx.x;
+    if (h >= a.vh) return;
+    const int lxh = a.lxh, lx = a.L[0], ly = a.L[1], lz = a.L[2], lt = a.L[3];
+    const int xh = h % lxh;
+    int rest = h / lxh;
+    const int y = rest % ly;
+    rest /= ly;
+    const int z = rest % lz;
+    const int t = rest / lz;
+    const int bit = (par + y + z + t) & 1;
+    const int x = 2 * xh + bit;
+    const int64_t s = 2 * (int64_t)h + bit;
+
+    Spinor<double> xo, yo;
+    SpinorIO<TMQCD_F64>::load(xo, a.X + (int64_t)par * a.hbytes, a.stride, h);
+    SpinorIO<TMQCD_F64>::load(yo, a.Y + (int64_t)par * a.hbytes, a.stride, h);
+    double g[8];
+    double* o = a.out + s * 32;
+    {
+        const int xf = x + 1 == lx ? 0 : x + 1;
+        force_dir<R, 0>(a, par, h, (h - xh) + (xf >> 1), x == lx - 1, xo, yo, g);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = g[i];
+    }
+    {
+        const int nf = y == ly - 1 ? h - (ly - 1) * lxh : h + lxh;
+        force_dir<R, 1>(a, par, h, nf, y == ly - 1, xo, yo, g);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[8 + i] = g[i];
+    }
+    {
+        const int st = lxh * ly;
+        const int nf = z == lz - 1 ? h - (lz - 1) * st : h + st;
+        force_dir<R, 2>(a, par, h, nf, z == lz - 1, xo, yo, g);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[16 + i] = g[i];
+    }
+    {
+        const int st = lxh * ly * lz;
+        const int nf = t == lt - 1 ? h - (lt - 1) * st : h + st;
+        force_dir<R, 3>(a, par, h, nf, t == lt - 1, xo, yo, g);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[24 + i] = g[i];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* X, const void* Y, double* out,
+                        const Cplx bc[4], double kappa, hipStream_t s) {
+    ForceK k;
+    k.gauge = static_cast<const char*>(gauge);
+    k.X = static_cast<const char*>(X);
+    k.Y = static_cast<const char*>(Y);
+    k.out = out;
+    k.stride = g.stride;
+    k.gstride = g.gstride;
+    k.hbytes = half_field_bytes(g, TMQCD_F64);
+    for (int i = 0; i < 4; ++i) {
+        k.L[i] = g.L[i];
+        k.bc[i] = {bc[i].re, bc[i].im};
+    }
+    k.lxh = g.lxh;
+    k.vh = (int)g.vh;
+    k.nb_half = (int)((g.vh + kBlock - 1) / kBlock);
+    k.kappa = kappa;
+    const dim3 grid(2 * k.nb_half);
+    if (recon == TMQCD_RECON12) hipLaunchKernelGGL((force_kernel<TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k);
+    else hipLaunchKernelGGL((force_kernel<TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k);
+    return hipGetLastError();
+}
+
+}  // namespace tmqcd

@@ -1,0 +1,324 @@
+// The even-odd hop stencil (paper, section 2.1: the hopping part of D_tm, and the
+// storage-format section for the parity-split SoA layout).
+//
+// One thread per output site.  For each of the 8 directions the neighbour
+// spinor is spin-projected to a half spinor with (1 -+ gamma_mu), multiplied by
+// U_mu(x) or U_mu(x - mu)^+, and the lower spin components are rebuilt from the
+// upper ones (the projectors have rank 2), which gives the standard 1320 flops
+// per site.  The epilogue applies the twisted diagonal and, inside CG, the
+// solver update and a deterministic FP64 reduction.
+#include "device.h"
+#include "internal.h"
+
+namespace tmqcd {
+namespace {
+
+// gamma_mu = [[0, B], [B^+, 0]] in the chiral basis.  Row r of B has its one
+// nonzero in column kPerm[mu][r], equal to i^kB[mu][r]; row r of B^+ has it in
+// the same column, equal to i^kBd[mu][r].
+constexpr int kPerm[4][2] = {{1, 0}, {1, 0}, {0, 1}, {0, 1}};
+constexpr int kB[4][2] = {{3, 3}, {2, 0}, {3, 1}, {2, 2}};
+constexpr int kBd[4][2] = {{1, 1}, {0, 2}, {1, 3}, {2, 2}};
+
+// (1 + eps gamma_mu) psi = [h ; eps B^+ h] with h = psi_up + eps B psi_dn
+template <int MU, int EPS, int R, typename T>
+__device__ __forceinline__ void project_row(Half<T>& h, const Spinor<T>& v) {
+    constexpr int code = kB[MU][R] + (EPS > 0 ? 0 : 2);
+    constexpr int src = 2 + kPerm[MU][R];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) h.s[R][c] = v.s[R][c] + mul_i<code>(v.s[src][c]);
+}
+template <int MU, int EPS, int R, typename T>
+__device__ __forceinline__ void accumulate_row(Spinor<T>& acc, const Half<T>& g) {
+    constexpr int code = kBd[MU][R] + (EPS > 0 ? 0 : 2);
+    constexpr int src = kPerm[MU][R];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc.s[R][c] = acc.s[R][c] + g.s[R][c];
+        acc.s[2 + R][c] = acc.s[2 + R][c] + mul_i<code>(g.s[src][c]);
+    }
+}
+
+template <bool ADJ, typename T>
+__device__ __forceinline__ void su3_mul(Half<T>& g, const Su3<T>& u, const Half<T>& h) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if constexpr (ADJ) {
+                g.s[r][a] = cmul_cj(u.m[0][a], h.s[r][0]) + cmul_cj(u.m[1][a], h.s[r][1]) + cmul_cj(u.m[2][a], h.s[r][2]);
+            } else {
+                g.s[r][a] = u.m[a][0] * h.s[r][0] + u.m[a][1] * h.s[r][1] + u.m[a][2] * h.s[r][2];
+            }
+        }
+}
+
+struct HopK {
+    const char* gauge;
+    const char* in;
+    const char* own;
+    char* out;
+    char* x;
+    char* r;
+    const char* p;
+    CgState* st;
+    double* partials;
+    int64_t stride, gstride, hbytes, vhbytes;
+    int L[4];
+    int lxh, vh, nb_half, nblocks, out_parity, nparity;
+    C<double> bc[4];
+    C<double> cu_own, cd_own, cu_hop, cd_hop;
+};
+
+// One of the eight terms: FWD: b+ (1 -+ gamma_mu) U_mu(x) psi(x+mu);
+// backward: b- (1 +- gamma_mu) U_mu(x-mu)^+ psi(x-mu) (signs flip for H^+).
+template <int P, int R, int MU, bool FWD, bool DAG, typename T>
+__device__ __forceinline__ void hop_term(Spinor<T>& acc, const HopK& a, const char* in, int link_par,
+                                         int link_h, int nh, bool cross, C<T> phase) {
+    constexpr int EPS = FWD ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
+    Spinor<T> v;
+    SpinorIO<P>::load(v, in, a.stride, nh);
+    Su3<T> u;
+    LinkIO<P, R>::load(u, a.gauge, a.gstride, link_par, MU, link_h);
+    Half<T> hs, g;
+    project_row<MU, EPS, 0>(hs, v);
+    project_row<MU, EPS, 1>(hs, v);
+    su3_mul<!FWD>(g, u, hs);
+    if (cross) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g.s[r][c] = g.s[r][c] * phase;
+    }
+    accumulate_row<MU, EPS, 0>(acc, g);
+    accumulate_row<MU, EPS, 1>(acc, g);
+}
+
+template <int P, int R, bool DAG, bool OWN, int EPI, int PV>
+__global__ __launch_bounds__(kBlock) void hop_kernel(const HopK a) {
+    using T = typename Prec<P>::T;
+    static_assert(std::is_same<T, typename Prec<PV>::T>::value, "vector and dslash compute types differ");
+    if constexpr (EPI != kEpiStore) {
+        if (a.st->done) return;
+    }
+    const int bid = xcd_swizzle(blockIdx.x, a.nblocks);
+    int par = a.out_parity, lb = bid;
+    if (a.nparity == 2) {
+        par = bid >= a.nb_half ? 1 : 0;
+        lb = bid - par * a.nb_half;
+    }
+    const int h = lb * kBlock + threadIdx.x;
+    const bool two = a.nparity == 2;
+    const char* in = a.in + (two ? (int64_t)(1 - par) * a.hbytes : 0);
+    double red = 0;
+
+    if (h < a.vh) {
+        const int lxh = a.lxh, ly = a.L[1], lz = a.L[2], lt = a.L[3];
+        const int xh = h % lxh;
+        int rest = h / lxh;
+        const int y = rest % ly;
+        rest /= ly;
+        const int z = rest % lz;
+        const int t = rest / lz;
+        const int x = 2 * xh + ((par + y + z + t) & 1);
+        const int row = h - xh;
+        const int opar = 1 - par;
+
+        Spinor<T> acc;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc.s[s][c] = {T(0), T(0)};
+
+        // x direction: the neighbour's half index depends on the row parity
+        {
+            const int lx = a.L[0];
+            const int xf = x + 1 == lx ? 0 : x + 1;
+            const int xb = x == 0 ? lx - 1 : x - 1;
+            const C<T> ph = cvt<T>(a.bc[0]);
+            hop_term<P, R, 0, true, DAG>(acc, a, in, par, h, row + (xf >> 1), x == lx - 1, ph);
+            const int nb = row + (xb >> 1);
+            hop_term<P, R, 0, false, DAG>(acc, a, in, opar, nb, nb, x == 0, conj(ph));
+        }
+        {
+            const int st = lxh;
+            const int nf = y == ly - 1 ? h - (ly - 1) * st : h + st;
+            const int nb = y == 0 ? h + (ly - 1) * st : h - st;
+            const C<T> ph = cvt<T>(a.bc[1]);
+            hop_term<P, R, 1, true, DAG>(acc, a, in, par, h, nf, y == ly - 1, ph);
+            hop_term<P, R, 1, false, DAG>(acc, a, in, opar, nb, nb, y == 0, conj(ph));
+        }
+        {
+            const int st = lxh * ly;
+            const int nf = z == lz - 1 ? h - (lz - 1) * st : h + st;
+            const int nb = z == 0 ? h + (lz - 1) * st : h - st;
+            const C<T> ph = cvt<T>(a.bc[2]);
+            hop_term<P, R, 2, true, DAG>(acc, a, in, par, h, nf, z == lz - 1, ph);
+            hop_term<P, R, 2, false, DAG>(acc, a, in, opar, nb, nb, z == 0, conj(ph));
+        }
+        {
+            const int st = lxh * ly * lz;
+            const int nf = t == lt - 1 ? h - (lt - 1) * st : h + st;
+            const int nb = t == 0 ? h + (lt - 1) * st : h - st;
+            const C<T> ph = cvt<T>(a.bc[3]);
+            hop_term<P, R, 3, true, DAG>(acc, a, in, par, h, nf, t == lt - 1, ph);
+            hop_term<P, R, 3, false, DAG>(acc, a, in, opar, nb, nb, t == 0, conj(ph));
+        }
+
+        // epilogue: out = c_hop * acc (+ c_own * own), c = diag(cu, cu, cd, cd)
+        const C<T> cuh = cvt<T>(a.cu_hop), cdh = cvt<T>(a.cd_hop);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc.s[0][c] = cuh * acc.s[0][c];
+            acc.s[1][c] = cuh * acc.s[1][c];
+            acc.s[2][c] = cdh * acc.s[2][c];
+            acc.s[3][c] = cdh * acc.s[3][c];
+        }
+        const int64_t hoff = two ? (int64_t)par * a.hbytes : 0;
+        if constexpr (OWN) {
+            Spinor<T> o;
+            SpinorIO<P>::load(o, a.own + hoff, a.stride, h);
+            const C<T> cuo = cvt<T>(a.cu_own), cdo = cvt<T>(a.cd_own);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc.s[0][c] = acc.s[0][c] + cuo * o.s[0][c];
+                acc.s[1][c] = acc.s[1][c] + cuo * o.s[1][c];
+                acc.s[2][c] = acc.s[2][c] + cdo * o.s[2][c];
+                acc.s[3][c] = acc.s[3][c] + cdo * o.s[3][c];
+            }
+        }
+        if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
+            SpinorIO<P>::store(a.out + hoff, a.stride, h, acc);
+            if constexpr (EPI == kEpiStoreNorm) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) red += (double)norm2(acc.s[s][c]);
+            }
+        } else {
+            // x += alpha p, r -= alpha (A p)
+            const T alpha = (T)a.st->alpha;
+            const int64_t voff = two ? (int64_t)par * a.vhbytes : 0;
+            Spinor<T> pv, xv, rv;
+            SpinorIO<P>::load(pv, a.p + hoff, a.stride, h);
+            SpinorIO<PV>::load(xv, a.x + voff, a.stride, h);
+            SpinorIO<PV>::load(rv, a.r + voff, a.stride, h);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
+                    rv.s[s][c] = rv.s[s][c] - scale(alpha, acc.s[s][c]);
+                }
+            SpinorIO<PV>::store(a.x + voff, a.stride, h, xv);
+            SpinorIO<PV>::store(a.r + voff, a.stride, h, rv);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) red += (double)norm2(rv.s[s][c]);
+        }
+    }
+
+    if constexpr (EPI != kEpiStore) {
+        double v[1] = {red}, tot[1];
+        const int slot = EPI == kEpiStoreNorm ? 0 : 1;
+        if (grid_reduce<1>(v, tot, a.partials, &a.st->counter[slot], bid, a.nblocks) && threadIdx.x == 0) {
+            CgState* st = a.st;
+            if constexpr (EPI == kEpiStoreNorm) {
+                const double pap = tot[0];
+                st->pAp = pap;
+                if (!(pap > 0.0) || !isfinite(pap)) st->done = kDoneBreakdown;
+                else st->alpha = st->rr / pap;
+            } else {
+                const double rr = tot[0];
+                const double rr_old = st->rr;
+                st->rr_prev = rr_old;
+                st->rr = rr;
+                st->beta = rr / rr_old;
+                const int it = st->iter + 1;
+                st->iter = it;
+                if (!isfinite(rr)) st->done = kDoneBreakdown;
+                else if (rr <= st->stop_rr) st->done = kDoneStop;
+                else if (it >= st->max_iter) st->done = kDoneMaxIter;
+            }
+        }
+    }
+}
+
+template <int P, int R, bool DAG, bool OWN, int EPI>
+hipError_t launch_inst(const HopK& k, hipStream_t s) {
+    constexpr int PV = P == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
+    hipLaunchKernelGGL((hop_kernel<P, R, DAG, OWN, EPI, PV>), dim3(k.nblocks), dim3(kBlock), 0, s, k);
+    return hipGetLastError();
+}
+
+template <int P, int R>
+hipError_t dispatch_variant(const HopParams& a, const HopK& k, hipStream_t s) {
+    const bool own = a.own != nullptr;
+    switch (a.epi) {
+        case kEpiStore:
+            if (!a.dag && !own) return launch_inst<P, R, false, false, kEpiStore>(k, s);
+            if (a.dag && !own) return launch_inst<P, R, true, false, kEpiStore>(k, s);
+            if (!a.dag && own) return launch_inst<P, R, false, true, kEpiStore>(k, s);
+            return launch_inst<P, R, true, true, kEpiStore>(k, s);
+        case kEpiStoreNorm:
+            if (!a.dag && own) return launch_inst<P, R, false, true, kEpiStoreNorm>(k, s);
+            break;
+        case kEpiCgUpdate:
+            if (a.dag && own) return launch_inst<P, R, true, true, kEpiCgUpdate>(k, s);
+            break;
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int hop_blocks(const Geom& g, int nparity) { return nparity * (int)((g.vh + kBlock - 1) / kBlock); }
+
+hipError_t launch_hop(const HopParams& a, hipStream_t s) {
+    HopK k;
+    k.gauge = static_cast<const char*>(a.gauge);
+    k.in = static_cast<const char*>(a.in);
+    k.own = static_cast<const char*>(a.own);
+    k.out = static_cast<char*>(a.out);
+    k.x = static_cast<char*>(a.x);
+    k.r = static_cast<char*>(a.r);
+    k.p = static_cast<const char*>(a.p);
+    k.st = a.st;
+    k.partials = a.partials;
+    k.stride = a.g.stride;
+    k.gstride = a.g.gstride;
+    k.hbytes = half_field_bytes(a.g, a.prec);
+    k.vhbytes = half_field_bytes(a.g, a.vprec);
+    for (int i = 0; i < 4; ++i) {
+        k.L[i] = a.g.L[i];
+        k.bc[i] = {a.bc[i].re, a.bc[i].im};
+    }
+    k.lxh = a.g.lxh;
+    k.vh = (int)a.g.vh;
+    k.nb_half = (int)((a.g.vh + kBlock - 1) / kBlock);
+    k.nblocks = hop_blocks(a.g, a.nparity);
+    k.out_parity = a.out_parity;
+    k.nparity = a.nparity;
+    k.cu_own = {a.cu_own.re, a.cu_own.im};
+    k.cd_own = {a.cd_own.re, a.cd_own.im};
+    k.cu_hop = {a.cu_hop.re, a.cu_hop.im};
+    k.cd_hop = {a.cd_hop.re, a.cd_hop.im};
+    const int want_vprec = a.prec == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
+    if (a.epi == kEpiCgUpdate && a.vprec != want_vprec) return hipErrorInvalidValue;
+    const bool r12 = a.recon == TMQCD_RECON12;
+    switch (a.prec) {
+        case TMQCD_F64:
+            return r12 ? dispatch_variant<TMQCD_F64, TMQCD_RECON12>(a, k, s)
+                       : dispatch_variant<TMQCD_F64, TMQCD_RECON18>(a, k, s);
+        case TMQCD_F32:
+            return r12 ? dispatch_variant<TMQCD_F32, TMQCD_RECON12>(a, k, s)
+                       : dispatch_variant<TMQCD_F32, TMQCD_RECON18>(a, k, s);
+        case TMQCD_F16:
+            return r12 ? dispatch_variant<TMQCD_F16, TMQCD_RECON12>(a, k, s)
+                       : dispatch_variant<TMQCD_F16, TMQCD_RECON18>(a, k, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tmqcd

@@ -1,0 +1,93 @@
+// Host-side interfaces between the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.h"
+
+namespace tmqcd {
+
+struct CgState;   // device.h
+
+struct Cplx {
+    double re, im;
+};
+
+// Epilogue kinds of the hop kernel.
+enum HopEpilogue {
+    kEpiStore = 0,      // out = own-term + hop-term
+    kEpiStoreNorm = 1,  // ... and |out|^2 -> pAp; alpha = rr / pAp
+    kEpiCgUpdate = 2,   // out not stored: x += alpha p; r -= alpha out; |r|^2 -> rr, beta
+};
+
+// out_p = [c_own * own_p] + c_hop * (H in)_p, where c = diag(cu, cu, cd, cd) in
+// spin (upper / lower chiral halves), H is the hop (or H^dagger when dag), and
+// p runs over one output parity (nparity = 1; in is the half field of the
+// other parity) or both (nparity = 2; in, own and out are full fields).
+struct HopParams {
+    Geom g;
+    int prec, recon;
+    const void* gauge;
+    const void* in;
+    const void* own;
+    void* out;
+    int out_parity;
+    int nparity;
+    bool dag;
+    Cplx bc[4];
+    Cplx cu_own, cd_own, cu_hop, cd_hop;
+    int epi;
+    // reductions and CG update (epi != kEpiStore)
+    CgState* st;
+    double* partials;
+    void* x;          // vector precision
+    void* r;          // vector precision
+    const void* p;    // dslash precision
+    int vprec;        // precision of x and r
+};
+
+hipError_t launch_hop(const HopParams& a, hipStream_t s);
+int hop_blocks(const Geom& g, int nparity);   // grid size (and partial count) of a hop launch
+
+// ---- BLAS-1 over packed fields of nhalf half fields -------------------------
+struct VecSpec {
+    const Geom* g;
+    int nhalf;       // 1 = half field, 2 = full field
+};
+// dst = src (precision conversion, rounding to nearest)
+hipError_t launch_convert(const VecSpec& v, void* dst, int pdst, const void* src, int psrc, hipStream_t s);
+// st->result[slot] = |src|^2 (deterministic FP64 reduction)
+hipError_t launch_norm2(const VecSpec& v, const void* src, int prec, CgState* st, int slot, double* partials,
+                        hipStream_t s);
+// r = b - ax (all FP64), st->result[slot] = |r|^2
+hipError_t launch_residual(const VecSpec& v, void* r, const void* b, const void* ax, CgState* st, int slot,
+                           double* partials, hipStream_t s);
+// p = r + beta p with beta = st->beta; nothing when st->done and skip_if_done
+hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st, bool skip_if_done,
+                       hipStream_t s);
+// x64 += xs (low precision), then xs = 0
+hipError_t launch_accumulate(const VecSpec& v, void* x64, void* xs, int ps, hipStream_t s);
+hipError_t launch_zero(const VecSpec& v, void* dst, int prec, hipStream_t s);
+
+// ---- solver state --------------------------------------------------------------
+struct StateInit {
+    double rr, rr_prev, stop_rr, alpha, beta;
+    int iter, max_iter, done;
+    bool set_rr, set_rr_prev, set_stop, set_alpha, set_beta, set_iter, set_max_iter, set_done, reset_counters;
+};
+hipError_t launch_set_state(CgState* st, const StateInit& v, hipStream_t s);
+// st->rr = st->result[slot]; optionally stop_rr = factor * rr
+hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipStream_t s);
+
+// ---- packing ----------------------------------------------------------------------
+hipError_t launch_pack_gauge(const Geom& g, const void* canon, void* packed, int prec, int recon, hipStream_t s);
+hipError_t launch_pack_spinor(const Geom& g, const void* canon, void* packed, int prec, int subset, int nrhs,
+                              bool unpack, hipStream_t s);
+
+// ---- fermion force ---------------------------------------------------------------
+hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* X, const void* Y, double* out,
+                        const Cplx bc[4], double kappa, hipStream_t s);
+
+}  // namespace tmqcd

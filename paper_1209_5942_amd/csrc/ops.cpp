@@ -1,0 +1,439 @@
+// Operator composition (M, M^+, Mhat, Mhat^+, their normal operators) and the
+// CG solvers built on the hop kernel.
+//
+// Even-odd preconditioning (paper, section 2.1): the Schur complement on even
+// sites Mhat = A_ee - kappa^2 H_eo A_oo^{-1} H_oe, with A = 1 + i w gamma5,
+// w = 2 kappa mu.  In the chiral basis gamma5 = diag(-1,-1,+1,+1), so A acts on
+// the upper two spins as (1 - i w) and on the lower two as (1 + i w).  The
+// adjoints use H^+ (gamma_mu -> -gamma_mu) and A^+ = A(-mu).
+//
+// One CG iteration on Mhat^+ Mhat is four hop launches and one BLAS launch:
+//   t1 = A^{-1} H_oe p
+//   t2 = A p - kappa^2 H_eo t1                 and  p^+ A p = |t2|^2, alpha
+//   t3 = A(-mu)^{-1} H^+_oe t2
+//   (A p) = A(-mu) t2 - kappa^2 H^+_eo t3      fused with x += alpha p,
+//                                               r -= alpha A p, |r|^2, beta
+//   p = r + beta p
+// All scalars stay on the device; the host queues several iterations, then
+// reads the state once.  Kernels queued after convergence return at once.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "device.h"
+#include "internal.h"
+#include "ops.h"
+
+namespace tmqcd {
+
+thread_local int g_last_hip_error = 0;
+
+namespace {
+
+Cplx cx(double re, double im) { return {re, im}; }
+Cplx cdiv1(Cplx z) {   // 1 / z
+    const double d = z.re * z.re + z.im * z.im;
+    return {z.re / d, -z.im / d};
+}
+
+}  // namespace
+
+OpCtx make_ctx(const tmqcd_problem& prob, int prec, int recon, const void* gauge, hipStream_t s) {
+    OpCtx c;
+    c.g = make_geom(prob);
+    c.prec = prec;
+    c.recon = recon;
+    c.gauge = gauge;
+    c.s = s;
+    c.kappa = prob.kappa;
+    c.w = 2.0 * prob.kappa * prob.mu;
+    for (int i = 0; i < 4; ++i) c.bc[i] = {prob.bc[i][0], prob.bc[i][1]};
+    return c;
+}
+
+// A(+mu) or A(-mu) = A^+, upper/lower chiral halves
+static void twist(const OpCtx& c, bool dag, Cplx& up, Cplx& dn) {
+    const double w = dag ? -c.w : c.w;
+    up = cx(1.0, -w);
+    dn = cx(1.0, w);
+}
+
+static HopParams base_params(const OpCtx& c) {
+    HopParams a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = c.g;
+    a.prec = c.prec;
+    a.recon = c.recon;
+    a.gauge = c.gauge;
+    for (int i = 0; i < 4; ++i) a.bc[i] = c.bc[i];
+    a.epi = kEpiStore;
+    a.vprec = c.prec == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
+    return a;
+}
+
+hipError_t op_dslash_pq(const OpCtx& c, const void* in, void* out, int out_parity, double coef) {
+    HopParams a = base_params(c);
+    a.in = in;
+    a.out = out;
+    a.out_parity = out_parity;
+    a.nparity = 1;
+    a.cu_hop = a.cd_hop = cx(coef, 0);
+    return launch_hop(a, c.s);
+}
+
+// full field: out = A(+-mu) in - kappa H(^+) in
+hipError_t op_full(const OpCtx& c, const void* in, void* out, bool dag, int epi, CgState* st, double* partials,
+                   void* x, void* r, const void* p) {
+    HopParams a = base_params(c);
+    a.in = in;
+    a.own = in;
+    a.out = out;
+    a.nparity = 2;
+    a.dag = dag;
+    twist(c, dag, a.cu_own, a.cd_own);
+    a.cu_hop = a.cd_hop = cx(-c.kappa, 0);
+    a.epi = epi;
+    a.st = st;
+    a.partials = partials;
+    a.x = x;
+    a.r = r;
+    a.p = p;
+    return launch_hop(a, c.s);
+}
+
+// even sites: t_o = A(+-mu)^{-1} H(^+)_oe in_e
+hipError_t op_schur_first(const OpCtx& c, const void* in_e, void* t_o, bool dag) {
+    HopParams a = base_params(c);
+    a.in = in_e;
+    a.out = t_o;
+    a.out_parity = 1;
+    a.nparity = 1;
+    a.dag = dag;
+    Cplx up, dn;
+    twist(c, dag, up, dn);
+    a.cu_hop = cdiv1(up);
+    a.cd_hop = cdiv1(dn);
+    return launch_hop(a, c.s);
+}
+
+// even sites: out_e = A(+-mu) own_e - kappa^2 H(^+)_eo t_o
+hipError_t op_schur_second(const OpCtx& c, const void* t_o, const void* own_e, void* out_e, bool dag, int epi,
+                           CgState* st, double* partials, void* x, void* r, const void* p) {
+    HopParams a = base_params(c);
+    a.in = t_o;
+    a.own = own_e;
+    a.out = out_e;
+    a.out_parity = 0;
+    a.nparity = 1;
+    a.dag = dag;
+    twist(c, dag, a.cu_own, a.cd_own);
+    a.cu_hop = a.cd_hop = cx(-c.kappa * c.kappa, 0);
+    a.epi = epi;
+    a.st = st;
+    a.partials = partials;
+    a.x = x;
+    a.r = r;
+    a.p = p;
+    return launch_hop(a, c.s);
+}
+
+// out = op(in) with temporaries from tmp (op-dependent size, see dslash_tmp_bytes)
+hipError_t apply_operator(const OpCtx& c, int op, const void* in, void* out, char* tmp) {
+    const int64_t hb = half_field_bytes(c.g, c.prec);
+    hipError_t e = hipSuccess;
+    switch (op) {
+        case TMQCD_DSLASH_EO: return op_dslash_pq(c, in, out, 0, -c.kappa);
+        case TMQCD_DSLASH_OE: return op_dslash_pq(c, in, out, 1, -c.kappa);
+        case TMQCD_M: return op_full(c, in, out, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+        case TMQCD_MDAG: return op_full(c, in, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+        case TMQCD_MDAGM:
+            e = op_full(c, in, tmp, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+            if (e != hipSuccess) return e;
+            return op_full(c, tmp, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+        case TMQCD_MHAT:
+        case TMQCD_MHATDAG: {
+            const bool dag = op == TMQCD_MHATDAG;
+            e = op_schur_first(c, in, tmp, dag);
+            if (e != hipSuccess) return e;
+            return op_schur_second(c, tmp, in, out, dag, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+        }
+        case TMQCD_MHATDAGMHAT: {
+            char* t_o = tmp;
+            char* t_e = tmp + hb;
+            e = op_schur_first(c, in, t_o, false);
+            if (e != hipSuccess) return e;
+            e = op_schur_second(c, t_o, in, t_e, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+            if (e != hipSuccess) return e;
+            e = op_schur_first(c, t_e, t_o, true);
+            if (e != hipSuccess) return e;
+            return op_schur_second(c, t_o, t_e, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+int64_t dslash_tmp_bytes(const Geom& g, int op, int prec) {
+    const int64_t hb = half_field_bytes(g, prec);
+    switch (op) {
+        case TMQCD_MDAGM: return 2 * hb;
+        case TMQCD_MHAT:
+        case TMQCD_MHATDAG: return hb;
+        case TMQCD_MHATDAGMHAT: return 2 * hb;
+    }
+    return 0;
+}
+
+// ------------------------------------------------------------- workspace ---
+static int64_t align(int64_t v) { return round_up(v, kAlignBytes); }
+
+int64_t state_bytes() { return align(sizeof(CgState)); }
+int64_t partial_bytes(const Geom& g) { return align(8 * (int64_t)hop_blocks(g, 2) + 8 * kBlock); }
+
+CgWorkspace carve_cg(const Geom& g, int op, int inner_prec, char* base) {
+    CgWorkspace w;
+    std::memset(&w, 0, sizeof(w));
+    const bool full = op == TMQCD_MDAGM;
+    const int nh = full ? 2 : 1;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align(bytes);
+        return p;
+    };
+    w.st = reinterpret_cast<CgState*>(take(sizeof(CgState)));
+    w.partials = reinterpret_cast<double*>(take(partial_bytes(g)));
+    const int64_t h64 = half_field_bytes(g, TMQCD_F64);
+    w.r = take(nh * h64);
+    w.p = take(nh * h64);
+    w.ax = take(nh * h64);
+    if (full) {
+        w.t1 = take(2 * h64);
+    } else {
+        w.t1 = take(h64);
+        w.t2 = take(h64);
+        w.t3 = take(h64);
+    }
+    if (inner_prec != TMQCD_F64) {
+        const int pv = TMQCD_F32;
+        const int64_t hv = half_field_bytes(g, pv), hd = half_field_bytes(g, inner_prec);
+        w.rs = take(nh * hv);
+        w.xs = take(nh * hv);
+        w.ps = take(nh * hd);
+        if (full) {
+            w.t1s = take(2 * hd);
+        } else {
+            w.t1s = take(hd);
+            w.t2s = take(hd);
+            w.t3s = take(hd);
+        }
+    }
+    w.total = off;
+    return w;
+}
+
+// ------------------------------------------------------------------ CG ---
+namespace {
+
+struct Fields {
+    void* x;
+    void* r;
+    void* p;
+    void* t1;
+    void* t2;
+    void* t3;
+};
+
+// Queue one CG iteration (all precisions): see the file header.
+hipError_t queue_iteration(const OpCtx& c, bool full, const Fields& f, CgState* st, double* partials, int pv) {
+    hipError_t e;
+    VecSpec vs{&c.g, full ? 2 : 1};
+    if (full) {
+        e = op_full(c, f.p, f.t1, false, kEpiStoreNorm, st, partials, nullptr, nullptr, nullptr);
+        if (e != hipSuccess) return e;
+        e = op_full(c, f.t1, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p);
+        if (e != hipSuccess) return e;
+    } else {
+        e = op_schur_first(c, f.p, f.t1, false);
+        if (e != hipSuccess) return e;
+        e = op_schur_second(c, f.t1, f.p, f.t2, false, kEpiStoreNorm, st, partials, nullptr, nullptr, nullptr);
+        if (e != hipSuccess) return e;
+        e = op_schur_first(c, f.t2, f.t3, true);
+        if (e != hipSuccess) return e;
+        e = op_schur_second(c, f.t3, f.t2, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p);
+        if (e != hipSuccess) return e;
+    }
+    return launch_xpay(vs, f.p, c.prec, f.r, pv, st, true, c.s);
+}
+
+struct HostState {
+    CgState s;
+};
+
+hipError_t read_state(CgState* st, HostState& h, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(&h.s, st, sizeof(CgState), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+StateInit no_change() {
+    StateInit v;
+    std::memset(&v, 0, sizeof(v));
+    return v;
+}
+
+}  // namespace
+
+#define TRY(expr)                                     \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) {                       \
+            g_last_hip_error = (int)e_;               \
+            return TMQCD_EHIP;                        \
+        }                                             \
+    } while (0)
+
+int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b, void* x, const tmqcd_cg_opts& o,
+           tmqcd_cg_stats& stats, void* ws, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::memset(&stats, 0, sizeof(stats));
+    const bool full = o.op == TMQCD_MDAGM;
+    const int nh = full ? 2 : 1;
+    const int q = o.inner_prec;
+    const bool mixed = q != TMQCD_F64;
+    const Geom g = make_geom(prob);
+    CgWorkspace w = carve_cg(g, o.op, q, static_cast<char*>(ws));
+    const OpCtx c64 = make_ctx(prob, TMQCD_F64, o.recon, gauge[TMQCD_F64], s);
+    const OpCtx cq = mixed ? make_ctx(prob, q, o.recon, gauge[q], s) : c64;
+    const VecSpec vs{&g, nh};
+    const int op = full ? TMQCD_MDAGM : TMQCD_MHATDAGMHAT;
+    const int hops_per_apply = full ? 2 : 4;
+    const int check = o.check_every > 0 ? o.check_every : 8;
+    const double delta = o.reliable_delta > 0 ? o.reliable_delta : 0.1;
+    char* tmp64 = static_cast<char*>(w.t1);   // t1 (and t2 for even-odd) are contiguous
+
+    // state: counters zero, iteration count, cap
+    StateInit si = no_change();
+    si.set_iter = si.set_max_iter = si.set_done = si.reset_counters = true;
+    si.iter = 0;
+    si.max_iter = o.max_iter;
+    si.done = kDoneRunning;
+    TRY(launch_set_state(w.st, si, s));
+
+    // r = b - A x (FP64); |b|^2 -> result[1], |r|^2 -> result[0]
+    int applies = 0;
+    auto true_residual = [&]() -> hipError_t {
+        hipError_t e = apply_operator(c64, op, x, w.ax, tmp64);
+        if (e != hipSuccess) return e;
+        ++applies;
+        return launch_residual(vs, w.r, b, w.ax, w.st, 0, w.partials, s);
+    };
+    if (o.x_is_zero) {
+        TRY(launch_zero(vs, x, TMQCD_F64, s));
+        TRY(launch_convert(vs, w.r, TMQCD_F64, b, TMQCD_F64, s));
+        TRY(launch_norm2(vs, w.r, TMQCD_F64, w.st, 0, w.partials, s));
+    } else {
+        TRY(true_residual());
+    }
+    TRY(launch_norm2(vs, b, TMQCD_F64, w.st, 1, w.partials, s));
+    HostState hs;
+    TRY(read_state(w.st, hs, s));
+    const double bb = hs.s.result[1];
+    double rr = hs.s.result[0];
+    if (!(bb > 0.0)) {   // b = 0: x = 0 is exact
+        TRY(launch_zero(vs, x, TMQCD_F64, s));
+        stats.converged = 1;
+        stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        TRY(hipStreamSynchronize(s));
+        return TMQCD_OK;
+    }
+    if (!std::isfinite(rr) || !std::isfinite(bb)) return TMQCD_EBREAKDOWN;
+    const double target = o.tol * o.tol * bb;
+
+    // fields of the iteration
+    Fields f;
+    int pv;
+    if (mixed) {
+        pv = TMQCD_F32;
+        f = Fields{w.xs, w.rs, w.ps, w.t1s, w.t2s, w.t3s};
+        TRY(launch_convert(vs, w.rs, pv, w.r, TMQCD_F64, s));
+        TRY(launch_zero(vs, w.xs, pv, s));
+        TRY(launch_convert(vs, w.ps, q, w.r, TMQCD_F64, s));
+    } else {
+        pv = TMQCD_F64;
+        f = Fields{x, w.r, w.p, w.t1, w.t2, w.t3};
+        TRY(launch_convert(vs, w.p, TMQCD_F64, w.r, TMQCD_F64, s));
+    }
+    auto start_cycle = [&](double rr_now) -> hipError_t {
+        StateInit v = no_change();
+        v.set_rr = v.set_stop = v.set_done = true;
+        v.rr = rr_now;
+        v.stop_rr = mixed ? std::max(delta * delta * rr_now, target) : target;
+        v.done = kDoneRunning;
+        return launch_set_state(w.st, v, s);
+    };
+    TRY(start_cycle(rr));
+
+    int status = TMQCD_OK;
+    int iters_done = 0;
+    for (;;) {
+        if (rr > target) {
+            // queue iterations in batches until the device flags a stop
+            for (;;) {
+                for (int k = 0; k < check; ++k) TRY(queue_iteration(cq, full, f, w.st, w.partials, pv));
+                TRY(read_state(w.st, hs, s));
+                if (hs.s.done != kDoneRunning) break;
+            }
+            iters_done = hs.s.iter;
+        }
+        // fold the low-precision solution into x and recompute the FP64 residual
+        if (mixed) TRY(launch_accumulate(vs, x, w.xs, pv, s));
+        TRY(true_residual());
+        TRY(read_state(w.st, hs, s));
+        const double rr_true = hs.s.result[0];
+        stats.reliable_updates += 1;
+        stats.iter_rel_residual = std::sqrt(hs.s.rr / bb);
+        if (!std::isfinite(rr_true)) {
+            status = TMQCD_EBREAKDOWN;
+            break;
+        }
+        if (rr_true <= target) {
+            stats.converged = 1;
+            rr = rr_true;
+            break;
+        }
+        if (hs.s.done == kDoneBreakdown) {
+            status = TMQCD_EBREAKDOWN;
+            rr = rr_true;
+            break;
+        }
+        if (hs.s.iter >= o.max_iter) {
+            status = TMQCD_ENOCONV;
+            rr = rr_true;
+            break;
+        }
+        // reliable update: restart the recursion from the true residual, keeping
+        // the search direction: p = r + (rr_true / rr_prev) p
+        const double rr_prev = hs.s.rr_prev > 0 ? hs.s.rr_prev : rr_true;
+        if (mixed) TRY(launch_convert(vs, w.rs, pv, w.r, TMQCD_F64, s));
+        StateInit v = no_change();
+        v.set_beta = true;
+        v.beta = rr_true / rr_prev;
+        v.set_done = true;
+        v.done = kDoneRunning;
+        TRY(launch_set_state(w.st, v, s));
+        TRY(launch_xpay(vs, f.p, cq.prec, f.r, pv, w.st, false, s));
+        rr = rr_true;
+        TRY(start_cycle(rr));
+    }
+    stats.iters = iters_done;
+    stats.hop_launches = hops_per_apply * (iters_done + applies);
+    stats.true_rel_residual = std::sqrt(rr / bb);
+    TRY(hipStreamSynchronize(s));
+    stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
+#undef TRY
+
+}  // namespace tmqcd

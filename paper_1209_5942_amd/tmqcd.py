@@ -1,0 +1,233 @@
+"""Thin ctypes binding of libtmqcd.so (the C interface in include/tmqcd.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device memory comes from torch (``torch.empty(..., device="cuda")``)
+and calls are ordered on ``torch.cuda.current_stream()`` unless a stream is
+given.  The library must be built (``python -m paper_1209_5942_amd.build``);
+loading raises ``TmqcdLibraryMissing`` otherwise - there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libtmqcd.so")
+
+# constants of include/tmqcd.h
+OK, EINVAL, EALIAS, EALIGN, ENOCONV, EBREAKDOWN, EHIP, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6, -7
+F64, F32, F16 = 0, 1, 2
+RECON18, RECON12 = 0, 1
+FULL, EVEN, ODD = 0, 1, 2
+DSLASH_EO, DSLASH_OE, M, MDAG, MDAGM, MHAT, MHATDAG, MHATDAGMHAT = range(8)
+OPS = {"DSLASH_EO": DSLASH_EO, "DSLASH_OE": DSLASH_OE, "M": M, "MDAG": MDAG, "MDAGM": MDAGM,
+       "MHAT": MHAT, "MHATDAG": MHATDAG, "MHATDAGMHAT": MHATDAGMHAT}
+OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), MDAG: (FULL, FULL),
+              MDAGM: (FULL, FULL), MHAT: (EVEN, EVEN), MHATDAG: (EVEN, EVEN), MHATDAGMHAT: (EVEN, EVEN)}
+
+ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
+                "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg", "tmqcd_force",
+                "tmqcd_error_string", "tmqcd_last_hip_error")
+
+
+class TmqcdLibraryMissing(RuntimeError):
+    pass
+
+
+class TmqcdError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {error_string(code)} (code {code}, hip error {last_hip_error()})")
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("kappa", ctypes.c_double), ("mu", ctypes.c_double),
+                ("bc", (ctypes.c_double * 2) * 4)]
+
+
+class CCgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int32), ("recon", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("x_is_zero", ctypes.c_int32)]
+
+
+class CCgStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("hop_launches", ctypes.c_int32), ("true_rel_residual", ctypes.c_double),
+                ("iter_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libtmqcd.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TmqcdLibraryMissing(f"{LIB_PATH} is missing: run `python -m paper_1209_5942_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, V, I, S = ctypes.POINTER(CProblem), ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        sig = {
+            "tmqcd_gauge_bytes": (S, [P, I, I]),
+            "tmqcd_spinor_bytes": (S, [P, I, I, I]),
+            "tmqcd_workspace_bytes": (S, [P, I, I, I]),
+            "tmqcd_pack_gauge": (I, [P, V, V, I, I, V]),
+            "tmqcd_pack_spinor": (I, [P, V, V, I, I, I, V]),
+            "tmqcd_unpack_spinor": (I, [P, V, V, I, I, I, V]),
+            "tmqcd_dslash": (I, [P, V, V, V, I, I, I, I, V, S, V]),
+            "tmqcd_cg": (I, [P, ctypes.POINTER(V * 3), V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats),
+                             V, S, V]),
+            "tmqcd_force": (I, [P, V, I, V, V, V, V]),
+            "tmqcd_error_string": (ctypes.c_char_p, [I]),
+            "tmqcd_last_hip_error": (I, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype, fn.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return lib().tmqcd_error_string(code).decode()
+
+
+def last_hip_error() -> int:
+    return lib().tmqcd_last_hip_error()
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise TmqcdError(code, where)
+
+
+@dataclass
+class Problem:
+    """Lattice extents (Lx, Ly, Lz, Lt), kappa, mu and per-direction boundary phases."""
+    dims: tuple
+    kappa: float
+    mu: float
+    bc: tuple = (1, 1, 1, -1)
+
+    def c(self) -> CProblem:
+        p = CProblem()
+        for i in range(4):
+            p.dims[i] = int(self.dims[i])
+            z = complex(self.bc[i])
+            p.bc[i][0], p.bc[i][1] = z.real, z.imag
+        p.kappa, p.mu = float(self.kappa), float(self.mu)
+        return p
+
+    @property
+    def volume(self) -> int:
+        v = 1
+        for d in self.dims:
+            v *= int(d)
+        return v
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _bytes(n: int, device="cuda"):
+    import torch
+    return torch.empty(int(n), dtype=torch.uint8, device=device)
+
+
+def gauge_bytes(prob: Problem, prec=F64, recon=RECON18) -> int:
+    return lib().tmqcd_gauge_bytes(ctypes.byref(prob.c()), prec, recon)
+
+
+def spinor_bytes(prob: Problem, prec=F64, subset=FULL, nrhs=1) -> int:
+    return lib().tmqcd_spinor_bytes(ctypes.byref(prob.c()), prec, subset, nrhs)
+
+
+def workspace_bytes(prob: Problem, op: int, prec_mask: int = 1, nrhs: int = 1) -> int:
+    return lib().tmqcd_workspace_bytes(ctypes.byref(prob.c()), op, prec_mask, nrhs)
+
+
+def workspace(prob: Problem, op: int, prec_mask: int = 1 | 2 | 4, nrhs: int = 1):
+    return _bytes(workspace_bytes(prob, op, prec_mask, nrhs))
+
+
+def pack_gauge(prob: Problem, U_canon, prec=F64, recon=RECON18, out=None, stream=None):
+    """U_canon: complex128 device tensor (V, 4, 3, 3) -> packed uint8 device tensor."""
+    assert U_canon.is_contiguous()
+    out = _bytes(gauge_bytes(prob, prec, recon)) if out is None else out
+    _check(lib().tmqcd_pack_gauge(ctypes.byref(prob.c()), _ptr(U_canon), _ptr(out), prec, recon, _stream(stream)),
+           "tmqcd_pack_gauge")
+    return out
+
+
+def pack_spinor(prob: Problem, psi, prec=F64, subset=FULL, nrhs=1, out=None, stream=None):
+    """psi: complex128 device tensor ([nrhs,] n, 4, 3) -> packed uint8 device tensor."""
+    assert psi.is_contiguous()
+    out = _bytes(spinor_bytes(prob, prec, subset, nrhs)) if out is None else out
+    _check(lib().tmqcd_pack_spinor(ctypes.byref(prob.c()), _ptr(psi), _ptr(out), prec, subset, nrhs,
+                                   _stream(stream)), "tmqcd_pack_spinor")
+    return out
+
+
+def unpack_spinor(prob: Problem, packed, prec=F64, subset=FULL, nrhs=1, stream=None):
+    import torch
+    n = prob.volume if subset == FULL else prob.volume // 2
+    shape = (n, 4, 3) if nrhs == 1 else (nrhs, n, 4, 3)
+    out = torch.empty(shape, dtype=torch.complex128, device=packed.device)
+    _check(lib().tmqcd_unpack_spinor(ctypes.byref(prob.c()), _ptr(packed), _ptr(out), prec, subset, nrhs,
+                                     _stream(stream)), "tmqcd_unpack_spinor")
+    return out
+
+
+def dslash(prob: Problem, U_packed, inp, op, prec=F64, recon=RECON18, nrhs=1, ws=None, out=None, stream=None):
+    """out = op(inp) on packed fields."""
+    if out is None:
+        out = _bytes(spinor_bytes(prob, prec, OP_SUBSETS[op][1], nrhs))
+    if ws is None:
+        ws = _bytes(workspace_bytes(prob, op, 1 << prec, nrhs))
+    _check(lib().tmqcd_dslash(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(inp), _ptr(out), op, prec, recon, nrhs,
+                              _ptr(ws), ws.numel(), _stream(stream)), "tmqcd_dslash")
+    return out
+
+
+def cg(prob: Problem, U_packed: dict, b, x=None, *, tol=1e-10, max_iter=10000, op=MHATDAGMHAT, inner_prec=F64,
+       recon=RECON18, reliable_delta=0.0, check_every=0, ws=None, stream=None, raise_on_noconv=True):
+    """Solve op x = b (packed FP64 fields).  U_packed maps precision -> packed gauge field.
+
+    Returns (x, stats dict, return code)."""
+    subset = FULL if op == MDAGM else EVEN
+    x_is_zero = x is None
+    if x is None:
+        x = _bytes(spinor_bytes(prob, F64, subset))
+    if ws is None:
+        ws = _bytes(workspace_bytes(prob, op, 1 | (1 << inner_prec)))
+    gp = (ctypes.c_void_p * 3)(*[_ptr(U_packed.get(p)) for p in (F64, F32, F16)])
+    o = CCgOpts(tol=tol, max_iter=max_iter, op=op, inner_prec=inner_prec, recon=recon,
+                reliable_delta=reliable_delta, check_every=check_every, x_is_zero=int(x_is_zero))
+    st = CCgStats()
+    rc = lib().tmqcd_cg(ctypes.byref(prob.c()), ctypes.byref(gp), _ptr(b), _ptr(x), ctypes.byref(o),
+                        ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream))
+    if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
+        raise TmqcdError(rc, "tmqcd_cg")
+    return x, st.as_dict(), rc
+
+
+def force(prob: Problem, U_packed, X, Y, recon=RECON18, out=None, stream=None):
+    """dS_f/dw^a, float64 device tensor (V, 4, 8), from packed FP64 full fields X and Y = M X."""
+    import torch
+    if out is None:
+        out = torch.empty((prob.volume, 4, 8), dtype=torch.float64, device=X.device)
+    _check(lib().tmqcd_force(ctypes.byref(prob.c()), _ptr(U_packed), recon, _ptr(X), _ptr(Y), _ptr(out),
+                             _stream(stream)), "tmqcd_force")
+    return out

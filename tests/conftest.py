@@ -17,3 +17,13 @@ def pytest_configure(config):
 def rng():
     import numpy as np
     return np.random.default_rng(12345)
+
+
+@pytest.fixture(scope="session")
+def built_lib():
+    """The in-tree HIP library; built here (hipcc cross-compiles for gfx950) only if absent."""
+    from paper_1209_5942_amd import tmqcd
+    if not os.path.exists(tmqcd.LIB_PATH):
+        from paper_1209_5942_amd import build
+        build.build()
+    return tmqcd.LIB_PATH

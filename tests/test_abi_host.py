@@ -1,0 +1,121 @@
+"""The C interface on the host (no GPU): the library loads, exports every entry
+point the header declares, reports packed sizes that match the paper's memory
+table, and rejects bad arguments before making any HIP call."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_1209_5942_amd import tmqcd as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L(built_lib):
+    return T.lib()
+
+
+def test_header_symbols_exported(L):
+    header = open(os.path.join(ROOT, "include", "tmqcd.h")).read()
+    declared = set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\*?\s+\**(tmqcd_[a-z_0-9]+)\(", header, re.M))
+    assert declared == set(T.ENTRY_POINTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_sizes_match_paper_memory_table(L):
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "memory_table.json")))
+    prob = T.Problem((8, 8, 8, 8), 0.15, 0.0)       # V/2 is a multiple of 64: no padding
+    v = prob.volume
+    assert T.spinor_bytes(prob, T.F64, T.FULL) == gold["phi"] * v
+    assert T.spinor_bytes(prob, T.F64, T.EVEN) == gold["phi_eo"] * v
+    assert T.gauge_bytes(prob, T.F64, T.RECON18) == gold["U"] * v
+    assert T.gauge_bytes(prob, T.F64, T.RECON12) == gold["U_REC12"] * v
+    # lower precisions halve and quarter the storage (FP16 spinors carry one FP32 scale per site)
+    assert T.spinor_bytes(prob, T.F32, T.FULL) == gold["phi"] * v // 2
+    assert T.spinor_bytes(prob, T.F16, T.FULL) == gold["phi"] * v // 4 + 4 * v
+    assert T.gauge_bytes(prob, T.F32, T.RECON12) == gold["U_REC12"] * v // 2
+    assert T.spinor_bytes(prob, T.F64, T.FULL, nrhs=12) == 12 * gold["phi"] * v
+
+
+def test_ragged_volume_is_padded_to_a_wavefront(L):
+    prob = T.Problem((6, 2, 2, 2), 0.15, 0.0)       # V/2 = 24 -> padded to 64
+    assert T.spinor_bytes(prob, T.F64, T.EVEN) == 12 * 16 * 64
+    assert T.workspace_bytes(prob, T.MHATDAGMHAT, 1 | 2 | 4) > 0
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 4, 4), (4, 4, 4, 1), (0, 4, 4, 4), (4, 4, 6, 5)])
+def test_bad_extents_rejected(L, dims):
+    prob = T.Problem(dims, 0.15, 0.0)
+    assert T.gauge_bytes(prob) == 0
+    rc = L.tmqcd_dslash(ctypes.byref(prob.c()), 256, 512, 1 << 20, T.M, T.F64, T.RECON18, 1, None, 0, None)
+    assert rc == T.EINVAL
+
+
+def _dslash(L, prob, U, inp, out, op=T.M, prec=T.F64, recon=T.RECON18, nrhs=1, ws=None, wsb=0):
+    return L.tmqcd_dslash(ctypes.byref(prob.c()), U, inp, out, op, prec, recon, nrhs, ws, wsb, None)
+
+
+def test_dslash_argument_errors(L):
+    prob = T.Problem((4, 4, 4, 4), 0.15, 0.01)
+    fb = T.spinor_bytes(prob, T.F64, T.FULL)
+    U, a, b = 1 << 30, 1 << 32, 1 << 34              # never dereferenced: every call fails validation
+    assert _dslash(L, prob, None, a, b) == T.EINVAL
+    assert _dslash(L, prob, U, a, b, op=99) == T.EINVAL
+    assert _dslash(L, prob, U, a, b, prec=3) == T.EINVAL
+    assert _dslash(L, prob, U, a, b, recon=2) == T.EINVAL
+    assert _dslash(L, prob, U, a, b, nrhs=0) == T.EINVAL
+    assert _dslash(L, prob, U, a, b, nrhs=17) == T.EINVAL
+    assert _dslash(L, prob, U, a + 8, b) == T.EALIGN
+    assert _dslash(L, prob, U, a, a + fb - 256) == T.EALIAS
+    assert _dslash(L, prob, U, a, b, op=T.MHAT, ws=None) == T.EWORKSPACE
+    need = T.workspace_bytes(prob, T.MHAT, 1)
+    assert _dslash(L, prob, U, a, b, op=T.MHAT, ws=1 << 36, wsb=need - 1) == T.EWORKSPACE
+    assert _dslash(L, prob, U, a, b, op=T.MHAT, ws=a, wsb=need) == T.EALIAS
+
+
+def test_cg_argument_errors(L):
+    prob = T.Problem((4, 4, 4, 4), 0.15, 0.01)
+    gp = (ctypes.c_void_p * 3)(1 << 30, None, None)
+    st = T.CCgStats()
+
+    def call(**kw):
+        o = dict(tol=1e-10, max_iter=100, op=T.MHATDAGMHAT, inner_prec=T.F64, recon=0, reliable_delta=0.0,
+                 check_every=0, x_is_zero=1)
+        ws = kw.pop("ws", 1 << 36)
+        wsb = kw.pop("wsb", 1 << 30)
+        b = kw.pop("b", 1 << 32)
+        x = kw.pop("x", 1 << 34)
+        o.update(kw)
+        return L.tmqcd_cg(ctypes.byref(prob.c()), ctypes.byref(gp), b, x, ctypes.byref(T.CCgOpts(**o)),
+                          ctypes.byref(st), ws, wsb, None)
+
+    assert call(op=T.M) == T.EINVAL
+    assert call(tol=0.0) == T.EINVAL
+    assert call(max_iter=0) == T.EINVAL
+    assert call(inner_prec=T.F32) == T.EINVAL          # no FP32 gauge field given
+    assert call(reliable_delta=1.5) == T.EINVAL
+    assert call(x=(1 << 32) + 256) == T.EALIAS
+    assert call(ws=None) == T.EWORKSPACE
+    assert call(wsb=1024) == T.EWORKSPACE
+    assert call(b=(1 << 32) + 4) == T.EALIGN
+
+
+def test_pack_and_force_argument_errors(L):
+    prob = T.Problem((4, 4, 4, 4), 0.15, 0.01)
+    p = ctypes.byref(prob.c())
+    assert L.tmqcd_pack_gauge(p, None, 1 << 30, 0, 0, None) == T.EINVAL
+    assert L.tmqcd_pack_gauge(p, (1 << 30) + 8, 1 << 32, 0, 0, None) == T.EALIGN
+    assert L.tmqcd_pack_spinor(p, 1 << 30, 1 << 30, 0, 0, 1, None) == T.EALIAS
+    assert L.tmqcd_pack_spinor(p, 1 << 30, 1 << 32, 0, 5, 1, None) == T.EINVAL
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, None, 1 << 34, None) == T.EINVAL
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, 1 << 32, None) == T.EALIAS
+
+
+def test_error_strings(L):
+    for code in (T.OK, T.EINVAL, T.EALIAS, T.EALIGN, T.ENOCONV, T.EBREAKDOWN, T.EHIP, T.EWORKSPACE):
+        assert T.error_string(code) and "unknown" not in T.error_string(code)
+    assert "unknown" in T.error_string(-99)
