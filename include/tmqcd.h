@@ -142,7 +142,8 @@ typedef struct {
     int32_t inner_prec;      /* TMQCD_F64: plain FP64 CG; TMQCD_F32 / TMQCD_F16: mixed precision */
     int32_t recon;           /* link storage of every U_packed[] given */
     double  reliable_delta;  /* mixed: reliable update when the residual fell by this factor (0 -> 0.1) */
-    int32_t check_every;     /* iterations queued between host residual checks (0 -> 8) */
+    int32_t check_every;     /* most iterations queued between host residual checks (0 -> 32); batches
+                                are sized from the observed convergence rate */
     int32_t x_is_zero;       /* 1: ignore the contents of x and start from x0 = 0 */
 } tmqcd_cg_opts;
 

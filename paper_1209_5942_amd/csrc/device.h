@@ -158,6 +158,22 @@ struct SpinorIO<TMQCD_F16> {
 };
 
 // --------------------------------------------------------- link site I/O ---
+// Links are read exactly once per hop; nontemporal loads keep them from
+// displacing the neighbour spinors that other sites will read again.
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+    if constexpr (sizeof(V) == 16) {
+        typedef int v4 __attribute__((ext_vector_type(4)));
+        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const v4*>(p)));
+    } else if constexpr (sizeof(V) == 8) {
+        typedef int v2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const v2*>(p)));
+    } else {
+        static_assert(sizeof(V) == 4, "unsupported link unit");
+        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const int*>(p)));
+    }
+}
+
 // `base` points at the whole packed gauge field; the link of direction mu whose
 // origin site has parity `par` and half index h.
 template <typename T>
@@ -180,7 +196,7 @@ struct LinkIO<TMQCD_F64, R> {
         const double2* p = reinterpret_cast<const double2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < kUnits; ++k) {
-            double2 w = p[k * gstride];
+            const double2 w = ld_stream(p + k * gstride);
             u.m[k / 3][k % 3] = {w.x, w.y};
         }
         if constexpr (R == TMQCD_RECON12) rebuild_third_row(u);
@@ -202,7 +218,7 @@ struct LinkIO<TMQCD_F32, TMQCD_RECON18> {
         const float2* p = reinterpret_cast<const float2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            float2 w = p[k * gstride];
+            const float2 w = ld_stream(p + k * gstride);
             u.m[k / 3][k % 3] = {w.x, w.y};
         }
     }
@@ -223,7 +239,7 @@ struct LinkIO<TMQCD_F32, TMQCD_RECON12> {
         const float4* p = reinterpret_cast<const float4*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            float4 w = p[k * gstride];
+            const float4 w = ld_stream(p + k * gstride);
             u.m[(2 * k) / 3][(2 * k) % 3] = {w.x, w.y};
             u.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {w.z, w.w};
         }
@@ -249,7 +265,7 @@ struct LinkIO<TMQCD_F16, TMQCD_RECON18> {
         const __half2* p = reinterpret_cast<const __half2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            float2 w = __half22float2(p[k * gstride]);
+            const float2 w = __half22float2(ld_stream(p + k * gstride));
             u.m[k / 3][k % 3] = {w.x, w.y};
         }
     }
@@ -277,7 +293,7 @@ struct LinkIO<TMQCD_F16, TMQCD_RECON12> {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             U8 w;
-            w.u = p[k * gstride];
+            w.u = ld_stream(p + k * gstride);
             u.m[(2 * k) / 3][(2 * k) % 3] = {__half2float(w.h[0]), __half2float(w.h[1])};
             u.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {__half2float(w.h[2]), __half2float(w.h[3])};
         }

@@ -308,7 +308,7 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
     const VecSpec vs{&g, nh};
     const int op = full ? TMQCD_MDAGM : TMQCD_MHATDAGMHAT;
     const int hops_per_apply = full ? 2 : 4;
-    const int check = o.check_every > 0 ? o.check_every : 8;
+    const int check = o.check_every > 0 ? o.check_every : 32;
     const double delta = o.reliable_delta > 0 ? o.reliable_delta : 0.1;
     char* tmp64 = static_cast<char*>(w.t1);   // t1 (and t2 for even-odd) are contiguous
 
@@ -340,14 +340,17 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
     TRY(read_state(w.st, hs, s));
     const double bb = hs.s.result[1];
     double rr = hs.s.result[0];
-    if (!(bb > 0.0)) {   // b = 0: x = 0 is exact
+    if (!std::isfinite(rr) || !std::isfinite(bb)) {
+        TRY(hipStreamSynchronize(s));
+        return TMQCD_EBREAKDOWN;
+    }
+    if (bb == 0.0) {   // b = 0: x = 0 is exact
         TRY(launch_zero(vs, x, TMQCD_F64, s));
         stats.converged = 1;
         stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         TRY(hipStreamSynchronize(s));
         return TMQCD_OK;
     }
-    if (!std::isfinite(rr) || !std::isfinite(bb)) return TMQCD_EBREAKDOWN;
     const double target = o.tol * o.tol * bb;
 
     // fields of the iteration
@@ -378,11 +381,26 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
     int iters_done = 0;
     for (;;) {
         if (rr > target) {
-            // queue iterations in batches until the device flags a stop
+            // Queue iterations in batches until the device flags a stop.  After the
+            // first batch, each batch is sized from the observed convergence rate so
+            // that few iterations are queued past the stop (those return at once).
+            int batch = std::min(check, 8);
+            double rr_poll = rr;
+            int it_poll = iters_done;
             for (;;) {
-                for (int k = 0; k < check; ++k) TRY(queue_iteration(cq, full, f, w.st, w.partials, pv));
+                for (int k = 0; k < batch; ++k) TRY(queue_iteration(cq, full, f, w.st, w.partials, pv));
                 TRY(read_state(w.st, hs, s));
                 if (hs.s.done != kDoneRunning) break;
+                int next = check;
+                const int di = hs.s.iter - it_poll;
+                if (di > 0 && hs.s.rr > 0 && hs.s.rr < rr_poll) {
+                    const double rate = std::log(hs.s.rr / rr_poll) / di;
+                    const double need = std::ceil(std::log(hs.s.stop_rr / hs.s.rr) / rate);
+                    next = need < 1 ? 1 : (need > check ? check : (int)need);
+                }
+                batch = next;
+                rr_poll = hs.s.rr;
+                it_poll = hs.s.iter;
             }
             iters_done = hs.s.iter;
         }

@@ -201,13 +201,16 @@ def dslash(prob: Problem, U_packed, inp, op, prec=F64, recon=RECON18, nrhs=1, ws
     return out
 
 
-def cg(prob: Problem, U_packed: dict, b, x=None, *, tol=1e-10, max_iter=10000, op=MHATDAGMHAT, inner_prec=F64,
-       recon=RECON18, reliable_delta=0.0, check_every=0, ws=None, stream=None, raise_on_noconv=True):
+def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, max_iter=10000, op=MHATDAGMHAT,
+       inner_prec=F64, recon=RECON18, reliable_delta=0.0, check_every=0, ws=None, stream=None,
+       raise_on_noconv=True):
     """Solve op x = b (packed FP64 fields).  U_packed maps precision -> packed gauge field.
 
-    Returns (x, stats dict, return code)."""
+    x: output buffer (allocated when None).  x_is_zero: start from x0 = 0 (default: when x is None);
+    otherwise the contents of x are the start vector.  Returns (x, stats dict, return code)."""
     subset = FULL if op == MDAGM else EVEN
-    x_is_zero = x is None
+    if x_is_zero is None:
+        x_is_zero = x is None
     if x is None:
         x = _bytes(spinor_bytes(prob, F64, subset))
     if ws is None:
