@@ -107,8 +107,9 @@ typedef struct {
 size_t tmqcd_gauge_bytes(const tmqcd_problem* prob, int prec, int recon);
 size_t tmqcd_spinor_bytes(const tmqcd_problem* prob, int prec, int subset, int nrhs);
 /* Workspace for tmqcd_dslash (op), tmqcd_cg (op = TMQCD_MDAGM or
- * TMQCD_MHATDAGMHAT) and tmqcd_force (op = -1).  prec_mask: bit (1 << prec) for
- * every storage precision the call will use (for CG: F64 and the inner one). */
+ * TMQCD_MHATDAGMHAT) and the reductions of the HMC helpers (op = -1).  prec_mask:
+ * bit (1 << prec) for every storage precision the call will use (for CG: F64 and
+ * the inner one). */
 size_t tmqcd_workspace_bytes(const tmqcd_problem* prob, int op, int prec_mask, int nrhs);
 
 /* ---- layout conversion (the paper's transparent AoS <-> SoA conversion) ----- */
@@ -116,6 +117,10 @@ size_t tmqcd_workspace_bytes(const tmqcd_problem* prob, int op, int prec_mask, i
  * packed layout of (prec, recon).  Rounds to nearest even on down-conversion. */
 int tmqcd_pack_gauge(const tmqcd_problem* prob, const void* U_canon, void* U_packed,
                      int prec, int recon, void* stream);
+/* Inverse of tmqcd_pack_gauge: packed -> canonical complex128 U_canon[V][4][3][3]
+ * (12-real links come back with their third row rebuilt). */
+int tmqcd_unpack_gauge(const tmqcd_problem* prob, const void* U_packed, void* U_canon,
+                       int prec, int recon, void* stream);
 /* Pack canonical complex128 spinors [nrhs][n][4][3] (n = V for TMQCD_FULL, V/2
  * otherwise) into the packed layout of prec.  in_canon and out_packed must not
  * overlap. */
@@ -170,16 +175,41 @@ int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const voi
              void* stream);
 
 /* ---- the fermion force -------------------------------------------------------- */
-/* dSdw[V][4][8] (device, float64, canonical): the gradient of
- * S_f = phi^+ (M^+ M)^{-1} phi with respect to w^a for U_mu(x) -> exp(i w^a T^a) U_mu(x),
- * given X = (M^+ M)^{-1} phi and Y = M X as packed FP64 full fields (the paper's
- * force section: the fermion force needs one inversion and only the hopping
- * part of M depends on U).  U_packed: FP64, RECON18 or RECON12.
- * G^a = -2 kappa Im Tr[T^a (b+ Q1 - conj(b+) Q2)],
- * Q1 = sum_spin [(1 - gamma_mu) U_mu(x) X(x+mu)] (x) Y(x)^+,
- * Q2 = sum_spin X(x) (x) [U_mu(x) (1 + gamma_mu) Y(x+mu)]^+. */
+/* The gradient G^a_mu(x) = dS_f/dw^a of S_f = phi^+ (M^+ M)^{-1} phi with respect
+ * to U_mu(x) -> exp(i w^a T^a) U_mu(x), T^a = lambda^a / 2, given X = (M^+ M)^{-1} phi
+ * and Y = M X as packed FP64 full fields (the paper's force section: the fermion
+ * force needs one inversion, and only the hopping part of M depends on U):
+ *   G^a = -2 kappa Im Tr[T^a (b+ Q1 - conj(b+) Q2)],
+ *   Q1 = sum_spin [(1 - gamma_mu) U_mu(x) X(x+mu)] (x) Y(x)^+,
+ *   Q2 = sum_spin X(x) (x) [U_mu(x) (1 + gamma_mu) Y(x+mu)]^+.
+ * dSdw[V][4][8] (device, float64, canonical) receives scale * G (accumulate = 0)
+ * or has scale * G added (accumulate = 1): with dSdw = p and scale = -dt this is
+ * the HMC momentum update.  U_packed: FP64, RECON18 or RECON12. */
 int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X,
-                const void* Y, double* dSdw, void* stream);
+                const void* Y, double* dSdw, double scale, int accumulate, void* stream);
+
+/* ---- hybrid Monte-Carlo helpers (the paper's ensemble-generation section) ----- */
+/* Gradient of the Wilson plaquette action S_g = (beta/3) sum_{x,mu<nu} (3 - Re Tr P_mu_nu(x))
+ * (the paper's tree-level Symanzik action at c1 = 0; no boundary phases):
+ * G^a = (beta/3) Im Tr[T^a U_mu(x) V_mu(x)], V_mu the six staples.  Written or
+ * accumulated into dSdw[V][4][8] like tmqcd_force.  U_packed: FP64, RECON18. */
+int tmqcd_gauge_force(const tmqcd_problem* prob, const void* U_packed, double beta, double* dSdw,
+                      double scale, int accumulate, void* stream);
+/* U_mu(x) <- exp(i dt p^a T^a) U_mu(x) for every link, in place on the packed
+ * FP64 RECON18 field; p[V][4][8] (device, float64).  The exponential is exact to
+ * FP64 rounding (Taylor polynomial after scaling, then squaring). */
+int tmqcd_update_links(const tmqcd_problem* prob, void* U_packed, const double* p, double dt,
+                       void* stream);
+/* Deterministic FP64 reductions into device memory.  ws: tmqcd_workspace_bytes(prob, -1, 1, 1) bytes.
+ *   tmqcd_plaquette:      result[0] = sum_{x, mu<nu} Re Tr P_mu_nu(x)       (U_packed FP64 RECON18)
+ *   tmqcd_momentum_norm2: result[0] = sum p^2 over all V*4*8 entries
+ *   tmqcd_dot:            result[0] + i result[1] = x^+ y for packed FP64 fields of `subset` */
+int tmqcd_plaquette(const tmqcd_problem* prob, const void* U_packed, double* result, void* ws,
+                    size_t ws_bytes, void* stream);
+int tmqcd_momentum_norm2(const tmqcd_problem* prob, const double* p, double* result, void* ws,
+                         size_t ws_bytes, void* stream);
+int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subset, double* result,
+              void* ws, size_t ws_bytes, void* stream);
 
 /* ---- diagnostics ------------------------------------------------------------- */
 const char* tmqcd_error_string(int code);

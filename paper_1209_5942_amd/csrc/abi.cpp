@@ -63,6 +63,8 @@ int out_subset(int op) {
     return TMQCD_EVEN;
 }
 
+int64_t mom_bytes(const Geom& g) { return 2 * g.vh * 4 * 8 * 8; }
+
 int hip_fail(hipError_t e) {
     g_last_hip_error = (int)e;
     return TMQCD_EHIP;
@@ -107,7 +109,7 @@ size_t tmqcd_spinor_bytes(const tmqcd_problem* prob, int prec, int subset, int n
 
 size_t tmqcd_workspace_bytes(const tmqcd_problem* prob, int op, int prec_mask, int nrhs) {
     if (!valid_problem(prob) || nrhs < 1 || nrhs > kMaxRhs) return 0;
-    if (op == -1) return 256;   // the force needs no workspace
+    if (op == -1) return (size_t)round_up(8 * aux_partials_doubles(make_geom(*prob)), kAlignBytes);
     if (!valid_op(op) || (prec_mask & ~7) || prec_mask == 0) return 0;
     const Geom g = make_geom(*prob);
     int64_t need = dslash_workspace(g, op, prec_mask);
@@ -125,6 +127,16 @@ int tmqcd_pack_gauge(const tmqcd_problem* prob, const void* U_canon, void* U_pac
     const Geom g = make_geom(*prob);
     if (overlap(U_canon, 2 * g.vh * 4 * 9 * 16, U_packed, gauge_bytes(g, prec, recon))) return TMQCD_EALIAS;
     const hipError_t e = launch_pack_gauge(g, U_canon, U_packed, prec, recon, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_unpack_gauge(const tmqcd_problem* prob, const void* U_packed, void* U_canon, int prec, int recon,
+                       void* stream) {
+    if (!valid_problem(prob) || !valid_prec(prec) || !valid_recon(recon) || !U_canon || !U_packed) return TMQCD_EINVAL;
+    if (!aligned(U_canon, 16) || !aligned(U_packed, kAlignBytes)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    if (overlap(U_canon, 2 * g.vh * 4 * 9 * 16, U_packed, gauge_bytes(g, prec, recon))) return TMQCD_EALIAS;
+    const hipError_t e = launch_unpack_gauge(g, U_packed, U_canon, prec, recon, (hipStream_t)stream);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
@@ -209,18 +221,89 @@ int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const voi
 }
 
 int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X, const void* Y,
-                double* dSdw, void* stream) {
-    if (!valid_problem(prob) || !valid_recon(recon) || !U_packed || !X || !Y || !dSdw) return TMQCD_EINVAL;
+                double* dSdw, double scale, int accumulate, void* stream) {
+    if (!valid_problem(prob) || !valid_recon(recon) || !U_packed || !X || !Y || !dSdw || !std::isfinite(scale) ||
+        (accumulate != 0 && accumulate != 1))
+        return TMQCD_EINVAL;
     if (!aligned(U_packed, kAlignBytes) || !aligned(X, kAlignBytes) || !aligned(Y, kAlignBytes) ||
         !aligned(dSdw, 16))
         return TMQCD_EALIGN;
     const Geom g = make_geom(*prob);
-    const int64_t fb = field_bytes(g, TMQCD_F64, TMQCD_FULL), ob = 2 * g.vh * 4 * 8 * 8;
-    if (overlap(dSdw, ob, X, fb) || overlap(dSdw, ob, Y, fb) || overlap(dSdw, ob, U_packed, gauge_bytes(g, TMQCD_F64, recon)))
+    const int64_t fb = field_bytes(g, TMQCD_F64, TMQCD_FULL), ob = mom_bytes(g);
+    if (overlap(dSdw, ob, X, fb) || overlap(dSdw, ob, Y, fb) ||
+        overlap(dSdw, ob, U_packed, gauge_bytes(g, TMQCD_F64, recon)))
         return TMQCD_EALIAS;
     Cplx bc[4];
     for (int i = 0; i < 4; ++i) bc[i] = {prob->bc[i][0], prob->bc[i][1]};
-    const hipError_t e = launch_force(g, U_packed, recon, X, Y, dSdw, bc, prob->kappa, (hipStream_t)stream);
+    const hipError_t e =
+        launch_force(g, U_packed, recon, X, Y, dSdw, bc, prob->kappa, scale, accumulate, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_gauge_force(const tmqcd_problem* prob, const void* U_packed, double beta, double* dSdw, double scale,
+                      int accumulate, void* stream) {
+    if (!valid_problem(prob) || !U_packed || !dSdw || !std::isfinite(beta) || !std::isfinite(scale) ||
+        (accumulate != 0 && accumulate != 1))
+        return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes) || !aligned(dSdw, 16)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    if (overlap(dSdw, mom_bytes(g), U_packed, gauge_bytes(g, TMQCD_F64, TMQCD_RECON18))) return TMQCD_EALIAS;
+    const hipError_t e = launch_gauge_force(g, U_packed, beta, dSdw, scale, accumulate, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_update_links(const tmqcd_problem* prob, void* U_packed, const double* p, double dt, void* stream) {
+    if (!valid_problem(prob) || !U_packed || !p || !std::isfinite(dt)) return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes) || !aligned(p, 16)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    if (overlap(p, mom_bytes(g), U_packed, gauge_bytes(g, TMQCD_F64, TMQCD_RECON18))) return TMQCD_EALIAS;
+    const hipError_t e = launch_update_links(g, U_packed, p, dt, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+static int aux_ws_check(const Geom& g, void* ws, size_t ws_bytes) {
+    if (!ws || (int64_t)ws_bytes < 8 * aux_partials_doubles(g)) return TMQCD_EWORKSPACE;
+    if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+    return TMQCD_OK;
+}
+
+int tmqcd_plaquette(const tmqcd_problem* prob, const void* U_packed, double* result, void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!valid_problem(prob) || !U_packed || !result) return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes) || !aligned(result, 8)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int rc = aux_ws_check(g, ws, ws_bytes);
+    if (rc != TMQCD_OK) return rc;
+    if (overlap(ws, ws_bytes, U_packed, gauge_bytes(g, TMQCD_F64, TMQCD_RECON18)) || overlap(ws, ws_bytes, result, 8))
+        return TMQCD_EALIAS;
+    const hipError_t e = launch_plaquette(g, U_packed, result, static_cast<double*>(ws), (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_momentum_norm2(const tmqcd_problem* prob, const double* p, double* result, void* ws, size_t ws_bytes,
+                         void* stream) {
+    if (!valid_problem(prob) || !p || !result) return TMQCD_EINVAL;
+    if (!aligned(p, 16) || !aligned(result, 8)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int rc = aux_ws_check(g, ws, ws_bytes);
+    if (rc != TMQCD_OK) return rc;
+    if (overlap(ws, ws_bytes, p, mom_bytes(g)) || overlap(ws, ws_bytes, result, 8)) return TMQCD_EALIAS;
+    const hipError_t e = launch_mom_norm2(g, p, result, static_cast<double*>(ws), (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subset, double* result, void* ws,
+              size_t ws_bytes, void* stream) {
+    if (!valid_problem(prob) || !x || !y || !result || !valid_subset(subset)) return TMQCD_EINVAL;
+    if (!aligned(x, kAlignBytes) || !aligned(y, kAlignBytes) || !aligned(result, 8)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int rc = aux_ws_check(g, ws, ws_bytes);
+    if (rc != TMQCD_OK) return rc;
+    const int64_t fb = field_bytes(g, TMQCD_F64, subset);
+    if (overlap(ws, ws_bytes, x, fb) || overlap(ws, ws_bytes, y, fb) || overlap(ws, ws_bytes, result, 16))
+        return TMQCD_EALIAS;
+    const hipError_t e = launch_spinor_dot(g, x, y, subset == TMQCD_FULL ? 2 : 1, result, static_cast<double*>(ws),
+                                           (hipStream_t)stream);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 

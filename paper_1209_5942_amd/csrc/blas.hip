@@ -157,6 +157,7 @@ __global__ void set_state_kernel(CgState* st, StateInit v) {
     if (v.set_beta) st->beta = v.beta;
     if (v.set_iter) st->iter = v.iter;
     if (v.set_max_iter) st->max_iter = v.max_iter;
+    if (v.set_cycle_end) st->cycle_end = v.cycle_end;
     if (v.set_done) st->done = v.done;
     if (v.reset_counters)
         for (int i = 0; i < 8; ++i) st->counter[i] = 0u;

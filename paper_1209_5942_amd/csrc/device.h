@@ -191,12 +191,14 @@ template <int R>
 struct LinkIO<TMQCD_F64, R> {
     using T = double;
     static constexpr int kUnits = R == TMQCD_RECON18 ? 9 : 6;
+    // STREAM: nontemporal loads (the link is read once); false where links are re-read
+    template <bool STREAM = true>
     __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
                                                 int64_t h) {
         const double2* p = reinterpret_cast<const double2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < kUnits; ++k) {
-            const double2 w = ld_stream(p + k * gstride);
+            const double2 w = STREAM ? ld_stream(p + k * gstride) : p[k * gstride];
             u.m[k / 3][k % 3] = {w.x, w.y};
         }
         if constexpr (R == TMQCD_RECON12) rebuild_third_row(u);
@@ -346,8 +348,8 @@ struct CgState {
     double stop_rr;   // the update kernel flags done when rr <= stop_rr
     int iter;         // iterations completed
     int max_iter;
-    int done;         // 0 running, 1 reached stop_rr, 2 breakdown, 3 iteration cap
-    int pad;
+    int cycle_end;    // the update kernel flags done when iter reaches it (reliable-update cycle cap)
+    int done;         // 0 running, 1 reached stop_rr or cycle_end, 2 breakdown, 3 iteration cap
     double result[4]; // scratch results of standalone reductions
     unsigned counter[8];
 };

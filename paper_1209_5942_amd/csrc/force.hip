@@ -75,6 +75,8 @@ struct ForceK {
     int lxh, vh, nb_half;
     C<double> bc[4];
     double kappa;
+    double scale;
+    int accumulate;
 };
 
 template <int R, int MU>
@@ -83,7 +85,7 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
     const char* Xn = a.X + (int64_t)(1 - par) * a.hbytes;
     const char* Yn = a.Y + (int64_t)(1 - par) * a.hbytes;
     Su3<double> u;
-    LinkIO<TMQCD_F64, R>::load(u, a.gauge, a.gstride, par, MU, h);
+    LinkIO<TMQCD_F64, R>::template load<true>(u, a.gauge, a.gstride, par, MU, h);
     Spinor<double> xn, yn, v1, v2;
     SpinorIO<TMQCD_F64>::load(xn, Xn, a.stride, nh);
     SpinorIO<TMQCD_F64>::load(yn, Yn, a.stride, nh);
@@ -141,34 +143,34 @@ __global__ __launch_bounds__(kBlock) void force_kernel(const ForceK a) {
         const int xf = x + 1 == lx ? 0 : x + 1;
         force_dir<R, 0>(a, par, h, (h - xh) + (xf >> 1), x == lx - 1, xo, yo, g);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) o[i] = g[i];
+        for (int i = 0; i < 8; ++i) o[i] = a.accumulate ? o[i] + a.scale * g[i] : a.scale * g[i];
     }
     {
         const int nf = y == ly - 1 ? h - (ly - 1) * lxh : h + lxh;
         force_dir<R, 1>(a, par, h, nf, y == ly - 1, xo, yo, g);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) o[8 + i] = g[i];
+        for (int i = 0; i < 8; ++i) o[8 + i] = a.accumulate ? o[8 + i] + a.scale * g[i] : a.scale * g[i];
     }
     {
         const int st = lxh * ly;
         const int nf = z == lz - 1 ? h - (lz - 1) * st : h + st;
         force_dir<R, 2>(a, par, h, nf, z == lz - 1, xo, yo, g);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) o[16 + i] = g[i];
+        for (int i = 0; i < 8; ++i) o[16 + i] = a.accumulate ? o[16 + i] + a.scale * g[i] : a.scale * g[i];
     }
     {
         const int st = lxh * ly * lz;
         const int nf = t == lt - 1 ? h - (lt - 1) * st : h + st;
         force_dir<R, 3>(a, par, h, nf, t == lt - 1, xo, yo, g);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) o[24 + i] = g[i];
+        for (int i = 0; i < 8; ++i) o[24 + i] = a.accumulate ? o[24 + i] + a.scale * g[i] : a.scale * g[i];
     }
 }
 
 }  // namespace
 
 hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* X, const void* Y, double* out,
-                        const Cplx bc[4], double kappa, hipStream_t s) {
+                        const Cplx bc[4], double kappa, double scale, int accumulate, hipStream_t s) {
     ForceK k;
     k.gauge = static_cast<const char*>(gauge);
     k.X = static_cast<const char*>(X);
@@ -185,6 +187,8 @@ hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void*
     k.vh = (int)g.vh;
     k.nb_half = (int)((g.vh + kBlock - 1) / kBlock);
     k.kappa = kappa;
+    k.scale = scale;
+    k.accumulate = accumulate;
     const dim3 grid(2 * k.nb_half);
     if (recon == TMQCD_RECON12) hipLaunchKernelGGL((force_kernel<TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k);
     else hipLaunchKernelGGL((force_kernel<TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k);

@@ -1,0 +1,389 @@
+// Kernels of the hybrid Monte-Carlo around the solver (paper: the ensemble-
+// generation section - momenta conjugate to U, the gauge force from staples,
+// and the evolution U' = exp(i dt P) U):
+//   * Wilson plaquette gauge force (the tree-level Symanzik action at c1 = 0),
+//     G^a = (beta/3) Im Tr[T^a U_mu(x) V_mu(x)] with V_mu the six staples,
+//     written or accumulated with a scale factor (momentum updates fuse here);
+//   * link update U_mu(x) <- exp(i dt p^a T^a) U_mu(x): the exponential of the
+//     anti-hermitian generator by a degree-16 Taylor polynomial after scaling
+//     by 2^-n (||dt P|| / 2^n <= 1/4) and n squarings;
+//   * deterministic two-pass reductions: the plaquette sum, sum p^2, and the
+//     complex inner product of two packed FP64 spinor fields.
+// Momenta and forces use the canonical layout double[V][4][8]; links are the
+// packed FP64 18-real field, updated in place.
+#include "device.h"
+#include "internal.h"
+
+namespace tmqcd {
+namespace {
+
+struct LatK {
+    int L[4];
+    int lxh;
+    int vh;
+    int nb_half;
+    int64_t gstride;
+};
+
+LatK make_latk(const Geom& g) {
+    LatK k;
+    for (int i = 0; i < 4; ++i) k.L[i] = g.L[i];
+    k.lxh = g.lxh;
+    k.vh = (int)g.vh;
+    k.nb_half = (int)((g.vh + kBlock - 1) / kBlock);
+    k.gstride = g.gstride;
+    return k;
+}
+
+// coordinates of the site (par, h)
+__device__ __forceinline__ void coords_of(const LatK& k, int par, int h, int c[4]) {
+    const int xh = h % k.lxh;
+    int rest = h / k.lxh;
+    c[1] = rest % k.L[1];
+    rest /= k.L[1];
+    c[2] = rest % k.L[2];
+    c[3] = rest / k.L[2];
+    c[0] = 2 * xh + ((par + c[1] + c[2] + c[3]) & 1);
+}
+
+// link U_mu at the site c + d (periodic), FP64 18-real packed layout
+__device__ __forceinline__ void link_at(Su3<double>& u, const LatK& k, const char* gauge, const int c[4],
+                                        const int d[4], int mu) {
+    int q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int v = c[i] + d[i];
+        v = v < 0 ? v + k.L[i] : (v >= k.L[i] ? v - k.L[i] : v);
+        q[i] = v;
+    }
+    const int par = (q[0] + q[1] + q[2] + q[3]) & 1;
+    const int s = q[0] + k.L[0] * (q[1] + k.L[1] * (q[2] + k.L[2] * q[3]));
+    LinkIO<TMQCD_F64, TMQCD_RECON18>::load<false>(u, gauge, k.gstride, par, mu, s >> 1);
+}
+
+__device__ __forceinline__ void mat_mul(Su3<double>& r, const Su3<double>& a, const Su3<double>& b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[i][0] * b.m[0][j] + a.m[i][1] * b.m[1][j] + a.m[i][2] * b.m[2][j];
+}
+// a * b^+
+__device__ __forceinline__ void mat_mul_nd(Su3<double>& r, const Su3<double>& a, const Su3<double>& b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r.m[i][j] = cmul_cj(b.m[j][0], a.m[i][0]) + cmul_cj(b.m[j][1], a.m[i][1]) + cmul_cj(b.m[j][2], a.m[i][2]);
+}
+// a^+ * b
+__device__ __forceinline__ void mat_mul_dn(Su3<double>& r, const Su3<double>& a, const Su3<double>& b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r.m[i][j] = cmul_cj(a.m[0][i], b.m[0][j]) + cmul_cj(a.m[1][i], b.m[1][j]) + cmul_cj(a.m[2][i], b.m[2][j]);
+}
+
+// Im Tr(lambda^a W) for the eight Gell-Mann matrices
+__device__ __forceinline__ void im_tr_lambda(const Su3<double>& q, double g[8]) {
+    g[0] = q.m[1][0].im + q.m[0][1].im;
+    g[1] = q.m[0][1].re - q.m[1][0].re;
+    g[2] = q.m[0][0].im - q.m[1][1].im;
+    g[3] = q.m[2][0].im + q.m[0][2].im;
+    g[4] = q.m[0][2].re - q.m[2][0].re;
+    g[5] = q.m[2][1].im + q.m[1][2].im;
+    g[6] = q.m[1][2].re - q.m[2][1].re;
+    g[7] = (q.m[0][0].im + q.m[1][1].im - 2.0 * q.m[2][2].im) * 0.57735026918962576451;
+}
+
+__global__ __launch_bounds__(kBlock) void gauge_force_kernel(LatK k, const char* gauge, double* out, double coef,
+                                                             int accumulate) {
+    const int par = blockIdx.x >= (unsigned)k.nb_half ? 1 : 0;
+    const int h = (blockIdx.x - par * k.nb_half) * kBlock + threadIdx.x;
+    if (h >= k.vh) return;
+    int c[4];
+    coords_of(k, par, h, c);
+    const int64_t s = 2 * (int64_t)h + (c[0] & 1);
+    const int zero[4] = {0, 0, 0, 0};
+    for (int mu = 0; mu < 4; ++mu) {
+        Su3<double> v, a, b, t, u;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) v.m[i][j] = {0.0, 0.0};
+        for (int nu = 0; nu < 4; ++nu) {
+            if (nu == mu) continue;
+            int dm[4] = {0, 0, 0, 0}, dn[4] = {0, 0, 0, 0}, dmn[4] = {0, 0, 0, 0}, dmn2[4] = {0, 0, 0, 0};
+            dm[mu] = 1;
+            dn[nu] = 1;
+            dmn[mu] = 1;
+            dmn[nu] = -1;
+            dmn2[nu] = -1;
+            // U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+            link_at(a, k, gauge, c, dm, nu);
+            link_at(b, k, gauge, c, dn, mu);
+            mat_mul_nd(t, a, b);
+            link_at(a, k, gauge, c, zero, nu);
+            mat_mul_nd(b, t, a);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) v.m[i][j] = v.m[i][j] + b.m[i][j];
+            // U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
+            link_at(a, k, gauge, c, dmn, nu);
+            link_at(b, k, gauge, c, dmn2, mu);
+            mat_mul(t, b, a);                          // U_mu(x-nu) U_nu(x+mu-nu)
+            link_at(a, k, gauge, c, dmn2, nu);
+            mat_mul_dn(b, t, a);                       // (U_mu U_nu)^+ U_nu(x-nu)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) v.m[i][j] = v.m[i][j] + b.m[i][j];
+        }
+        link_at(u, k, gauge, c, zero, mu);
+        mat_mul(t, u, v);
+        double g[8];
+        im_tr_lambda(t, g);
+        double* o = out + s * 32 + mu * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = accumulate ? o[i] + coef * g[i] : coef * g[i];
+    }
+}
+
+// exp(A) for anti-hermitian traceless A = i dt p^a T^a: scaling, Taylor, squaring
+__device__ void su3_exp_i(Su3<double>& e, const double p[8], double dt) {
+    // Q = dt sum_a p^a lambda^a / 2 (hermitian); A = i Q
+    const double s3 = 0.57735026918962576451;
+    const double h = 0.5 * dt;
+    Su3<double> a;
+    // Q entries
+    const C<double> q00 = {h * (p[2] + s3 * p[7]), 0.0};
+    const C<double> q11 = {h * (-p[2] + s3 * p[7]), 0.0};
+    const C<double> q22 = {h * (-2.0 * s3 * p[7]), 0.0};
+    const C<double> q01 = {h * p[0], -h * p[1]};
+    const C<double> q02 = {h * p[3], -h * p[4]};
+    const C<double> q12 = {h * p[5], -h * p[6]};
+    const C<double> qq[3][3] = {{q00, q01, q02}, {conj(q01), q11, q12}, {conj(q02), conj(q12), q22}};
+    double nrm = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            a.m[i][j] = {-qq[i][j].im, qq[i][j].re};   // i * Q
+            nrm += norm2(qq[i][j]);
+        }
+    nrm = sqrt(nrm);
+    int n = 0;
+    while (nrm > 0.25 && n < 40) {
+        nrm *= 0.5;
+        ++n;
+    }
+    const double sc = ldexp(1.0, -n);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a.m[i][j] = scale(sc, a.m[i][j]);
+    // Horner: E = I + A (I + A/2 (I + A/3 (... (I + A/16))))
+    Su3<double> t;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) e.m[i][j] = {i == j ? 1.0 : 0.0, 0.0};
+    for (int kk = 16; kk >= 1; --kk) {
+        mat_mul(t, a, e);
+        const double inv = 1.0 / kk;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) e.m[i][j] = C<double>{(i == j ? 1.0 : 0.0), 0.0} + scale(inv, t.m[i][j]);
+    }
+    for (int kk = 0; kk < n; ++kk) {
+        mat_mul(t, e, e);
+        e = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void update_links_kernel(LatK k, char* gauge, const double* mom, double dt,
+                                                              int64_t nlinks) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= nlinks) return;
+    const int64_t s = idx >> 2;
+    const int mu = (int)(idx & 3);
+    const int x = (int)(s % k.L[0]);
+    int64_t r = s / k.L[0];
+    const int y = (int)(r % k.L[1]);
+    r /= k.L[1];
+    const int z = (int)(r % k.L[2]);
+    const int t = (int)(r / k.L[2]);
+    const int par = (x + y + z + t) & 1;
+    double p[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) p[a] = mom[idx * 8 + a];
+    Su3<double> e, u, nu;
+    su3_exp_i(e, p, dt);
+    LinkIO<TMQCD_F64, TMQCD_RECON18>::load<true>(u, gauge, k.gstride, par, mu, s >> 1);
+    mat_mul(nu, e, u);
+    LinkIO<TMQCD_F64, TMQCD_RECON18>::store(gauge, k.gstride, par, mu, s >> 1, nu);
+}
+
+// ----------------------------------------------------------- reductions ---
+template <int N>
+__device__ __forceinline__ void block_partial(double (&v)[N], double* partials) {
+    __shared__ double sh[N][kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double s = wave_sum(v[i]);
+        if (lane == 0) sh[i][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double s = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) s += sh[i][w];
+            partials[(int64_t)blockIdx.x * N + i] = s;
+        }
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void finalize_kernel(const double* partials, int nblocks, double* result) {
+    double acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] += partials[(int64_t)b * N + i];
+    __shared__ double sh[N][kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double s = wave_sum(acc[i]);
+        if (lane == 0) sh[i][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double s = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) s += sh[i][w];
+            result[i] = s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void plaquette_kernel(LatK k, const char* gauge, double* partials) {
+    const int par = blockIdx.x >= (unsigned)k.nb_half ? 1 : 0;
+    const int h = (blockIdx.x - par * k.nb_half) * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (h < k.vh) {
+        int c[4];
+        coords_of(k, par, h, c);
+        const int zero[4] = {0, 0, 0, 0};
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                int dm[4] = {0, 0, 0, 0}, dn[4] = {0, 0, 0, 0};
+                dm[mu] = 1;
+                dn[nu] = 1;
+                Su3<double> a, b, t1, t2;
+                link_at(a, k, gauge, c, zero, mu);
+                link_at(b, k, gauge, c, dm, nu);
+                mat_mul(t1, a, b);                     // U_mu(x) U_nu(x+mu)
+                link_at(a, k, gauge, c, zero, nu);
+                link_at(b, k, gauge, c, dn, mu);
+                mat_mul(t2, a, b);                     // U_nu(x) U_mu(x+nu)
+                // Re Tr[t1 t2^+]
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) v[0] += t1.m[i][j].re * t2.m[i][j].re + t1.m[i][j].im * t2.m[i][j].im;
+            }
+    }
+    block_partial<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void mom_norm2_kernel(const double* mom, int64_t n, double* partials) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < n) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) v[0] += mom[i * 8 + a] * mom[i * 8 + a];
+    }
+    block_partial<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void spinor_dot_kernel(const char* x, const char* y, int64_t stride, int vh,
+                                                            int nhalf, int64_t hbytes, double* partials) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < nhalf * vh) {
+        const int half = i / vh, h = i - half * vh;
+        Spinor<double> a, b;
+        SpinorIO<TMQCD_F64>::load(a, x + half * hbytes, stride, h);
+        SpinorIO<TMQCD_F64>::load(b, y + half * hbytes, stride, h);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const C<double> z = cmul_cj(a.s[s][c], b.s[s][c]);
+                v[0] += z.re;
+                v[1] += z.im;
+            }
+    }
+    block_partial<2>(v, partials);
+}
+
+}  // namespace
+
+int64_t aux_partials_doubles(const Geom& g) {
+    // the largest grid among the reductions (momentum norm: 4 V threads), two values per block
+    return 2 * ((8 * g.vh + kBlock - 1) / kBlock) + 2;
+}
+
+hipError_t launch_gauge_force(const Geom& g, const void* gauge, double beta, double* out, double scale, int accumulate,
+                              hipStream_t s) {
+    const LatK k = make_latk(g);
+    // G^a = (beta/3) Im Tr[T^a U V] = (beta/6) Im Tr[lambda^a U V]
+    hipLaunchKernelGGL(gauge_force_kernel, dim3(2 * k.nb_half), dim3(kBlock), 0, s, k,
+                       static_cast<const char*>(gauge), out, scale * beta / 6.0, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_links(const Geom& g, void* gauge, const double* mom, double dt, hipStream_t s) {
+    const LatK k = make_latk(g);
+    const int64_t n = 8 * g.vh;
+    hipLaunchKernelGGL(update_links_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, k,
+                       static_cast<char*>(gauge), mom, dt, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_plaquette(const Geom& g, const void* gauge, double* result, double* partials, hipStream_t s) {
+    const LatK k = make_latk(g);
+    const int nb = 2 * k.nb_half;
+    hipLaunchKernelGGL(plaquette_kernel, dim3(nb), dim3(kBlock), 0, s, k, static_cast<const char*>(gauge), partials);
+    hipLaunchKernelGGL((finalize_kernel<1>), dim3(1), dim3(kBlock), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_mom_norm2(const Geom& g, const double* mom, double* result, double* partials, hipStream_t s) {
+    const int64_t n = 8 * g.vh;
+    const int nb = (int)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(mom_norm2_kernel, dim3(nb), dim3(kBlock), 0, s, mom, n, partials);
+    hipLaunchKernelGGL((finalize_kernel<1>), dim3(1), dim3(kBlock), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_spinor_dot(const Geom& g, const void* x, const void* y, int nhalf, double* result, double* partials,
+                             hipStream_t s) {
+    const int nb = (int)((nhalf * g.vh + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(spinor_dot_kernel, dim3(nb), dim3(kBlock), 0, s, static_cast<const char*>(x),
+                       static_cast<const char*>(y), g.stride, (int)g.vh, nhalf, half_field_bytes(g, TMQCD_F64),
+                       partials);
+    hipLaunchKernelGGL((finalize_kernel<2>), dim3(1), dim3(kBlock), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+}  // namespace tmqcd

@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(const HopK a) {
                 const int it = st->iter + 1;
                 st->iter = it;
                 if (!isfinite(rr)) st->done = kDoneBreakdown;
-                else if (rr <= st->stop_rr) st->done = kDoneStop;
+                else if (rr <= st->stop_rr || it >= st->cycle_end) st->done = kDoneStop;
                 else if (it >= st->max_iter) st->done = kDoneMaxIter;
             }
         }

@@ -74,8 +74,9 @@ hipError_t launch_zero(const VecSpec& v, void* dst, int prec, hipStream_t s);
 // ---- solver state --------------------------------------------------------------
 struct StateInit {
     double rr, rr_prev, stop_rr, alpha, beta;
-    int iter, max_iter, done;
-    bool set_rr, set_rr_prev, set_stop, set_alpha, set_beta, set_iter, set_max_iter, set_done, reset_counters;
+    int iter, max_iter, cycle_end, done;
+    bool set_rr, set_rr_prev, set_stop, set_alpha, set_beta, set_iter, set_max_iter, set_cycle_end, set_done,
+        reset_counters;
 };
 hipError_t launch_set_state(CgState* st, const StateInit& v, hipStream_t s);
 // st->rr = st->result[slot]; optionally stop_rr = factor * rr
@@ -83,11 +84,23 @@ hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipS
 
 // ---- packing ----------------------------------------------------------------------
 hipError_t launch_pack_gauge(const Geom& g, const void* canon, void* packed, int prec, int recon, hipStream_t s);
+hipError_t launch_unpack_gauge(const Geom& g, const void* packed, void* canon, int prec, int recon, hipStream_t s);
 hipError_t launch_pack_spinor(const Geom& g, const void* canon, void* packed, int prec, int subset, int nrhs,
                               bool unpack, hipStream_t s);
 
 // ---- fermion force ---------------------------------------------------------------
+// out = scale * G (accumulate = 0) or out += scale * G (accumulate = 1)
 hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* X, const void* Y, double* out,
-                        const Cplx bc[4], double kappa, hipStream_t s);
+                        const Cplx bc[4], double kappa, double scale, int accumulate, hipStream_t s);
+
+// ---- HMC kernels and auxiliary reductions (partials: aux_partials_doubles(g) doubles) ----
+int64_t aux_partials_doubles(const Geom& g);
+hipError_t launch_gauge_force(const Geom& g, const void* gauge, double beta, double* out, double scale, int accumulate,
+                              hipStream_t s);
+hipError_t launch_update_links(const Geom& g, void* gauge, const double* mom, double dt, hipStream_t s);
+hipError_t launch_plaquette(const Geom& g, const void* gauge, double* result, double* partials, hipStream_t s);
+hipError_t launch_mom_norm2(const Geom& g, const double* mom, double* result, double* partials, hipStream_t s);
+hipError_t launch_spinor_dot(const Geom& g, const void* x, const void* y, int nhalf, double* result, double* partials,
+                             hipStream_t s);
 
 }  // namespace tmqcd

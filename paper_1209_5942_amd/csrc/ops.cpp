@@ -353,6 +353,7 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
     }
     const double target = o.tol * o.tol * bb;
 
+    int iters_done = 0;
     // fields of the iteration
     Fields f;
     int pv;
@@ -367,18 +368,21 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
         f = Fields{x, w.r, w.p, w.t1, w.t2, w.t3};
         TRY(launch_convert(vs, w.p, TMQCD_F64, w.r, TMQCD_F64, s));
     }
+    // A low-precision inner solve may stagnate above its trigger; after
+    // kCycleCap iterations it returns to an FP64 update regardless.
+    constexpr int kCycleCap = 500;
     auto start_cycle = [&](double rr_now) -> hipError_t {
         StateInit v = no_change();
-        v.set_rr = v.set_stop = v.set_done = true;
+        v.set_rr = v.set_stop = v.set_done = v.set_cycle_end = true;
         v.rr = rr_now;
         v.stop_rr = mixed ? std::max(delta * delta * rr_now, target) : target;
+        v.cycle_end = mixed ? iters_done + kCycleCap : o.max_iter;
         v.done = kDoneRunning;
         return launch_set_state(w.st, v, s);
     };
     TRY(start_cycle(rr));
 
     int status = TMQCD_OK;
-    int iters_done = 0;
     for (;;) {
         if (rr > target) {
             // Queue iterations in batches until the device flags a stop.  After the

@@ -42,6 +42,22 @@ __global__ __launch_bounds__(kBlock) void pack_gauge_kernel(PackK k, const doubl
     }
 }
 
+template <int P, int R>
+__global__ __launch_bounds__(kBlock) void unpack_gauge_kernel(PackK k, double2* canon, const char* packed) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= k.vol) return;
+    const int par = parity_of(k, s);
+    const int64_t h = s >> 1;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        Su3<typename Prec<P>::T> u;
+        LinkIO<P, R>::load(u, packed, k.gstride, par, mu, h);
+        double2* dst = canon + (s * 4 + mu) * 9;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) dst[e] = make_double2((double)u.m[e / 3][e % 3].re, (double)u.m[e / 3][e % 3].im);
+    }
+}
+
 // canonical site index i of field `rhs` <-> (half, h) of the packed field
 template <int P, bool UNPACK>
 __global__ __launch_bounds__(kBlock) void pack_spinor_kernel(PackK k, double2* canon, char* packed, int subset,
@@ -112,6 +128,25 @@ hipError_t launch_pack_gauge(const Geom& g, const void* canon, void* packed, int
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_unpack_gauge(const Geom& g, const void* packed, void* canon, int prec, int recon, hipStream_t s) {
+    const PackK k = make_packk(g, prec);
+    const dim3 grid((unsigned)((k.vol + kBlock - 1) / kBlock));
+    double2* c = static_cast<double2*>(canon);
+    const char* p = static_cast<const char*>(packed);
+    const bool r12 = recon == TMQCD_RECON12;
+#define TMQCD_UNPACK(PR)                                                                                      \
+    if (prec == PR) {                                                                                         \
+        if (r12) hipLaunchKernelGGL((unpack_gauge_kernel<PR, TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k, c, p); \
+        else hipLaunchKernelGGL((unpack_gauge_kernel<PR, TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k, c, p);     \
+        return hipGetLastError();                                                                             \
+    }
+    TMQCD_UNPACK(TMQCD_F64)
+    TMQCD_UNPACK(TMQCD_F32)
+    TMQCD_UNPACK(TMQCD_F16)
+#undef TMQCD_UNPACK
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pack_spinor(const Geom& g, const void* canon, void* packed, int prec, int subset, int nrhs,

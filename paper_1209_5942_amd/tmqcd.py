@@ -27,7 +27,8 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
               MDAGM: (FULL, FULL), MHAT: (EVEN, EVEN), MHATDAG: (EVEN, EVEN), MHATDAGMHAT: (EVEN, EVEN)}
 
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
-                "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg", "tmqcd_force",
+                "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg", "tmqcd_force",
+                "tmqcd_gauge_force", "tmqcd_update_links", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot",
                 "tmqcd_error_string", "tmqcd_last_hip_error")
 
 
@@ -71,18 +72,24 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise TmqcdLibraryMissing(f"{LIB_PATH} is missing: run `python -m paper_1209_5942_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
-        P, V, I, S = ctypes.POINTER(CProblem), ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        P, V, I, S, D = ctypes.POINTER(CProblem), ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
         sig = {
             "tmqcd_gauge_bytes": (S, [P, I, I]),
             "tmqcd_spinor_bytes": (S, [P, I, I, I]),
             "tmqcd_workspace_bytes": (S, [P, I, I, I]),
             "tmqcd_pack_gauge": (I, [P, V, V, I, I, V]),
+            "tmqcd_unpack_gauge": (I, [P, V, V, I, I, V]),
             "tmqcd_pack_spinor": (I, [P, V, V, I, I, I, V]),
             "tmqcd_unpack_spinor": (I, [P, V, V, I, I, I, V]),
             "tmqcd_dslash": (I, [P, V, V, V, I, I, I, I, V, S, V]),
             "tmqcd_cg": (I, [P, ctypes.POINTER(V * 3), V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats),
                              V, S, V]),
-            "tmqcd_force": (I, [P, V, I, V, V, V, V]),
+            "tmqcd_force": (I, [P, V, I, V, V, V, D, I, V]),
+            "tmqcd_gauge_force": (I, [P, V, D, V, D, I, V]),
+            "tmqcd_update_links": (I, [P, V, V, D, V]),
+            "tmqcd_plaquette": (I, [P, V, V, V, S, V]),
+            "tmqcd_momentum_norm2": (I, [P, V, V, V, S, V]),
+            "tmqcd_dot": (I, [P, V, V, I, V, V, S, V]),
             "tmqcd_error_string": (ctypes.c_char_p, [I]),
             "tmqcd_last_hip_error": (I, []),
         }
@@ -171,6 +178,15 @@ def pack_gauge(prob: Problem, U_canon, prec=F64, recon=RECON18, out=None, stream
     return out
 
 
+def unpack_gauge(prob: Problem, U_packed, prec=F64, recon=RECON18, stream=None):
+    """Packed links -> complex128 device tensor (V, 4, 3, 3)."""
+    import torch
+    out = torch.empty((prob.volume, 4, 3, 3), dtype=torch.complex128, device=U_packed.device)
+    _check(lib().tmqcd_unpack_gauge(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(out), prec, recon, _stream(stream)),
+           "tmqcd_unpack_gauge")
+    return out
+
+
 def pack_spinor(prob: Problem, psi, prec=F64, subset=FULL, nrhs=1, out=None, stream=None):
     """psi: complex128 device tensor ([nrhs,] n, 4, 3) -> packed uint8 device tensor."""
     assert psi.is_contiguous()
@@ -226,11 +242,68 @@ def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, m
     return x, st.as_dict(), rc
 
 
-def force(prob: Problem, U_packed, X, Y, recon=RECON18, out=None, stream=None):
-    """dS_f/dw^a, float64 device tensor (V, 4, 8), from packed FP64 full fields X and Y = M X."""
+def _mom(prob: Problem, out, like):
     import torch
     if out is None:
-        out = torch.empty((prob.volume, 4, 8), dtype=torch.float64, device=X.device)
+        out = torch.empty((prob.volume, 4, 8), dtype=torch.float64, device=like.device)
+    return out
+
+
+def force(prob: Problem, U_packed, X, Y, recon=RECON18, out=None, scale=1.0, accumulate=False, stream=None):
+    """scale * dS_f/dw^a (float64 device tensor (V, 4, 8)) from packed FP64 full fields X and Y = M X;
+    with accumulate the result is added to `out`."""
+    out = _mom(prob, out, X)
     _check(lib().tmqcd_force(ctypes.byref(prob.c()), _ptr(U_packed), recon, _ptr(X), _ptr(Y), _ptr(out),
-                             _stream(stream)), "tmqcd_force")
+                             float(scale), int(accumulate), _stream(stream)), "tmqcd_force")
+    return out
+
+
+def gauge_force(prob: Problem, U_packed, beta, out=None, scale=1.0, accumulate=False, stream=None):
+    """scale * dS_g/dw^a of the Wilson plaquette action (FP64 RECON18 links)."""
+    out = _mom(prob, out, U_packed)
+    _check(lib().tmqcd_gauge_force(ctypes.byref(prob.c()), _ptr(U_packed), float(beta), _ptr(out), float(scale),
+                                   int(accumulate), _stream(stream)), "tmqcd_gauge_force")
+    return out
+
+
+def update_links(prob: Problem, U_packed, p, dt, stream=None):
+    """U <- exp(i dt p^a T^a) U in place (FP64 RECON18 packed links)."""
+    _check(lib().tmqcd_update_links(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(p), float(dt), _stream(stream)),
+           "tmqcd_update_links")
+    return U_packed
+
+
+def aux_workspace(prob: Problem):
+    return _bytes(workspace_bytes(prob, -1, 1, 1))
+
+
+def _result(n, like):
+    import torch
+    return torch.empty(n, dtype=torch.float64, device=like.device)
+
+
+def plaquette(prob: Problem, U_packed, ws=None, out=None, stream=None):
+    """Device tensor [sum_{x, mu<nu} Re Tr P_mu_nu(x)]."""
+    ws = aux_workspace(prob) if ws is None else ws
+    out = _result(1, U_packed) if out is None else out
+    _check(lib().tmqcd_plaquette(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(out), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "tmqcd_plaquette")
+    return out
+
+
+def momentum_norm2(prob: Problem, p, ws=None, out=None, stream=None):
+    """Device tensor [sum p^2]."""
+    ws = aux_workspace(prob) if ws is None else ws
+    out = _result(1, p) if out is None else out
+    _check(lib().tmqcd_momentum_norm2(ctypes.byref(prob.c()), _ptr(p), _ptr(out), _ptr(ws), ws.numel(),
+                                      _stream(stream)), "tmqcd_momentum_norm2")
+    return out
+
+
+def dot(prob: Problem, x, y, subset=FULL, ws=None, out=None, stream=None):
+    """Device tensor [Re, Im] of x^+ y for packed FP64 fields."""
+    ws = aux_workspace(prob) if ws is None else ws
+    out = _result(2, x) if out is None else out
+    _check(lib().tmqcd_dot(ctypes.byref(prob.c()), _ptr(x), _ptr(y), subset, _ptr(out), _ptr(ws), ws.numel(),
+                           _stream(stream)), "tmqcd_dot")
     return out

@@ -111,8 +111,18 @@ def test_pack_and_force_argument_errors(L):
     assert L.tmqcd_pack_gauge(p, (1 << 30) + 8, 1 << 32, 0, 0, None) == T.EALIGN
     assert L.tmqcd_pack_spinor(p, 1 << 30, 1 << 30, 0, 0, 1, None) == T.EALIAS
     assert L.tmqcd_pack_spinor(p, 1 << 30, 1 << 32, 0, 5, 1, None) == T.EINVAL
-    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, None, 1 << 34, None) == T.EINVAL
-    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, 1 << 32, None) == T.EALIAS
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, None, 1 << 34, 1.0, 0, None) == T.EINVAL
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, 1 << 34, 1.0, 2, None) == T.EINVAL
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, 1 << 32, 1.0, 0, None) == T.EALIAS
+    assert L.tmqcd_gauge_force(p, 1 << 30, float("nan"), 1 << 34, 1.0, 0, None) == T.EINVAL
+    assert L.tmqcd_gauge_force(p, 1 << 30, 5.0, 1 << 30, 1.0, 0, None) == T.EALIAS
+    assert L.tmqcd_update_links(p, 1 << 30, (1 << 34) + 4, 0.1, None) == T.EALIGN
+    assert L.tmqcd_plaquette(p, 1 << 30, 1 << 34, None, 0, None) == T.EWORKSPACE
+    ws = T.workspace_bytes(prob, -1, 1, 1)
+    assert ws >= 8 * 2 * (prob.volume * 4 // 256)
+    assert L.tmqcd_momentum_norm2(p, 1 << 30, 1 << 34, 1 << 36, 8, None) == T.EWORKSPACE
+    assert L.tmqcd_dot(p, 1 << 30, 1 << 32, 7, 1 << 34, 1 << 36, ws, None) == T.EINVAL
+    assert L.tmqcd_dot(p, 1 << 30, 1 << 32, T.FULL, 1 << 36, 1 << 36, ws, None) == T.EALIAS
 
 
 def test_error_strings(L):
