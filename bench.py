@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle residual check and CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 32^3 x 64 FP64-vs-mixed comparison")
+    ap.add_argument("--no-extras", action="store_true", help="skip the multi-RHS, batch and HMC measurements")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only a 1 GiB copy (counter calibration) and 10 FP64 hop launches at 24^3x48, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and this build has no "
@@ -98,6 +101,10 @@ def main():
     x_dev = torch.empty(T.spinor_bytes(prob, T.F64, T.EVEN), dtype=torch.uint8, device=dev)
     ws = T.workspace(prob, T.MHATDAGMHAT)
     torch.cuda.synchronize()
+
+    if args.kernel_only:
+        kernel_only(T, prob, gauges, b, dev)
+        return
 
     def step():
         _, st, _ = T.cg(prob, {T.F64: gauges[(0, 0)]}, b_dev, x_dev, x_is_zero=True, tol=1e-10, max_iter=5000,
@@ -220,6 +227,11 @@ def main():
         result["cg_32x32x32x64"] = mixed
         del gm, bm, xm, wsm
 
+    if not args.no_extras:
+        result["multi_rhs_24x24x24x48"] = bench_multi_rhs(T, prob, U, dev)
+        result["batch_cg"] = bench_batch(T, synth, dev)
+        result["hmc_16x16x16x32"] = bench_hmc(T, synth, dev)
+
     # ------------------------------------- oracle check and CPU baseline ---
     if not args.no_oracle:
         from threadpoolctl import threadpool_limits
@@ -243,6 +255,144 @@ def main():
             "sample": f"{reps} whole-lattice hops H psi of the FP64 NumPy oracle at 24^3x48 "
                       f"({reps * prob.volume} output sites x 1536 B), {dt:.1f} s, one thread"}
     print(json.dumps(result), flush=True)
+
+
+def kernel_only(T, prob, gauges, b, dev):
+    """Calibration copy of known size, then the FP64 hop kernel; for hardware-counter runs."""
+    import torch
+    a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    src = T.pack_spinor(prob, torch.from_numpy(b).to(dev), T.F64, T.EVEN)
+    out = torch.empty(T.spinor_bytes(prob, T.F64, T.ODD), dtype=torch.uint8, device=dev)
+    for _ in range(10):
+        T.dslash(prob, gauges[(0, 0)], src, T.DSLASH_OE, out=out)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel(), "hop_launches": 10, "hop_algorithmic_bytes": prob.volume // 2 * 1536,
+                      "hop_source_sha": hop_source_hash()}), flush=True)
+
+
+def _events_time(fn, reps, warm=3):
+    import torch
+    for _ in range(warm):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def bench_multi_rhs(T, prob, U, dev):
+    """12 spin-colour point sources through the odd<-even hop: one 12-RHS launch vs 12 launches."""
+    import torch
+
+    from paper_1209_5942_amd import synth
+    log("multi-RHS hop, 12 point sources")
+    vh = prob.volume // 2
+    src = torch.from_numpy(synth.point_sources(vh, 0)).to(dev)
+    U_dev = torch.from_numpy(U).to(dev)
+    out = {}
+    for p, r, pn in ((T.F64, 0, "f64_rec18"), (T.F64, 1, "f64_rec12"), (T.F32, 0, "f32_rec18"), (T.F32, 1, "f32_rec12")):
+        g = T.pack_gauge(prob, U_dev, p, r)
+        s = T.pack_spinor(prob, src, p, T.EVEN, nrhs=12)
+        o = torch.empty(T.spinor_bytes(prob, p, T.ODD, 12), dtype=torch.uint8, device=dev)
+        fi, fo = T.spinor_bytes(prob, p, T.EVEN), T.spinor_bytes(prob, p, T.ODD)
+        t_multi = _events_time(lambda: T.dslash(prob, g, s, T.DSLASH_OE, p, r, nrhs=12, out=o), 20)
+
+        def singles():
+            for k in range(12):
+                T.dslash(prob, g, s[k * fi:(k + 1) * fi], T.DSLASH_OE, p, r, out=o[k * fo:(k + 1) * fo])
+        t_single = _events_time(singles, 10)
+        link = BYTES_PER_SITE[(p, r)] - 2 * (192 if p == T.F64 else 96)
+        spin = 2 * (192 if p == T.F64 else 96)
+        out[pn] = {"multi_us": round(t_multi * 1e6, 1), "twelve_single_us": round(t_single * 1e6, 1),
+                   "speedup": round(t_single / t_multi, 3),
+                   "bytes_per_site_rhs": round(link / 12 + spin, 1),
+                   "multi_GB_s": round(vh * (link + 12 * spin) / t_multi / 1e9, 1)}
+    return out
+
+
+def bench_batch(T, synth, dev):
+    """8^4 + 12^3x24 + 16^3x32 (kappa 0.155, mu 0.01): one batched solve (graph / eager) vs three solves."""
+    import torch
+    log("batched CG over three lattices")
+    dims_list = [(8, 8, 8, 8), (12, 12, 12, 24), (16, 16, 16, 32)]
+    probs = [T.Problem(d, 0.155, 0.01, (1, 1, 1, -1)) for d in dims_list]
+    gauges, bs = [], []
+    for k, (pr, d) in enumerate(zip(probs, dims_list)):
+        gauges.append(T.pack_gauge(pr, torch.from_numpy(synth.random_links(d, 0.4, 60 + k)).to(dev)))
+        bs.append(T.pack_spinor(pr, torch.from_numpy(synth.gaussian_spinor(pr.volume // 2, 70 + k)).to(dev),
+                                T.F64, T.EVEN))
+    side = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(side):
+        xs = [torch.empty(T.spinor_bytes(pr, T.F64, T.EVEN), dtype=torch.uint8, device=dev) for pr in probs]
+        cp = (T.CProblem * 3)(*[pr.c() for pr in probs])
+        ws = torch.empty(T.lib().tmqcd_cg_batch_workspace_bytes(3, cp), dtype=torch.uint8, device=dev)
+        wss = [T.workspace(pr, T.MHATDAGMHAT, 1) for pr in probs]
+        for name, fn in (
+                ("graph_batch", lambda: T.cg_batch(probs, gauges, bs, xs, use_graph=True, ws=ws, stream=side)),
+                ("eager_batch", lambda: T.cg_batch(probs, gauges, bs, xs, use_graph=False, ws=ws, stream=side)),
+                ("three_solves", lambda: [T.cg(pr, {T.F64: g}, b, x, x_is_zero=True, ws=w, stream=side)
+                                          for pr, g, b, x, w in zip(probs, gauges, bs, xs, wss)])):
+            best = None
+            for _ in range(4):
+                side.synchronize()
+                t0 = time.perf_counter()
+                r = fn()
+                side.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            res[name + "_ms"] = round(best * 1e3, 3)
+            if name == "graph_batch":
+                res["iters"] = [st["iters"] for st in r[1]]
+                res["true_rel_residual"] = [st["true_rel_residual"] for st in r[1]]
+    res["sites"] = sum(pr.volume for pr in probs)
+    res["speedup_graph_vs_three"] = round(res["three_solves_ms"] / res["graph_batch_ms"], 3)
+    return res
+
+
+def bench_hmc(T, synth, dev):
+    """16^3x32, eps 0.4, kappa 0.155, mu 0.01: force kernel time and 10 leapfrog trajectories (tau 1, 20 steps)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1209_5942_amd.hmc import HMC
+    log("HMC 16^3x32")
+    dims = (16, 16, 16, 32)
+    prob = T.Problem(dims, 0.155, 0.01, (1, 1, 1, -1))
+    U = torch.from_numpy(synth.random_links(dims, 0.4, 80)).to(dev)
+    h = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10)
+    X = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(prob.volume, 81)).to(dev))
+    Y = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(prob.volume, 82)).to(dev))
+    G = torch.empty((prob.volume, 4, 8), dtype=torch.float64, device=dev)
+    t_force = _events_time(lambda: T.force(prob, h.U, X, Y, out=G), 20)
+    # compulsory bytes per site: 4 links, X and Y once each, the 4 x 8 outputs
+    force_bytes = prob.volume * (4 * 144 + 2 * 192 + 256)
+    dh, acc = [], 0
+    t0 = time.perf_counter()
+    for k in range(10):
+        p = torch.from_numpy(synth.gaussian_momenta(prob.volume, 1000 + k)).to(dev)
+        eta = torch.from_numpy(synth.gaussian_spinor(prob.volume, 2000 + k)).to(dev)
+        u = float(np.random.default_rng(3000 + k).random())
+        out = h.trajectory(p, eta, u, 20, 0.05)
+        dh.append(out["dH"])
+        acc += int(out["accepted"])
+    torch.cuda.synchronize()
+    t_traj = (time.perf_counter() - t0) / 10
+    e = np.exp(-np.clip(np.array(dh), -700, 700))
+    return {"force_us": round(t_force * 1e6, 1), "force_GB_s": round(force_bytes / t_force / 1e9, 1),
+            "trajectory_s": round(t_traj, 3), "dH": [round(x, 6) for x in dh], "acceptance": acc / 10,
+            "exp_minus_dH_mean": round(float(e.mean()), 4),
+            "exp_minus_dH_stderr": round(float(e.std(ddof=1) / math.sqrt(len(e))), 4),
+            "cg_iters_per_solve": round(h.cg_iters / max(1, h.solves), 1),
+            "setup": "two-flavour twisted-mass pseudofermion action (beta = 0), leapfrog 20 x 0.05 from the "
+                     "eps 0.4 start, force solves 1e-10, acceptance solves 1e-12"}
 
 
 if __name__ == "__main__":

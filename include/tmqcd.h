@@ -146,7 +146,8 @@ typedef struct {
     int32_t op;              /* TMQCD_MDAGM or TMQCD_MHATDAGMHAT */
     int32_t inner_prec;      /* TMQCD_F64: plain FP64 CG; TMQCD_F32 / TMQCD_F16: mixed precision */
     int32_t recon;           /* link storage of every U_packed[] given */
-    double  reliable_delta;  /* mixed: reliable update when the residual fell by this factor (0 -> 0.1) */
+    double  reliable_delta;  /* mixed: reliable update when the residual fell by this factor
+                                (0 -> 1e-4 for FP32, 1e-2 for FP16 inner precision) */
     int32_t check_every;     /* most iterations queued between host residual checks (0 -> 32); batches
                                 are sized from the observed convergence rate */
     int32_t x_is_zero;       /* 1: ignore the contents of x and start from x0 = 0 */
@@ -173,6 +174,22 @@ typedef struct {
 int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const void* b, void* x,
              const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes,
              void* stream);
+
+/* ---- several lattices at once ------------------------------------------------ */
+/* FP64 CG on Mhat^+ Mhat for n (1..8) lattices of any volumes in one solve:
+ * every stage of an iteration is a single grid-stride launch over the tiles of
+ * all lattices (each with its own solver state; converged lattices are skipped),
+ * and with use_graph = 1 one iteration is captured once in a hipGraph and
+ * replayed between host checks (on the null stream the library captures on a
+ * stream of its own).  probs[n], U_packed[n] (FP64, opts->recon), b[n], x[n]
+ * (packed FP64 even fields; x may not overlap any b or another x), stats[n].
+ * opts->op must be TMQCD_MHATDAGMHAT and opts->inner_prec TMQCD_F64; x starts
+ * from 0.  Results equal those of tmqcd_cg on each lattice alone.
+ * Returns TMQCD_ENOCONV if a lattice hit max_iter (the others are solved). */
+size_t tmqcd_cg_batch_workspace_bytes(int n, const tmqcd_problem* probs);
+int tmqcd_cg_batch(int n, const tmqcd_problem* probs, const void* const* U_packed, const void* const* b,
+                   void* const* x, const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, int use_graph,
+                   void* ws, size_t ws_bytes, void* stream);
 
 /* ---- the fermion force -------------------------------------------------------- */
 /* The gradient G^a_mu(x) = dS_f/dw^a of S_f = phi^+ (M^+ M)^{-1} phi with respect

@@ -83,11 +83,11 @@ int64_t cg_workspace(const Geom& g, int op, int prec_mask) {
     return need;
 }
 
-int64_t dslash_workspace(const Geom& g, int op, int prec_mask) {
+int64_t dslash_workspace(const Geom& g, int op, int prec_mask, int nrhs) {
     int64_t need = 0;
     for (int p = 0; p < 3; ++p)
         if (prec_mask & (1 << p)) {
-            const int64_t t = dslash_tmp_bytes(g, op, p);
+            const int64_t t = nrhs * dslash_tmp_bytes(g, op, p);
             need = t > need ? t : need;
         }
     return need;
@@ -112,7 +112,7 @@ size_t tmqcd_workspace_bytes(const tmqcd_problem* prob, int op, int prec_mask, i
     if (op == -1) return (size_t)round_up(8 * aux_partials_doubles(make_geom(*prob)), kAlignBytes);
     if (!valid_op(op) || (prec_mask & ~7) || prec_mask == 0) return 0;
     const Geom g = make_geom(*prob);
-    int64_t need = dslash_workspace(g, op, prec_mask);
+    int64_t need = dslash_workspace(g, op, prec_mask, nrhs);
     if (op == TMQCD_MDAGM || op == TMQCD_MHATDAGMHAT) {
         const int64_t t = cg_workspace(g, op, prec_mask);
         need = t > need ? t : need;
@@ -181,19 +181,15 @@ int tmqcd_dslash(const tmqcd_problem* prob, const void* U_packed, const void* in
     const Geom g = make_geom(*prob);
     const int64_t fin = field_bytes(g, prec, in_subset(op)), fout = field_bytes(g, prec, out_subset(op));
     if (overlap(in, nrhs * fin, out, nrhs * fout)) return TMQCD_EALIAS;
-    const int64_t need = dslash_tmp_bytes(g, op, prec);
+    const int64_t need = nrhs * dslash_tmp_bytes(g, op, prec);
     if (need > 0) {
         if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
         if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
         if (overlap(ws, need, in, nrhs * fin) || overlap(ws, need, out, nrhs * fout)) return TMQCD_EALIAS;
     }
     const OpCtx c = make_ctx(*prob, prec, recon, U_packed, (hipStream_t)stream);
-    for (int k = 0; k < nrhs; ++k) {
-        const hipError_t e = apply_operator(c, op, static_cast<const char*>(in) + k * fin,
-                                            static_cast<char*>(out) + k * fout, static_cast<char*>(ws));
-        if (e != hipSuccess) return hip_fail(e);
-    }
-    return TMQCD_OK;
+    const hipError_t e = apply_operator(c, op, in, out, static_cast<char*>(ws), nrhs);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
 int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const void* b, void* x,
@@ -218,6 +214,41 @@ int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const voi
     if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
     if (overlap(ws, need, b, fb) || overlap(ws, need, x, fb)) return TMQCD_EALIAS;
     return run_cg(*prob, U_packed, b, x, o, *stats, ws, (hipStream_t)stream);
+}
+
+size_t tmqcd_cg_batch_workspace_bytes(int n, const tmqcd_problem* probs) {
+    if (n < 1 || n > 8 || !probs) return 0;
+    for (int i = 0; i < n; ++i)
+        if (!valid_problem(&probs[i])) return 0;
+    return (size_t)cg_batch_workspace(n, probs);
+}
+
+int tmqcd_cg_batch(int n, const tmqcd_problem* probs, const void* const* U_packed, const void* const* b,
+                   void* const* x, const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, int use_graph, void* ws,
+                   size_t ws_bytes, void* stream) {
+    if (n < 1 || n > 8 || !probs || !U_packed || !b || !x || !opts || !stats || (use_graph != 0 && use_graph != 1))
+        return TMQCD_EINVAL;
+    const tmqcd_cg_opts& o = *opts;
+    if (o.op != TMQCD_MHATDAGMHAT || o.inner_prec != TMQCD_F64 || !valid_recon(o.recon) || o.max_iter < 1 ||
+        !(o.tol > 0.0) || !std::isfinite(o.tol) || o.check_every < 0)
+        return TMQCD_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!valid_problem(&probs[i]) || !U_packed[i] || !b[i] || !x[i]) return TMQCD_EINVAL;
+        if (!aligned(U_packed[i], kAlignBytes) || !aligned(b[i], kAlignBytes) || !aligned(x[i], kAlignBytes))
+            return TMQCD_EALIGN;
+    }
+    const int64_t need = cg_batch_workspace(n, probs);
+    if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
+    if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+    for (int i = 0; i < n; ++i) {
+        const int64_t fi = field_bytes(make_geom(probs[i]), TMQCD_F64, TMQCD_EVEN);
+        if (overlap(ws, need, x[i], fi) || overlap(ws, need, b[i], fi)) return TMQCD_EALIAS;
+        for (int j = 0; j < n; ++j) {
+            const int64_t fj = field_bytes(make_geom(probs[j]), TMQCD_F64, TMQCD_EVEN);
+            if (overlap(x[i], fi, b[j], fj) || (i != j && overlap(x[i], fi, x[j], fj))) return TMQCD_EALIAS;
+        }
+    }
+    return run_cg_batch(n, probs, U_packed, b, x, o, stats, use_graph == 1, ws, (hipStream_t)stream);
 }
 
 int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X, const void* Y,

@@ -116,6 +116,38 @@ __global__ __launch_bounds__(kBlock) void xpay_kernel(VecK v, char* p, int64_t p
     SpinorIO<PP>::store(p + half * pbytes, v.stride, h, pv);
 }
 
+constexpr int kMaxBatchVec = 8;
+struct XpayBatch {
+    int n;
+    int tile_start[kMaxBatchVec + 1];
+    VecK v[kMaxBatchVec];
+    char* p[kMaxBatchVec];
+    const char* r[kMaxBatchVec];
+    const CgState* st[kMaxBatchVec];
+    int64_t bytes;
+};
+
+// p = r + beta p for several lattices (FP64), grid-stride over their tiles
+__global__ __launch_bounds__(kBlock) void xpay_batch_kernel(const XpayBatch b) {
+    const int total = b.tile_start[b.n];
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        int i = 0;
+        while (tile >= b.tile_start[i + 1]) ++i;
+        if (b.st[i]->done) continue;
+        int half, h;
+        if (!site_of(b.v[i], (tile - b.tile_start[i]) * kBlock + threadIdx.x, half, h)) continue;
+        const double beta = b.st[i]->beta;
+        Spinor<double> pv, rv;
+        SpinorIO<TMQCD_F64>::load(pv, b.p[i] + half * b.bytes, b.v[i].stride, h);
+        SpinorIO<TMQCD_F64>::load(rv, b.r[i] + half * b.bytes, b.v[i].stride, h);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pv.s[s][c] = rv.s[s][c] + scale(beta, pv.s[s][c]);
+        SpinorIO<TMQCD_F64>::store(b.p[i] + half * b.bytes, b.v[i].stride, h, pv);
+    }
+}
+
 template <int PS>
 __global__ __launch_bounds__(kBlock) void accumulate_kernel(VecK v, char* x, int64_t xbytes, char* xs,
                                                             int64_t sbytes) {
@@ -281,6 +313,27 @@ hipError_t launch_set_state(CgState* st, const StateInit& v, hipStream_t s) {
 
 hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipStream_t s) {
     hipLaunchKernelGGL(rr_from_result_kernel, dim3(1), dim3(64), 0, s, st, slot, stop_factor);
+    return hipGetLastError();
+}
+
+hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* const* r, CgState* const* st, int n,
+                             int max_grid, hipStream_t s) {
+    if (n < 1 || n > kMaxBatchVec) return hipErrorInvalidValue;
+    XpayBatch b;
+    b.n = n;
+    b.tile_start[0] = 0;
+    b.bytes = half_field_bytes(*vs[0].g, TMQCD_F64);
+    for (int i = 0; i < n; ++i) {
+        b.v[i] = make_veck(vs[i]);
+        b.p[i] = static_cast<char*>(p[i]);
+        b.r[i] = static_cast<const char*>(r[i]);
+        b.st[i] = st[i];
+        b.tile_start[i + 1] = b.tile_start[i] + b.v[i].nblocks;
+    }
+    for (int i = 0; i < n; ++i)
+        if (vs[i].nhalf != 1) return hipErrorInvalidValue;   // even-site fields only
+    const int total = b.tile_start[n];
+    hipLaunchKernelGGL(xpay_batch_kernel, dim3(total < max_grid ? total : max_grid), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 

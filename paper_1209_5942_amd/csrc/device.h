@@ -190,6 +190,7 @@ struct LinkIO;
 template <int R>
 struct LinkIO<TMQCD_F64, R> {
     using T = double;
+    using Unit = double2;
     static constexpr int kUnits = R == TMQCD_RECON18 ? 9 : 6;
     // STREAM: nontemporal loads (the link is read once); false where links are re-read
     template <bool STREAM = true>
@@ -214,13 +215,15 @@ struct LinkIO<TMQCD_F64, R> {
 template <>
 struct LinkIO<TMQCD_F32, TMQCD_RECON18> {
     using T = float;
+    using Unit = float2;
     static constexpr int kUnits = 9;
+    template <bool STREAM = true>
     __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
                                                 int64_t h) {
         const float2* p = reinterpret_cast<const float2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const float2 w = ld_stream(p + k * gstride);
+            const float2 w = STREAM ? ld_stream(p + k * gstride) : p[k * gstride];
             u.m[k / 3][k % 3] = {w.x, w.y};
         }
     }
@@ -235,13 +238,15 @@ struct LinkIO<TMQCD_F32, TMQCD_RECON18> {
 template <>
 struct LinkIO<TMQCD_F32, TMQCD_RECON12> {
     using T = float;
+    using Unit = float4;
     static constexpr int kUnits = 3;
+    template <bool STREAM = true>
     __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
                                                 int64_t h) {
         const float4* p = reinterpret_cast<const float4*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float4 w = ld_stream(p + k * gstride);
+            const float4 w = STREAM ? ld_stream(p + k * gstride) : p[k * gstride];
             u.m[(2 * k) / 3][(2 * k) % 3] = {w.x, w.y};
             u.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {w.z, w.w};
         }
@@ -261,13 +266,15 @@ struct LinkIO<TMQCD_F32, TMQCD_RECON12> {
 template <>
 struct LinkIO<TMQCD_F16, TMQCD_RECON18> {
     using T = float;
+    using Unit = __half2;
     static constexpr int kUnits = 9;
+    template <bool STREAM = true>
     __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
                                                 int64_t h) {
         const __half2* p = reinterpret_cast<const __half2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const float2 w = __half22float2(ld_stream(p + k * gstride));
+            const float2 w = __half22float2(STREAM ? ld_stream(p + k * gstride) : p[k * gstride]);
             u.m[k / 3][k % 3] = {w.x, w.y};
         }
     }
@@ -284,18 +291,20 @@ struct LinkIO<TMQCD_F16, TMQCD_RECON18> {
 template <>
 struct LinkIO<TMQCD_F16, TMQCD_RECON12> {
     using T = float;
+    using Unit = uint2;
     static constexpr int kUnits = 3;
     union U8 {
         uint2 u;
         __half h[4];
     };
+    template <bool STREAM = true>
     __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
                                                 int64_t h) {
         const uint2* p = reinterpret_cast<const uint2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             U8 w;
-            w.u = ld_stream(p + k * gstride);
+            w.u = STREAM ? ld_stream(p + k * gstride) : p[k * gstride];
             u.m[(2 * k) / 3][(2 * k) % 3] = {__half2float(w.h[0]), __half2float(w.h[1])};
             u.m[(2 * k + 1) / 3][(2 * k + 1) % 3] = {__half2float(w.h[2]), __half2float(w.h[3])};
         }
@@ -412,6 +421,7 @@ __device__ __forceinline__ bool grid_reduce(double (&v)[N], double (&tot)[N], do
         tot[i] = s;
     }
     if (threadIdx.x == 0) atomicExch(counter, 0u);
+    __syncthreads();   // `sh` is reused if the caller reduces again (grid-stride loops)
     return true;
 }
 

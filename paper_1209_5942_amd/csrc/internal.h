@@ -46,9 +46,14 @@ struct HopParams {
     void* r;          // vector precision
     const void* p;    // dslash precision
     int vprec;        // precision of x and r
+    // several right-hand sides (epi == kEpiStore): fields nrhs apart by these byte strides
+    int nrhs;
+    int64_t in_fstride, own_fstride, out_fstride;
 };
 
 hipError_t launch_hop(const HopParams& a, hipStream_t s);
+// one launch over the same stage for n <= 8 lattices (FP64), grid-stride over their tiles
+hipError_t launch_hop_batch(const HopParams* ps, int n, int max_grid, hipStream_t s);
 int hop_blocks(const Geom& g, int nparity);   // grid size (and partial count) of a hop launch
 
 // ---- BLAS-1 over packed fields of nhalf half fields -------------------------
@@ -67,6 +72,9 @@ hipError_t launch_residual(const VecSpec& v, void* r, const void* b, const void*
 // p = r + beta p with beta = st->beta; nothing when st->done and skip_if_done
 hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st, bool skip_if_done,
                        hipStream_t s);
+// p = r + beta p for n <= 8 lattices (FP64 even fields), skipping lattices whose solve has stopped
+hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* const* r, CgState* const* st, int n,
+                             int max_grid, hipStream_t s);
 // x64 += xs (low precision), then xs = 0
 hipError_t launch_accumulate(const VecSpec& v, void* x64, void* xs, int ps, hipStream_t s);
 hipError_t launch_zero(const VecSpec& v, void* dst, int prec, hipStream_t s);

@@ -72,19 +72,27 @@ static HopParams base_params(const OpCtx& c) {
     return a;
 }
 
-hipError_t op_dslash_pq(const OpCtx& c, const void* in, void* out, int out_parity, double coef) {
+static void set_rhs(HopParams& a, const Rhs& r) {
+    a.nrhs = r.n;
+    a.in_fstride = r.in;
+    a.own_fstride = r.own;
+    a.out_fstride = r.out;
+}
+
+hipError_t op_dslash_pq(const OpCtx& c, const void* in, void* out, int out_parity, double coef, const Rhs& r = kOne) {
     HopParams a = base_params(c);
     a.in = in;
     a.out = out;
     a.out_parity = out_parity;
     a.nparity = 1;
     a.cu_hop = a.cd_hop = cx(coef, 0);
+    set_rhs(a, r);
     return launch_hop(a, c.s);
 }
 
 // full field: out = A(+-mu) in - kappa H(^+) in
 hipError_t op_full(const OpCtx& c, const void* in, void* out, bool dag, int epi, CgState* st, double* partials,
-                   void* x, void* r, const void* p) {
+                   void* x, void* r, const void* p, const Rhs& rh = kOne) {
     HopParams a = base_params(c);
     a.in = in;
     a.own = in;
@@ -99,11 +107,12 @@ hipError_t op_full(const OpCtx& c, const void* in, void* out, bool dag, int epi,
     a.x = x;
     a.r = r;
     a.p = p;
+    set_rhs(a, Rhs{rh.n, rh.in, rh.in, rh.out});
     return launch_hop(a, c.s);
 }
 
 // even sites: t_o = A(+-mu)^{-1} H(^+)_oe in_e
-hipError_t op_schur_first(const OpCtx& c, const void* in_e, void* t_o, bool dag) {
+HopParams hp_schur_first(const OpCtx& c, const void* in_e, void* t_o, bool dag, const Rhs& r) {
     HopParams a = base_params(c);
     a.in = in_e;
     a.out = t_o;
@@ -114,12 +123,16 @@ hipError_t op_schur_first(const OpCtx& c, const void* in_e, void* t_o, bool dag)
     twist(c, dag, up, dn);
     a.cu_hop = cdiv1(up);
     a.cd_hop = cdiv1(dn);
-    return launch_hop(a, c.s);
+    set_rhs(a, r);
+    return a;
+}
+hipError_t op_schur_first(const OpCtx& c, const void* in_e, void* t_o, bool dag, const Rhs& r = kOne) {
+    return launch_hop(hp_schur_first(c, in_e, t_o, dag, r), c.s);
 }
 
 // even sites: out_e = A(+-mu) own_e - kappa^2 H(^+)_eo t_o
-hipError_t op_schur_second(const OpCtx& c, const void* t_o, const void* own_e, void* out_e, bool dag, int epi,
-                           CgState* st, double* partials, void* x, void* r, const void* p) {
+HopParams hp_schur_second(const OpCtx& c, const void* t_o, const void* own_e, void* out_e, bool dag, int epi,
+                          CgState* st, double* partials, void* x, void* r, const void* p, const Rhs& rh) {
     HopParams a = base_params(c);
     a.in = t_o;
     a.own = own_e;
@@ -135,39 +148,62 @@ hipError_t op_schur_second(const OpCtx& c, const void* t_o, const void* own_e, v
     a.x = x;
     a.r = r;
     a.p = p;
-    return launch_hop(a, c.s);
+    set_rhs(a, rh);
+    return a;
+}
+hipError_t op_schur_second(const OpCtx& c, const void* t_o, const void* own_e, void* out_e, bool dag, int epi,
+                           CgState* st, double* partials, void* x, void* r, const void* p, const Rhs& rh = kOne) {
+    return launch_hop(hp_schur_second(c, t_o, own_e, out_e, dag, epi, st, partials, x, r, p, rh), c.s);
 }
 
-// out = op(in) with temporaries from tmp (op-dependent size, see dslash_tmp_bytes)
-hipError_t apply_operator(const OpCtx& c, int op, const void* in, void* out, char* tmp) {
+static int in_subset_of(int op) {
+    if (op == TMQCD_DSLASH_EO) return TMQCD_ODD;
+    if (op == TMQCD_M || op == TMQCD_MDAG || op == TMQCD_MDAGM) return TMQCD_FULL;
+    return TMQCD_EVEN;
+}
+static int out_subset_of(int op) {
+    if (op == TMQCD_DSLASH_OE) return TMQCD_ODD;
+    if (op == TMQCD_M || op == TMQCD_MDAG || op == TMQCD_MDAGM) return TMQCD_FULL;
+    return TMQCD_EVEN;
+}
+
+// out = op(in) for nrhs fields; temporaries from tmp (dslash_tmp_bytes(g, op, prec) * nrhs bytes)
+hipError_t apply_operator(const OpCtx& c, int op, const void* in, void* out, char* tmp, int nrhs) {
     const int64_t hb = half_field_bytes(c.g, c.prec);
+    const int64_t fi = field_bytes(c.g, c.prec, in_subset_of(op)), fo = field_bytes(c.g, c.prec, out_subset_of(op));
+    const Rhs io{nrhs, fi, fi, fo};
     hipError_t e = hipSuccess;
     switch (op) {
-        case TMQCD_DSLASH_EO: return op_dslash_pq(c, in, out, 0, -c.kappa);
-        case TMQCD_DSLASH_OE: return op_dslash_pq(c, in, out, 1, -c.kappa);
-        case TMQCD_M: return op_full(c, in, out, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
-        case TMQCD_MDAG: return op_full(c, in, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
-        case TMQCD_MDAGM:
-            e = op_full(c, in, tmp, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+        case TMQCD_DSLASH_EO: return op_dslash_pq(c, in, out, 0, -c.kappa, io);
+        case TMQCD_DSLASH_OE: return op_dslash_pq(c, in, out, 1, -c.kappa, io);
+        case TMQCD_M: return op_full(c, in, out, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr, io);
+        case TMQCD_MDAG: return op_full(c, in, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr, io);
+        case TMQCD_MDAGM: {
+            const Rhs first{nrhs, fi, fi, 2 * hb}, second{nrhs, 2 * hb, 2 * hb, fo};
+            e = op_full(c, in, tmp, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr, first);
             if (e != hipSuccess) return e;
-            return op_full(c, tmp, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+            return op_full(c, tmp, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr, second);
+        }
         case TMQCD_MHAT:
         case TMQCD_MHATDAG: {
             const bool dag = op == TMQCD_MHATDAG;
-            e = op_schur_first(c, in, tmp, dag);
+            e = op_schur_first(c, in, tmp, dag, Rhs{nrhs, fi, 0, hb});
             if (e != hipSuccess) return e;
-            return op_schur_second(c, tmp, in, out, dag, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+            return op_schur_second(c, tmp, in, out, dag, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   Rhs{nrhs, hb, fi, fo});
         }
         case TMQCD_MHATDAGMHAT: {
             char* t_o = tmp;
-            char* t_e = tmp + hb;
-            e = op_schur_first(c, in, t_o, false);
+            char* t_e = tmp + nrhs * hb;
+            e = op_schur_first(c, in, t_o, false, Rhs{nrhs, fi, 0, hb});
             if (e != hipSuccess) return e;
-            e = op_schur_second(c, t_o, in, t_e, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+            e = op_schur_second(c, t_o, in, t_e, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                Rhs{nrhs, hb, fi, hb});
             if (e != hipSuccess) return e;
-            e = op_schur_first(c, t_e, t_o, true);
+            e = op_schur_first(c, t_e, t_o, true, Rhs{nrhs, hb, 0, hb});
             if (e != hipSuccess) return e;
-            return op_schur_second(c, t_o, t_e, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+            return op_schur_second(c, t_o, t_e, out, true, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   Rhs{nrhs, hb, hb, fo});
         }
     }
     return hipErrorInvalidValue;
@@ -309,7 +345,9 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
     const int op = full ? TMQCD_MDAGM : TMQCD_MHATDAGMHAT;
     const int hops_per_apply = full ? 2 : 4;
     const int check = o.check_every > 0 ? o.check_every : 32;
-    const double delta = o.reliable_delta > 0 ? o.reliable_delta : 0.1;
+    // default reliable-update factor per inner precision (measured on 32^3 x 64:
+    // fewer FP64 restarts at the same iteration count and final residual)
+    const double delta = o.reliable_delta > 0 ? o.reliable_delta : (q == TMQCD_F16 ? 1e-2 : 1e-4);
     char* tmp64 = static_cast<char*>(w.t1);   // t1 (and t2 for even-odd) are contiguous
 
     // state: counters zero, iteration count, cap
@@ -323,7 +361,7 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
     // r = b - A x (FP64); |b|^2 -> result[1], |r|^2 -> result[0]
     int applies = 0;
     auto true_residual = [&]() -> hipError_t {
-        hipError_t e = apply_operator(c64, op, x, w.ax, tmp64);
+        hipError_t e = apply_operator(c64, op, x, w.ax, tmp64, 1);
         if (e != hipSuccess) return e;
         ++applies;
         return launch_residual(vs, w.r, b, w.ax, w.st, 0, w.partials, s);

@@ -20,8 +20,20 @@ struct OpCtx {
 
 OpCtx make_ctx(const tmqcd_problem& prob, int prec, int recon, const void* gauge, hipStream_t s);
 
-// out = op(in); tmp must hold dslash_tmp_bytes(g, op, prec) bytes
-hipError_t apply_operator(const OpCtx& c, int op, const void* in, void* out, char* tmp);
+// several right-hand sides: count and byte strides between consecutive fields
+struct Rhs {
+    int n;
+    int64_t in, own, out;
+};
+static const Rhs kOne = {1, 0, 0, 0};
+
+// launch parameters of the two halves of the Schur complement (see ops.cpp)
+HopParams hp_schur_first(const OpCtx& c, const void* in_e, void* t_o, bool dag, const Rhs& r);
+HopParams hp_schur_second(const OpCtx& c, const void* t_o, const void* own_e, void* out_e, bool dag, int epi,
+                          CgState* st, double* partials, void* x, void* r, const void* p, const Rhs& rh);
+
+// out = op(in) for nrhs consecutive fields; tmp must hold nrhs * dslash_tmp_bytes(g, op, prec) bytes
+hipError_t apply_operator(const OpCtx& c, int op, const void* in, void* out, char* tmp, int nrhs);
 int64_t dslash_tmp_bytes(const Geom& g, int op, int prec);
 
 struct CgWorkspace {
@@ -35,6 +47,13 @@ struct CgWorkspace {
 CgWorkspace carve_cg(const Geom& g, int op, int inner_prec, char* base);
 int64_t state_bytes();
 int64_t partial_bytes(const Geom& g);
+
+// CG on Mhat^+ Mhat for n lattices at once (FP64): every stage of an iteration
+// is one launch over all lattices; with use_graph one iteration is captured in
+// a hipGraph and replayed.  stats[n]; b, x: packed FP64 even fields.
+int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, const void* const* b, void* const* x,
+                 const tmqcd_cg_opts& o, tmqcd_cg_stats* stats, bool use_graph, void* ws, hipStream_t s);
+int64_t cg_batch_workspace(int n, const tmqcd_problem* probs);
 
 int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b, void* x, const tmqcd_cg_opts& o,
            tmqcd_cg_stats& stats, void* ws, hipStream_t s);

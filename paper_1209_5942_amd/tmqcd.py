@@ -27,7 +27,7 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
               MDAGM: (FULL, FULL), MHAT: (EVEN, EVEN), MHATDAG: (EVEN, EVEN), MHATDAGMHAT: (EVEN, EVEN)}
 
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
-                "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg", "tmqcd_force",
+                "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg", "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force",
                 "tmqcd_gauge_force", "tmqcd_update_links", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot",
                 "tmqcd_error_string", "tmqcd_last_hip_error")
 
@@ -84,6 +84,8 @@ def lib():
             "tmqcd_dslash": (I, [P, V, V, V, I, I, I, I, V, S, V]),
             "tmqcd_cg": (I, [P, ctypes.POINTER(V * 3), V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats),
                              V, S, V]),
+            "tmqcd_cg_batch_workspace_bytes": (S, [I, P]),
+            "tmqcd_cg_batch": (I, [I, P, V, V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats), I, V, S, V]),
             "tmqcd_force": (I, [P, V, I, V, V, V, D, I, V]),
             "tmqcd_gauge_force": (I, [P, V, D, V, D, I, V]),
             "tmqcd_update_links": (I, [P, V, V, D, V]),
@@ -240,6 +242,28 @@ def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, m
     if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
         raise TmqcdError(rc, "tmqcd_cg")
     return x, st.as_dict(), rc
+
+
+def cg_batch(probs, U_packed, bs, xs=None, *, tol=1e-10, max_iter=10000, recon=RECON18, use_graph=True,
+             check_every=0, ws=None, stream=None, raise_on_noconv=True):
+    """FP64 CG on Mhat^dag Mhat for several lattices in one solve (packed FP64 even fields).
+
+    Returns (xs, [stats dict per lattice], return code)."""
+    n = len(probs)
+    cp = (CProblem * n)(*[p.c() for p in probs])
+    if xs is None:
+        xs = [_bytes(spinor_bytes(p, F64, EVEN)) for p in probs]
+    if ws is None:
+        ws = _bytes(lib().tmqcd_cg_batch_workspace_bytes(n, cp))
+    arr = lambda ts: (ctypes.c_void_p * n)(*[_ptr(t) for t in ts])
+    o = CCgOpts(tol=tol, max_iter=max_iter, op=MHATDAGMHAT, inner_prec=F64, recon=recon, reliable_delta=0.0,
+                check_every=check_every, x_is_zero=1)
+    st = (CCgStats * n)()
+    rc = lib().tmqcd_cg_batch(n, cp, arr(U_packed), arr(bs), arr(xs), ctypes.byref(o), st, int(use_graph),
+                              _ptr(ws), ws.numel(), _stream(stream))
+    if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
+        raise TmqcdError(rc, "tmqcd_cg_batch")
+    return xs, [s.as_dict() for s in st], rc
 
 
 def _mom(prob: Problem, out, like):

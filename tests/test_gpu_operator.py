@@ -62,14 +62,35 @@ def test_operator_matches_oracle(fields, op, prec, recon):
     assert rel(got, want) < tol, (op, prec, recon, rel(got, want))
 
 
-def test_multi_rhs_equals_single(fields):
+@pytest.mark.parametrize("op", [T.DSLASH_OE, T.M, T.MDAG, T.MHATDAGMHAT])
+def test_multi_rhs_columns_equal_single_calls(fields, op):
     f = fields
-    psi = synth.gaussian_spinor(f.prob.volume, 31, 3)
-    inp = T.pack_spinor(f.prob, dev(psi), T.F64, T.FULL, nrhs=3)
-    out = host(T.unpack_spinor(f.prob, T.dslash(f.prob, f.gauge(T.F64, 0), inp, T.M, nrhs=3), T.F64, T.FULL, 3))
-    for k in range(3):
-        single = T.dslash(f.prob, f.gauge(T.F64, 0), T.pack_spinor(f.prob, dev(psi[k]), T.F64, T.FULL), T.M)
-        assert np.array_equal(host(T.unpack_spinor(f.prob, single, T.F64, T.FULL)), out[k])
+    sub_in, sub_out = T.OP_SUBSETS[op]
+    psi = f.spinor(sub_in, 31, nrhs=5)
+    inp = T.pack_spinor(f.prob, dev(psi), T.F64, sub_in, nrhs=5)
+    out = host(T.unpack_spinor(f.prob, T.dslash(f.prob, f.gauge(T.F64, 0), inp, op, nrhs=5), T.F64, sub_out, 5))
+    for k in range(5):
+        single = T.dslash(f.prob, f.gauge(T.F64, 0), T.pack_spinor(f.prob, dev(psi[k]), T.F64, sub_in), op)
+        one = host(T.unpack_spinor(f.prob, single, T.F64, sub_out))
+        assert rel(out[k], one) < 1e-14
+
+
+@pytest.mark.parametrize("op", ALL_OPS)
+@pytest.mark.parametrize("prec,recon", [(T.F64, T.RECON18), (T.F64, T.RECON12), (T.F32, T.RECON12),
+                                        (T.F16, T.RECON18)])
+def test_multi_rhs_point_sources_match_oracle(fields, op, prec, recon):
+    """The 12 spin-colour point sources at site 0 (plus a Gaussian column) through every operator."""
+    f = fields
+    sub_in, sub_out = T.OP_SUBSETS[op]
+    n = n_sites(f.prob, sub_in)
+    src = np.concatenate([synth.point_sources(n, 0), f.spinor(sub_in, 41, nrhs=1)], axis=0)   # 13 columns
+    inp = T.pack_spinor(f.prob, dev(src), prec, sub_in, nrhs=13)
+    out = host(T.unpack_spinor(f.prob, T.dslash(f.prob, f.gauge(prec, recon), inp, op, prec, recon, nrhs=13),
+                               prec, sub_out, 13))
+    tol = TOL[prec] * (4 if op in (T.MDAGM, T.MHATDAGMHAT) else 1)
+    for k in range(13):
+        want = oracle_op(op, f.U, src[k], f.dims, f.kappa, f.mu, f.bc)
+        assert rel(out[k], want) < tol, (k, rel(out[k], want))
 
 
 def test_dense_columns_2x2x2x2():
