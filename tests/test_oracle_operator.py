@@ -21,6 +21,17 @@ from oracle import dirac as D
 from paper_1209_5942_amd import synth
 
 BC_AP = (1, 1, 1, -1)
+
+# The documented chiral basis, written out entry by entry (independent of the oracle's
+# construction from Pauli matrices): gamma_x, gamma_y, gamma_z, gamma_t and gamma5.
+_i = 1j
+GAMMA_REF = np.array([
+    [[0, 0, 0, -_i], [0, 0, -_i, 0], [0, _i, 0, 0], [_i, 0, 0, 0]],
+    [[0, 0, 0, -1], [0, 0, 1, 0], [0, 1, 0, 0], [-1, 0, 0, 0]],
+    [[0, 0, -_i, 0], [0, 0, 0, _i], [_i, 0, 0, 0], [0, -_i, 0, 0]],
+    [[0, 0, -1, 0], [0, 0, 0, -1], [-1, 0, 0, 0], [0, -1, 0, 0]],
+], dtype=np.complex128)
+GAMMA5_REF = np.diag([-1, -1, 1, 1]).astype(np.complex128)
 BC_TWIST = (np.exp(0.3j), np.exp(0.7j), -1.0, np.exp(1.1j))
 
 
@@ -85,7 +96,7 @@ def _block_matrix(U, dims, kappa, mu, bc, sparse=False):
         cols.append(12 * j + c)
         vals.append(blk.reshape(-1))
 
-    a = np.kron(np.eye(4) + 2j * kappa * mu * D.GAMMA5, np.eye(3))
+    a = np.kron(np.eye(4) + 2j * kappa * mu * GAMMA5_REF, np.eye(3))
     for s in range(v):
         add(s, s, a)
         c = [s % lx, (s // lx) % ly, (s // (lx * ly)) % lz, s // (lx * ly * lz)]
@@ -94,14 +105,15 @@ def _block_matrix(U, dims, kappa, mu, bc, sparse=False):
             cf[m] = (c[m] + 1) % ext[m]
             y = cf[0] + lx * (cf[1] + ly * (cf[2] + lz * cf[3]))
             b = complex(bc[m]) if c[m] == ext[m] - 1 else 1.0
-            add(s, y, -kappa * b * np.kron(np.eye(4) - D.GAMMA[m], U[s, m]))
-            add(y, s, -kappa * np.conj(b) * np.kron(np.eye(4) + D.GAMMA[m], U[s, m].conj().T))
+            add(s, y, -kappa * b * np.kron(np.eye(4) - GAMMA_REF[m], U[s, m]))
+            add(y, s, -kappa * np.conj(b) * np.kron(np.eye(4) + GAMMA_REF[m], U[s, m].conj().T))
     mat = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                         shape=(12 * v, 12 * v)).tocsr()   # duplicates are summed
     return mat if sparse else mat.toarray()
 
 
 def test_gamma_basis():
+    np.testing.assert_array_equal(D.GAMMA, GAMMA_REF)
     for m in range(4):
         assert np.allclose(D.GAMMA[m], D.GAMMA[m].conj().T)
         for n in range(4):
