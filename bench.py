@@ -106,6 +106,12 @@ def main():
         kernel_only(T, prob, gauges, b, dev)
         return
 
+    # launch shapes of the hop kernels chosen by the autotuner on this problem
+    tuning = {f"class{r['kernel_class']}": {"block": r["block"], "xcd_remap": r["swizzle"], "us": round(r["us"], 2),
+                                          "default_us": round(r["default_us"], 2)}
+              for r in T.tune(prob, gauges[(0, 0)], T.F64, T.RECON18)}
+    log(f"tuned: {tuning}")
+
     def step():
         _, st, _ = T.cg(prob, {T.F64: gauges[(0, 0)]}, b_dev, x_dev, x_is_zero=True, tol=1e-10, max_iter=5000,
                         op=T.MHATDAGMHAT, ws=ws, check_every=16)
@@ -185,11 +191,13 @@ def main():
                                 "hop_launches_per_solve": st0["hop_launches"]},
         "roofline": {"bound": "hbm", "achieved": round(gbs_hop, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(gbs_hop / PEAK_HBM_GBPS, 4), "traffic": traffic_from_profile(vh),
-                     "kernel": "hop_kernel<F64,RECON18,dag=0,own=0,store> (DSLASH_OE / first Schur hop)",
+                     "kernel": f"hop_kernel<F64,RECON18,dag=0,own=0,store> block {tuning['class0']['block']} "
+                               "(DSLASH_OE / first Schur hop)",
                      "bytes_per_launch": vh * BYTES_PER_SITE[(0, 0)], "us_per_launch": round(t_hop * 1e6, 2),
                      "gflops": round(gflops_hop, 1), "measured_copy_peak_GB_s": round(copy_gbs, 1),
                      "frac_of_measured_copy": round(gbs_hop / copy_gbs, 4)},
         "dslash_sweep_24x24x24x48": sweep,
+        "tuning_f64_rec18": tuning,
         "context": {"paper_hd5870_dslash_dp_gflops": 60, "paper_hmc_speedup_vs_server_cpu": 4},
     }
 

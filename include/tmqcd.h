@@ -228,6 +228,37 @@ int tmqcd_momentum_norm2(const tmqcd_problem* prob, const double* p, double* res
 int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subset, double* result,
               void* ws, size_t ws_bytes, void* stream);
 
+/* ---- autotuning --------------------------------------------------------------- */
+/* Times every launch shape (128 or 256 threads per block, with or without the
+ * per-XCD block remap) of the three hop classes - 0: hop (+ twisted-mass own
+ * term), 1: hop + |out|^2 (CG), 2: hop + CG update - on this problem, precision
+ * and link compression (U_packed packed accordingly), admits only shapes whose
+ * output is bitwise identical to the default shape's, and records the fastest
+ * in a process-wide table keyed by (GPU architecture, class, prec, recon,
+ * extents) that later tmqcd_dslash / tmqcd_cg / tmqcd_cg_batch calls on the
+ * same key use (multi-RHS launches keep their own shape).  ws: at least
+ * tmqcd_tune_workspace_bytes(prob, prec) bytes.  Synchronises the stream.
+ * The paper tuned its kernels per GPU in the same spirit (memory stride,
+ * lattice extents compiled in). */
+typedef struct {
+    int32_t kernel_class;  /* 0, 1, 2 as above */
+    int32_t block;         /* chosen threads per block */
+    int32_t swizzle;       /* chosen XCD remap (1) or plain block order (0) */
+    int32_t candidates;    /* shapes tried */
+    int32_t rejected;      /* shapes whose output differed from the default's */
+    double  us;            /* time per launch of the chosen shape */
+    double  default_us;    /* time per launch of the default shape (256 threads, remap) */
+} tmqcd_tune_result;
+size_t tmqcd_tune_workspace_bytes(const tmqcd_problem* prob, int prec);
+int tmqcd_tune(const tmqcd_problem* prob, const void* U_packed, int prec, int recon, void* ws,
+               size_t ws_bytes, tmqcd_tune_result results[3], void* stream);
+/* The table as JSON lines (one object per key).  Loading replaces the table and
+ * fails with TMQCD_EINVAL on a malformed file or one tuned on another
+ * architecture. */
+int tmqcd_tune_save(const char* path);
+int tmqcd_tune_load(const char* path);
+void tmqcd_tune_clear(void);
+
 /* ---- diagnostics ------------------------------------------------------------- */
 const char* tmqcd_error_string(int code);
 int tmqcd_last_hip_error(void);   /* hipError_t of the last failed HIP call in this thread */

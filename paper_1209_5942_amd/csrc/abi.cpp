@@ -338,6 +338,27 @@ int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subse
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
+size_t tmqcd_tune_workspace_bytes(const tmqcd_problem* prob, int prec) {
+    if (!valid_problem(prob) || !valid_prec(prec)) return 0;
+    return (size_t)tune_workspace_bytes(make_geom(*prob), prec);
+}
+
+int tmqcd_tune(const tmqcd_problem* prob, const void* U_packed, int prec, int recon, void* ws, size_t ws_bytes,
+               tmqcd_tune_result results[3], void* stream) {
+    if (!valid_problem(prob) || !valid_prec(prec) || !valid_recon(recon) || !U_packed || !results) return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int64_t need = tune_workspace_bytes(g, prec);
+    if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
+    if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+    if (overlap(ws, need, U_packed, gauge_bytes(g, prec, recon))) return TMQCD_EALIAS;
+    return run_tune(*prob, U_packed, prec, recon, ws, (hipStream_t)stream, results);
+}
+
+int tmqcd_tune_save(const char* path) { return path ? tune_save(path) : TMQCD_EINVAL; }
+int tmqcd_tune_load(const char* path) { return path ? tune_load(path) : TMQCD_EINVAL; }
+void tmqcd_tune_clear(void) { tune_clear(); }
+
 const char* tmqcd_error_string(int code) {
     switch (code) {
         case TMQCD_OK: return "success";

@@ -180,6 +180,35 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(VecK v, char* dst, int64_t
     SpinorIO<P>::store(dst + half * bytes, v.stride, h, a);
 }
 
+// deterministic, site-dependent test values in [-1, 1) (for tuning runs)
+template <int P>
+__global__ __launch_bounds__(kBlock) void fill_kernel(VecK v, char* dst, int64_t bytes, unsigned seed) {
+    int half, h;
+    if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
+    Spinor<typename Prec<P>::T> a;
+    unsigned x = (unsigned)(half * v.vh + h) * 2654435761u ^ seed;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x = x * 1664525u + 1013904223u;
+            const float re = (float)(x >> 8) * (1.0f / 8388608.0f) - 1.0f;
+            x = x * 1664525u + 1013904223u;
+            const float im = (float)(x >> 8) * (1.0f / 8388608.0f) - 1.0f;
+            a.s[s][c] = {re, im};
+        }
+    SpinorIO<P>::store(dst + half * bytes, v.stride, h, a);
+}
+
+// number of 8-byte words that differ between two buffers
+__global__ __launch_bounds__(kBlock) void compare_kernel(const unsigned long long* a, const unsigned long long* b,
+                                                         int64_t n, unsigned long long* mismatches) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        c += a[i] != b[i];
+    if (c) atomicAdd(mismatches, c);
+}
+
 __global__ void set_state_kernel(CgState* st, StateInit v) {
     if (threadIdx.x != 0) return;
     if (v.set_rr) st->rr = v.rr;
@@ -334,6 +363,27 @@ hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* cons
         if (vs[i].nhalf != 1) return hipErrorInvalidValue;   // even-site fields only
     const int total = b.tile_start[n];
     hipLaunchKernelGGL(xpay_batch_kernel, dim3(total < max_grid ? total : max_grid), dim3(kBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+namespace {
+template <int P>
+struct FillRun {
+    static hipError_t run(const VecK k, char* dst, int64_t bytes, unsigned seed, hipStream_t s) {
+        hipLaunchKernelGGL((fill_kernel<P>), dim3(k.nblocks), dim3(kBlock), 0, s, k, dst, bytes, seed);
+        return hipGetLastError();
+    }
+};
+}  // namespace
+
+hipError_t launch_fill(const VecSpec& v, void* dst, int prec, unsigned seed, hipStream_t s) {
+    return by_prec<FillRun>(prec, make_veck(v), static_cast<char*>(dst), half_field_bytes(*v.g, prec), seed, s);
+}
+
+hipError_t launch_compare(const void* a, const void* b, int64_t bytes, unsigned long long* mismatches, hipStream_t s) {
+    const int64_t n = bytes / 8;
+    hipLaunchKernelGGL(compare_kernel, dim3(1024), dim3(kBlock), 0, s, static_cast<const unsigned long long*>(a),
+                       static_cast<const unsigned long long*>(b), n, mismatches);
     return hipGetLastError();
 }
 

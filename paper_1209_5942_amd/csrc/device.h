@@ -340,6 +340,7 @@ __device__ __forceinline__ int xcd_swizzle(int bid, int nblocks) {
 // ------------------------------------------------------------ reductions ---
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kMinBlock = 128;   // smallest block of a tunable hop launch (sizes the partial sums)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -373,9 +374,10 @@ __device__ __forceinline__ double coherent_load(const double* p) {
 // sums them in the fixed order of block index and returns true, with the
 // totals in `tot` for every thread of that block.  The counter is reset for
 // the next use by the block that consumed it.
-template <int N>
+template <int N, int BS = kBlock>
 __device__ __forceinline__ bool grid_reduce(double (&v)[N], double (&tot)[N], double* partials,
                                             unsigned* counter, int bid, int nblocks) {
+    constexpr int kWaves = BS / 64;
     __shared__ double sh[N][kWaves];
     __shared__ int last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -403,7 +405,7 @@ __device__ __forceinline__ bool grid_reduce(double (&v)[N], double (&tot)[N], do
     double acc[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[i] = 0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock)
+    for (int b = threadIdx.x; b < nblocks; b += BS)
 #pragma unroll
         for (int i = 0; i < N; ++i) acc[i] += coherent_load(&partials[(int64_t)b * N + i]);
     __syncthreads();

@@ -65,7 +65,7 @@ struct HopK {
     double* partials;
     int64_t stride, gstride, hbytes, vhbytes;
     int L[4];
-    int lxh, vh, nb_half, nblocks, out_parity, nparity;
+    int lxh, vh, nb_half, nblocks, out_parity, nparity, swizzle;
     C<double> bc[4];
     C<double> cu_own, cd_own, cu_hop, cd_hop;
 };
@@ -253,12 +253,12 @@ __device__ __forceinline__ double hop_site(const HopK& a, int par, int h) {
 
 // Grid reduction of the epilogue's per-site values and the solver-scalar
 // update by the last tile to finish (tile: this block's logical index).
-template <int EPI>
+template <int EPI, int BS = kBlock>
 __device__ __forceinline__ void hop_reduce(const HopK& a, double red, int tile, int ntiles) {
     if constexpr (EPI != kEpiStore) {
         double v[1] = {red}, tot[1];
         const int slot = EPI == kEpiStoreNorm ? 0 : 1;
-        if (grid_reduce<1>(v, tot, a.partials, &a.st->counter[slot], tile, ntiles) && threadIdx.x == 0) {
+        if (grid_reduce<1, BS>(v, tot, a.partials, &a.st->counter[slot], tile, ntiles) && threadIdx.x == 0) {
             CgState* st = a.st;
             if constexpr (EPI == kEpiStoreNorm) {
                 const double pap = tot[0];
@@ -281,22 +281,24 @@ __device__ __forceinline__ void hop_reduce(const HopK& a, double red, int tile, 
     }
 }
 
-template <int P, int R, bool DAG, bool OWN, int EPI, int PV>
-__global__ __launch_bounds__(kBlock) void hop_kernel(const HopK a) {
+// BS threads per block (a tuning choice); with a.swizzle the block index is
+// remapped so that each XCD works on a contiguous range of sites.
+template <int P, int R, bool DAG, bool OWN, int EPI, int PV, int BS>
+__global__ __launch_bounds__(BS) void hop_kernel(const HopK a) {
     static_assert(std::is_same<typename Prec<P>::T, typename Prec<PV>::T>::value,
                   "vector and dslash compute types differ");
     if constexpr (EPI != kEpiStore) {
         if (a.st->done) return;
     }
-    const int bid = xcd_swizzle(blockIdx.x, a.nblocks);
+    const int bid = a.swizzle ? xcd_swizzle(blockIdx.x, a.nblocks) : (int)blockIdx.x;
     int par = a.out_parity, lb = bid;
     if (a.nparity == 2) {
         par = bid >= a.nb_half ? 1 : 0;
         lb = bid - par * a.nb_half;
     }
-    const int h = lb * kBlock + threadIdx.x;
+    const int h = lb * BS + threadIdx.x;
     const double red = h < a.vh ? hop_site<P, R, DAG, OWN, EPI, PV>(a, par, h) : 0.0;
-    hop_reduce<EPI>(a, red, bid, a.nblocks);
+    hop_reduce<EPI, BS>(a, red, bid, a.nblocks);
 }
 
 // Several lattices in one launch: a grid-stride loop over the tiles of all
@@ -444,9 +446,12 @@ hipError_t launch_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
 }
 
 template <int P, int R, bool DAG, bool OWN, int EPI>
-hipError_t launch_inst(const HopK& k, hipStream_t s) {
+hipError_t launch_inst(const HopK& k, int block, hipStream_t s) {
     constexpr int PV = P == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
-    hipLaunchKernelGGL((hop_kernel<P, R, DAG, OWN, EPI, PV>), dim3(k.nblocks), dim3(kBlock), 0, s, k);
+    if (block == 128)
+        hipLaunchKernelGGL((hop_kernel<P, R, DAG, OWN, EPI, PV, 128>), dim3(k.nblocks), dim3(128), 0, s, k);
+    else
+        hipLaunchKernelGGL((hop_kernel<P, R, DAG, OWN, EPI, PV, 256>), dim3(k.nblocks), dim3(256), 0, s, k);
     return hipGetLastError();
 }
 
@@ -456,15 +461,15 @@ hipError_t dispatch_variant(const HopParams& a, const HopK& k, hipStream_t s) {
     const bool own = a.own != nullptr;
     switch (a.epi) {
         case kEpiStore:
-            if (!a.dag && !own) return launch_inst<P, R, false, false, kEpiStore>(k, s);
-            if (a.dag && !own) return launch_inst<P, R, true, false, kEpiStore>(k, s);
-            if (!a.dag && own) return launch_inst<P, R, false, true, kEpiStore>(k, s);
-            return launch_inst<P, R, true, true, kEpiStore>(k, s);
+            if (!a.dag && !own) return launch_inst<P, R, false, false, kEpiStore>(k, a.block, s);
+            if (a.dag && !own) return launch_inst<P, R, true, false, kEpiStore>(k, a.block, s);
+            if (!a.dag && own) return launch_inst<P, R, false, true, kEpiStore>(k, a.block, s);
+            return launch_inst<P, R, true, true, kEpiStore>(k, a.block, s);
         case kEpiStoreNorm:
-            if (!a.dag && own) return launch_inst<P, R, false, true, kEpiStoreNorm>(k, s);
+            if (!a.dag && own) return launch_inst<P, R, false, true, kEpiStoreNorm>(k, a.block, s);
             break;
         case kEpiCgUpdate:
-            if (a.dag && own) return launch_inst<P, R, true, true, kEpiCgUpdate>(k, s);
+            if (a.dag && own) return launch_inst<P, R, true, true, kEpiCgUpdate>(k, a.block, s);
             break;
     }
     return hipErrorInvalidValue;
@@ -472,7 +477,7 @@ hipError_t dispatch_variant(const HopParams& a, const HopK& k, hipStream_t s) {
 
 }  // namespace
 
-int hop_blocks(const Geom& g, int nparity) { return nparity * (int)((g.vh + kBlock - 1) / kBlock); }
+int hop_blocks(const Geom& g, int nparity) { return nparity * (int)((g.vh + kMinBlock - 1) / kMinBlock); }
 
 static HopK make_hopk(const HopParams& a) {
     HopK k;
@@ -495,8 +500,10 @@ static HopK make_hopk(const HopParams& a) {
     }
     k.lxh = a.g.lxh;
     k.vh = (int)a.g.vh;
-    k.nb_half = (int)((a.g.vh + kBlock - 1) / kBlock);
-    k.nblocks = hop_blocks(a.g, a.nparity);
+    const int bs = a.block == 128 ? 128 : 256;
+    k.nb_half = (int)((a.g.vh + bs - 1) / bs);
+    k.nblocks = a.nparity * k.nb_half;
+    k.swizzle = a.swizzle;
     k.out_parity = a.out_parity;
     k.nparity = a.nparity;
     k.cu_own = {a.cu_own.re, a.cu_own.im};
@@ -506,7 +513,18 @@ static HopK make_hopk(const HopParams& a) {
     return k;
 }
 
-hipError_t launch_hop(const HopParams& a, hipStream_t s) {
+hipError_t launch_hop(const HopParams& a_in, hipStream_t s) {
+    HopParams a = a_in;
+    if (a.block == 0) {   // not chosen by the caller: the tuned choice, else 256 threads with the XCD remap
+        TuneChoice t;
+        if (a.nrhs <= 1 && tune_lookup(a, &t)) {
+            a.block = t.block;
+            a.swizzle = t.swizzle;
+        } else {
+            a.block = 256;
+            a.swizzle = 1;
+        }
+    }
     const HopK k = make_hopk(a);
     const int want_vprec = a.prec == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
     if (a.epi == kEpiCgUpdate && a.vprec != want_vprec) return hipErrorInvalidValue;
@@ -550,7 +568,9 @@ hipError_t launch_hop_batch(const HopParams* ps, int n, int max_grid, hipStream_
         if (a.prec != TMQCD_F64 || a.vprec != TMQCD_F64 || a.nrhs > 1 || a.recon != ps[0].recon ||
             a.dag != ps[0].dag || (a.own != nullptr) != (ps[0].own != nullptr) || a.epi != ps[0].epi)
             return hipErrorInvalidValue;
-        b.lat[i] = make_hopk(a);
+        HopParams a256 = a;
+        a256.block = 256;
+        b.lat[i] = make_hopk(a256);
         b.tile_start[i + 1] = b.tile_start[i] + b.lat[i].nblocks;
     }
     const int total = b.tile_start[n];

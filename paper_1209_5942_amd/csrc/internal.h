@@ -49,7 +49,19 @@ struct HopParams {
     // several right-hand sides (epi == kEpiStore): fields nrhs apart by these byte strides
     int nrhs;
     int64_t in_fstride, own_fstride, out_fstride;
+    // launch shape: block 128 or 256 threads and the XCD remap; block = 0 takes the tuned choice
+    int block;
+    int swizzle;
 };
+
+// ---- autotuning (tune.cpp) ------------------------------------------------------
+struct TuneChoice {
+    int block;
+    int swizzle;
+    double us;
+};
+// the tuned launch shape for this hop (class from epi and own; single right-hand side)
+bool tune_lookup(const HopParams& a, TuneChoice* out);
 
 hipError_t launch_hop(const HopParams& a, hipStream_t s);
 // one launch over the same stage for n <= 8 lattices (FP64), grid-stride over their tiles
@@ -78,6 +90,9 @@ hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* cons
 // x64 += xs (low precision), then xs = 0
 hipError_t launch_accumulate(const VecSpec& v, void* x64, void* xs, int ps, hipStream_t s);
 hipError_t launch_zero(const VecSpec& v, void* dst, int prec, hipStream_t s);
+// deterministic test values; count of differing 8-byte words (added to *mismatches)
+hipError_t launch_fill(const VecSpec& v, void* dst, int prec, unsigned seed, hipStream_t s);
+hipError_t launch_compare(const void* a, const void* b, int64_t bytes, unsigned long long* mismatches, hipStream_t s);
 
 // ---- solver state --------------------------------------------------------------
 struct StateInit {

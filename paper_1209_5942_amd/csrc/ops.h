@@ -55,6 +55,14 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
                  const tmqcd_cg_opts& o, tmqcd_cg_stats* stats, bool use_graph, void* ws, hipStream_t s);
 int64_t cg_batch_workspace(int n, const tmqcd_problem* probs);
 
+// autotuning (tune.cpp)
+int64_t tune_workspace_bytes(const Geom& g, int prec);
+int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, void* ws, hipStream_t s,
+             tmqcd_tune_result results[3]);
+int tune_save(const char* path);
+int tune_load(const char* path);
+void tune_clear();
+
 int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b, void* x, const tmqcd_cg_opts& o,
            tmqcd_cg_stats& stats, void* ws, hipStream_t s);
 

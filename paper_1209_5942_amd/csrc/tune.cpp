@@ -1,0 +1,285 @@
+// Autotuner for the hop launches.  The paper tuned its memory stride per GPU and
+// compiled lattice extents into the kernels (its implementation-strategy
+// section); here the launch shape of every hop class - 128 or 256 threads per
+// block, with or without the per-XCD block remap - is chosen by timing on the
+// caller's problem.  A variant may be chosen only if its output is bitwise
+// identical to the default variant's (and its reduction equal within 1e-12):
+// the paper found compilers to miscompile large kernels, so every variant is
+// re-verified on the device it will run on.
+//
+// The choices live in a process-wide table keyed by (architecture, kernel
+// class, storage precision, link compression, lattice extents), guarded by a
+// mutex, and can be saved to / loaded from a JSON-lines file.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "device.h"
+#include "internal.h"
+#include "ops.h"
+
+namespace tmqcd {
+namespace {
+
+using Key = std::tuple<std::string, int, int, int, int, int, int, int>;   // arch, class, prec, recon, L[4]
+
+std::mutex g_mu;
+std::map<Key, TuneChoice> g_table;
+std::string g_arch;   // architecture of the device the table was filled on
+
+int class_of(int epi) { return epi == kEpiStoreNorm ? 1 : (epi == kEpiCgUpdate ? 2 : 0); }
+
+std::string current_arch() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a(p.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+Key key_of(const std::string& arch, int cls, int prec, int recon, const int L[4]) {
+    return Key(arch, cls, prec, recon, L[0], L[1], L[2], L[3]);
+}
+
+}  // namespace
+
+bool tune_lookup(const HopParams& a, TuneChoice* out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_table.empty()) return false;
+    const auto it = g_table.find(key_of(g_arch, class_of(a.epi), a.prec, a.recon, a.g.L));
+    if (it == g_table.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+namespace {
+
+struct TuneWs {
+    CgState* st;
+    double* partials;
+    unsigned long long* mism;
+    char *in_e, *t_o, *out_e, *ref;   // dslash precision
+    char *x, *r, *x0, *r0, *refx, *refr;   // vector precision
+    int64_t total;
+};
+
+TuneWs carve_tune(const Geom& g, int prec, char* base) {
+    TuneWs w;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        char* q = base ? base + off : nullptr;
+        off += round_up(bytes, kAlignBytes);
+        return q;
+    };
+    const int pv = prec == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
+    const int64_t hd = half_field_bytes(g, prec), hv = half_field_bytes(g, pv);
+    w.st = reinterpret_cast<CgState*>(take(sizeof(CgState)));
+    w.partials = reinterpret_cast<double*>(take(partial_bytes(g)));
+    w.mism = reinterpret_cast<unsigned long long*>(take(64));
+    w.in_e = take(hd);
+    w.t_o = take(hd);
+    w.out_e = take(hd);
+    w.ref = take(hd);
+    w.x = take(hv);
+    w.r = take(hv);
+    w.x0 = take(hv);
+    w.r0 = take(hv);
+    w.refx = take(hv);
+    w.refr = take(hv);
+    w.total = off;
+    return w;
+}
+
+}  // namespace
+
+int64_t tune_workspace_bytes(const Geom& g, int prec) { return carve_tune(g, prec, nullptr).total; }
+
+#define TRY(expr)                       \
+    do {                                \
+        hipError_t e_ = (expr);         \
+        if (e_ != hipSuccess) {         \
+            g_last_hip_error = (int)e_; \
+            rc = TMQCD_EHIP;            \
+            goto done;                  \
+        }                               \
+    } while (0)
+
+int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, void* ws, hipStream_t s,
+             tmqcd_tune_result results[3]) {
+    int rc = TMQCD_OK;
+    const Geom g = make_geom(prob);
+    const int pv = prec == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
+    const TuneWs w = carve_tune(g, prec, static_cast<char*>(ws));
+    const OpCtx c = make_ctx(prob, prec, recon, gauge, s);
+    const VecSpec vs{&g, 1};
+    const int64_t hd = half_field_bytes(g, prec), hv = half_field_bytes(g, pv);
+    const int shapes[4][2] = {{256, 1}, {256, 0}, {128, 1}, {128, 0}};   // first: the default, the reference
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const std::string arch = current_arch();
+    TRY(hipEventCreate(&e0));
+    TRY(hipEventCreate(&e1));
+    TRY(launch_fill(vs, w.in_e, prec, 11u, s));
+    TRY(launch_fill(vs, w.t_o, prec, 12u, s));
+    TRY(launch_fill(vs, w.x0, pv, 13u, s));
+    TRY(launch_fill(vs, w.r0, pv, 14u, s));
+    for (int cls = 0; cls < 3; ++cls) {
+        tmqcd_tune_result& res = results[cls];
+        std::memset(&res, 0, sizeof(res));
+        res.kernel_class = cls;
+        double ref_scalar = 0;
+        double best = 1e30;
+        for (int v = 0; v < 4; ++v) {
+            HopParams a;
+            if (cls == 0) a = hp_schur_first(c, w.in_e, w.t_o, false, kOne);
+            else if (cls == 1)
+                a = hp_schur_second(c, w.t_o, w.in_e, w.out_e, false, kEpiStoreNorm, w.st, w.partials, nullptr,
+                                    nullptr, nullptr, kOne);
+            else
+                a = hp_schur_second(c, w.t_o, w.in_e, nullptr, true, kEpiCgUpdate, w.st, w.partials, w.x, w.r,
+                                    w.in_e, kOne);
+            a.block = shapes[v][0];
+            a.swizzle = shapes[v][1];
+            // one verified run from a fixed state
+            StateInit si;
+            std::memset(&si, 0, sizeof(si));
+            si.set_rr = si.set_alpha = si.set_stop = si.set_iter = si.set_max_iter = si.set_cycle_end =
+                si.set_done = si.reset_counters = true;
+            si.rr = 1.0;
+            si.alpha = 0.37;
+            si.stop_rr = 0.0;
+            si.max_iter = si.cycle_end = 1 << 30;
+            si.done = kDoneRunning;
+            TRY(launch_set_state(w.st, si, s));
+            if (cls == 2) {
+                TRY(hipMemcpyAsync(w.x, w.x0, hv, hipMemcpyDeviceToDevice, s));
+                TRY(hipMemcpyAsync(w.r, w.r0, hv, hipMemcpyDeviceToDevice, s));
+            }
+            TRY(launch_hop(a, s));
+            CgState h;
+            TRY(hipMemcpyAsync(&h, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            TRY(hipStreamSynchronize(s));
+            const double scalar = cls == 1 ? h.pAp : (cls == 2 ? h.rr : 0.0);
+            bool ok = true;
+            if (v == 0) {
+                ref_scalar = scalar;
+                if (cls == 0) TRY(hipMemcpyAsync(w.ref, w.t_o, hd, hipMemcpyDeviceToDevice, s));
+                if (cls == 1) TRY(hipMemcpyAsync(w.ref, w.out_e, hd, hipMemcpyDeviceToDevice, s));
+                if (cls == 2) {
+                    TRY(hipMemcpyAsync(w.refx, w.x, hv, hipMemcpyDeviceToDevice, s));
+                    TRY(hipMemcpyAsync(w.refr, w.r, hv, hipMemcpyDeviceToDevice, s));
+                }
+            } else {
+                unsigned long long mism = 0;
+                TRY(hipMemsetAsync(w.mism, 0, 8, s));
+                if (cls == 0) TRY(launch_compare(w.ref, w.t_o, hd, w.mism, s));
+                if (cls == 1) TRY(launch_compare(w.ref, w.out_e, hd, w.mism, s));
+                if (cls == 2) {
+                    TRY(launch_compare(w.refx, w.x, hv, w.mism, s));
+                    TRY(launch_compare(w.refr, w.r, hv, w.mism, s));
+                }
+                TRY(hipMemcpyAsync(&mism, w.mism, 8, hipMemcpyDeviceToHost, s));
+                TRY(hipStreamSynchronize(s));
+                ok = mism == 0 && std::fabs(scalar - ref_scalar) <= 1e-12 * std::fabs(ref_scalar);
+            }
+            ++res.candidates;
+            if (!ok) {
+                ++res.rejected;
+                continue;
+            }
+            // time 20 launches (the state never flags done: stop_rr = 0, caps at 2^30)
+            constexpr int kReps = 20;
+            TRY(launch_hop(a, s));
+            TRY(hipEventRecord(e0, s));
+            for (int k = 0; k < kReps; ++k) TRY(launch_hop(a, s));
+            TRY(hipEventRecord(e1, s));
+            TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            TRY(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / kReps;
+            if (v == 0) res.default_us = us;
+            if (us < best) {
+                best = us;
+                res.block = a.block;
+                res.swizzle = a.swizzle;
+                res.us = us;
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            if (g_arch != arch) {
+                g_table.clear();
+                g_arch = arch;
+            }
+            g_table[key_of(arch, cls, prec, recon, g.L)] = TuneChoice{res.block, res.swizzle, res.us};
+        }
+    }
+    TRY(hipStreamSynchronize(s));
+done:
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    return rc;
+}
+
+#undef TRY
+
+int tune_save(const char* path) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return TMQCD_EINVAL;
+    for (const auto& kv : g_table) {
+        const Key& k = kv.first;
+        std::fprintf(f,
+                     "{\"arch\": \"%s\", \"class\": %d, \"prec\": %d, \"recon\": %d, \"dims\": [%d, %d, %d, %d], "
+                     "\"block\": %d, \"swizzle\": %d, \"us\": %.3f}\n",
+                     std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                     std::get<5>(k), std::get<6>(k), std::get<7>(k), kv.second.block, kv.second.swizzle,
+                     kv.second.us);
+    }
+    std::fclose(f);
+    return TMQCD_OK;
+}
+
+int tune_load(const char* path) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return TMQCD_EINVAL;
+    std::map<Key, TuneChoice> t;
+    std::string arch;
+    char line[512];
+    int rc = TMQCD_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        char a[64];
+        int cls, prec, recon, L[4], block, sw;
+        double us;
+        if (std::sscanf(line,
+                        "{\"arch\": \"%63[^\"]\", \"class\": %d, \"prec\": %d, \"recon\": %d, \"dims\": [%d, %d, %d, "
+                        "%d], \"block\": %d, \"swizzle\": %d, \"us\": %lf}",
+                        a, &cls, &prec, &recon, &L[0], &L[1], &L[2], &L[3], &block, &sw, &us) != 11 ||
+            (block != 128 && block != 256) || (sw != 0 && sw != 1) || cls < 0 || cls > 2 || (!arch.empty() && arch != a)) {
+            rc = TMQCD_EINVAL;
+            break;
+        }
+        arch = a;
+        t[key_of(arch, cls, prec, recon, L)] = TuneChoice{block, sw, us};
+    }
+    std::fclose(f);
+    if (rc != TMQCD_OK) return rc;
+    if (!arch.empty() && arch != current_arch()) return TMQCD_EINVAL;   // tuned on another architecture
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table = t;
+    g_arch = arch;
+    return TMQCD_OK;
+}
+
+void tune_clear() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.clear();
+}
+
+}  // namespace tmqcd

@@ -28,7 +28,8 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
 
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg", "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force",
-                "tmqcd_gauge_force", "tmqcd_update_links", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot",
+                "tmqcd_gauge_force", "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune",
+                "tmqcd_tune_save", "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot",
                 "tmqcd_error_string", "tmqcd_last_hip_error")
 
 
@@ -57,6 +58,15 @@ class CCgStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("hop_launches", ctypes.c_int32), ("true_rel_residual", ctypes.c_double),
                 ("iter_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CTuneResult(ctypes.Structure):
+    _fields_ = [("kernel_class", ctypes.c_int32), ("block", ctypes.c_int32), ("swizzle", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("rejected", ctypes.c_int32), ("us", ctypes.c_double),
+                ("default_us", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +102,11 @@ def lib():
             "tmqcd_plaquette": (I, [P, V, V, V, S, V]),
             "tmqcd_momentum_norm2": (I, [P, V, V, V, S, V]),
             "tmqcd_dot": (I, [P, V, V, I, V, V, S, V]),
+            "tmqcd_tune_workspace_bytes": (S, [P, I]),
+            "tmqcd_tune": (I, [P, V, I, I, V, S, ctypes.POINTER(CTuneResult), V]),
+            "tmqcd_tune_save": (I, [ctypes.c_char_p]),
+            "tmqcd_tune_load": (I, [ctypes.c_char_p]),
+            "tmqcd_tune_clear": (None, []),
             "tmqcd_error_string": (ctypes.c_char_p, [I]),
             "tmqcd_last_hip_error": (I, []),
         }
@@ -264,6 +279,27 @@ def cg_batch(probs, U_packed, bs, xs=None, *, tol=1e-10, max_iter=10000, recon=R
     if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
         raise TmqcdError(rc, "tmqcd_cg_batch")
     return xs, [s.as_dict() for s in st], rc
+
+
+def tune(prob: Problem, U_packed, prec=F64, recon=RECON18, stream=None):
+    """Tune the hop launch shapes for this problem; returns one dict per kernel class."""
+    ws = _bytes(lib().tmqcd_tune_workspace_bytes(ctypes.byref(prob.c()), prec))
+    res = (CTuneResult * 3)()
+    _check(lib().tmqcd_tune(ctypes.byref(prob.c()), _ptr(U_packed), prec, recon, _ptr(ws), ws.numel(), res,
+                            _stream(stream)), "tmqcd_tune")
+    return [r.as_dict() for r in res]
+
+
+def tune_save(path: str):
+    _check(lib().tmqcd_tune_save(str(path).encode()), "tmqcd_tune_save")
+
+
+def tune_load(path: str):
+    _check(lib().tmqcd_tune_load(str(path).encode()), "tmqcd_tune_load")
+
+
+def tune_clear():
+    lib().tmqcd_tune_clear()
 
 
 def _mom(prob: Problem, out, like):

@@ -129,3 +129,19 @@ def test_error_strings(L):
     for code in (T.OK, T.EINVAL, T.EALIAS, T.EALIGN, T.ENOCONV, T.EBREAKDOWN, T.EHIP, T.EWORKSPACE):
         assert T.error_string(code) and "unknown" not in T.error_string(code)
     assert "unknown" in T.error_string(-99)
+
+
+def test_tune_table_file_validation(L, tmp_path):
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text("not json\n")
+    assert L.tmqcd_tune_load(str(bad).encode()) == T.EINVAL
+    other = tmp_path / "other.jsonl"
+    other.write_text('{"arch": "gfx000", "class": 0, "prec": 0, "recon": 0, "dims": [4, 4, 4, 4], '
+                     '"block": 128, "swizzle": 1, "us": 1.000}\n')
+    assert L.tmqcd_tune_load(str(other).encode()) == T.EINVAL      # another architecture
+    assert L.tmqcd_tune_load(str(tmp_path / "missing").encode()) == T.EINVAL
+    prob = T.Problem((4, 4, 4, 4), 0.15, 0.0)
+    assert T.lib().tmqcd_tune_workspace_bytes(ctypes.byref(prob.c()), 0) > 0
+    res = (T.CTuneResult * 3)()
+    assert L.tmqcd_tune(ctypes.byref(prob.c()), 1 << 30, 0, 0, None, 0, res, None) == T.EWORKSPACE
+    assert L.tmqcd_tune(ctypes.byref(prob.c()), 1 << 30, 5, 0, 1 << 32, 1 << 30, res, None) == T.EINVAL
