@@ -32,7 +32,7 @@ BYTES_PER_SITE = {(0, 0): 1536, (0, 1): 1152, (1, 0): 768, (1, 1): 576, (2, 0): 
 FLOPS_PER_SITE = 1320           # Wilson hop, per output site
 WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.5, kappa=0.16, mu=0.005, seed=24, src_seed=26)
 MIXED = dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.162, mu=0.003, seed=32, src_seed=34)
-HOP_SOURCES = ("hop.hip", "device.h", "layout.h")
+HOP_SOURCES = ("hop.hip", "stencil.h", "device.h", "layout.h")
 
 
 def log(msg):
@@ -69,7 +69,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-RHS, batch and HMC measurements")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only a 1 GiB copy (counter calibration) and 10 FP64 hop launches at 24^3x48, for rocprofv3 --pmc")
+    ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
+                    help="write the hop's measured HBM traffic from two --pmc runs of --kernel-only, then exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(*args.traffic_from)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and this build has no "
               "multi-GPU path (--gpus must be 1).", file=sys.stderr)
@@ -107,7 +112,7 @@ def main():
         return
 
     # launch shapes of the hop kernels chosen by the autotuner on this problem
-    tuning = {f"class{r['kernel_class']}": {"block": r["block"], "xcd_remap": r["swizzle"], "us": round(r["us"], 2),
+    tuning = {f"class{r['kernel_class']}": {"block": r["block"], "order": r["order"], "us": round(r["us"], 2),
                                           "default_us": round(r["default_us"], 2)}
               for r in T.tune(prob, gauges[(0, 0)], T.F64, T.RECON18)}
     log(f"tuned: {tuning}")
@@ -266,18 +271,62 @@ def main():
 
 
 def kernel_only(T, prob, gauges, b, dev):
-    """Calibration copy of known size, then the FP64 hop kernel; for hardware-counter runs."""
+    """Calibration copy of known size, then the FP64 hop kernel in its tuned launch shape; for counter runs."""
     import torch
     a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
     c = torch.empty_like(a)
-    c.copy_(a)
+    c.copy_(a)                     # the first copy kernel of the run: the calibration
+    torch.cuda.synchronize()
+    tuned = T.tune(prob, gauges[(0, 0)], T.F64, T.RECON18)[0]
     src = T.pack_spinor(prob, torch.from_numpy(b).to(dev), T.F64, T.EVEN)
     out = torch.empty(T.spinor_bytes(prob, T.F64, T.ODD), dtype=torch.uint8, device=dev)
     for _ in range(10):
         T.dslash(prob, gauges[(0, 0)], src, T.DSLASH_OE, out=out)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": a.numel(), "hop_launches": 10, "hop_algorithmic_bytes": prob.volume // 2 * 1536,
+    print(json.dumps({"copy_bytes": a.numel(), "hop_launches": 10, "hop_block": tuned["block"],
+                      "hop_order": tuned["order"], "hop_algorithmic_bytes": prob.volume // 2 * 1536,
                       "hop_source_sha": hop_source_hash()}), flush=True)
+
+
+def traffic_from_counters(fetch_csv, write_csv, kernel_log):
+    """Write the per-launch HBM traffic of the FP64 hop from two rocprofv3 --pmc runs of --kernel-only.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
+    counters read for the calibration copy of known size in the same run.
+    """
+    import csv
+    with open(kernel_log) as fh:
+        info = [json.loads(l) for l in fh if l.startswith("{")][-1]
+
+    def rows(path, counter):
+        out = []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    out.append(r)
+        return sorted(out, key=lambda r: int(r["Dispatch_Id"]))
+
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rs = rows(path, counter)
+        copy = [float(r["Counter_Value"]) for r in rs if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer")][:1]
+        hop = [float(r["Counter_Value"]) for r in rs
+               if "hop_kernel<0, 0, false, false, 0, 0," in r["Kernel_Name"]
+               and int(r["Workgroup_Size"]) == info["hop_block"]][-info["hop_launches"]:]
+        assert len(copy) == 1 and len(hop) == info["hop_launches"], (counter, len(copy), len(hop))
+        factor = info["copy_bytes"] / 1024.0 / copy[0]
+        res[counter] = {"copy_kib": copy[0], "factor": round(factor, 4), "hop_kib_mean": sum(hop) / len(hop),
+                        "hop_bytes": sum(hop) / len(hop) * 1024.0 * factor}
+    total = res["FETCH_SIZE"]["hop_bytes"] + res["WRITE_SIZE"]["hop_bytes"]
+    rec = {"source_sha": info["hop_source_sha"], "vh": info["hop_algorithmic_bytes"] // 1536,
+           "hop_block": info["hop_block"], "hop_order": info["hop_order"],
+           "bytes_per_launch": round(total), "algorithmic_bytes_per_launch": info["hop_algorithmic_bytes"],
+           "ratio_to_algorithmic": round(total / info["hop_algorithmic_bytes"], 4), "counters": res}
+    path = os.path.join(ROOT, "profiles", "hop_f64_24x24x24x48_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
 
 
 def _events_time(fn, reps, warm=3):

@@ -229,35 +229,56 @@ int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subse
               void* ws, size_t ws_bytes, void* stream);
 
 /* ---- autotuning --------------------------------------------------------------- */
-/* Times every launch shape (128 or 256 threads per block, with or without the
- * per-XCD block remap) of the three hop classes - 0: hop (+ twisted-mass own
- * term), 1: hop + |out|^2 (CG), 2: hop + CG update - on this problem, precision
- * and link compression (U_packed packed accordingly), admits only shapes whose
- * output is bitwise identical to the default shape's, and records the fastest
- * in a process-wide table keyed by (GPU architecture, class, prec, recon,
- * extents) that later tmqcd_dslash / tmqcd_cg / tmqcd_cg_batch calls on the
- * same key use (multi-RHS launches keep their own shape).  ws: at least
- * tmqcd_tune_workspace_bytes(prob, prec) bytes.  Synchronises the stream.
- * The paper tuned its kernels per GPU in the same spirit (memory stride,
- * lattice extents compiled in). */
+/* The paper tuned its kernels per GPU (memory stride, lattice extents compiled
+ * in); here the launch shape of each hop kernel class is chosen by timing on
+ * the caller's problem.  A shape is a block size (128 or 256 threads) and a
+ * block order, i.e. which output sites a block covers:
+ *   0  linear: block b covers half sites [b*w, b*w + w) of its parity;
+ *   1  linear, block index remapped so that each XCD gets a contiguous range;
+ *   2  every t-slice cut into 8 site ranges, one per XCD, each XCD walking
+ *      through t (its t-neighbours are in slices it has in flight);
+ *   3  the (y, z) plane cut into square regions sized to the L2, each XCD
+ *      sweeping its regions one by one through all t.
+ * Kernel classes: 0 hop (+ twisted-mass own term), 1 hop + |out|^2 (CG),
+ * 2 hop + CG update, 3 multi-RHS hop (256 threads: 64 sites x 4 waves; only
+ * the order is tuned).  Only shapes whose output is bitwise identical to the
+ * default shape's (256 threads, order 1) are admitted (for classes 1 and 2
+ * the reduction may differ by 1e-12 relative: the partial sums group
+ * differently).  The fastest shape is recorded in a process-wide table keyed by
+ * (GPU architecture, class, prec, recon, extents, nrhs) that later
+ * tmqcd_dslash / tmqcd_cg / tmqcd_cg_batch calls on the same key use; keys
+ * without an entry take the default shape.  The tuning calls synchronise the
+ * stream. */
 typedef struct {
-    int32_t kernel_class;  /* 0, 1, 2 as above */
+    int32_t kernel_class;  /* 0..3 as above */
     int32_t block;         /* chosen threads per block */
-    int32_t swizzle;       /* chosen XCD remap (1) or plain block order (0) */
+    int32_t order;         /* chosen block order, 0..3 as above */
     int32_t candidates;    /* shapes tried */
     int32_t rejected;      /* shapes whose output differed from the default's */
     double  us;            /* time per launch of the chosen shape */
-    double  default_us;    /* time per launch of the default shape (256 threads, remap) */
+    double  default_us;    /* time per launch of the default shape */
 } tmqcd_tune_result;
+/* Classes 0, 1, 2 (8 shapes each).  ws: at least tmqcd_tune_workspace_bytes. */
 size_t tmqcd_tune_workspace_bytes(const tmqcd_problem* prob, int prec);
 int tmqcd_tune(const tmqcd_problem* prob, const void* U_packed, int prec, int recon, void* ws,
                size_t ws_bytes, tmqcd_tune_result results[3], void* stream);
+/* Class 3 for nrhs in [2, 16] (4 orders).  ws: at least
+ * tmqcd_tune_mrhs_workspace_bytes(prob, prec, nrhs) bytes. */
+size_t tmqcd_tune_mrhs_workspace_bytes(const tmqcd_problem* prob, int prec, int nrhs);
+int tmqcd_tune_mrhs(const tmqcd_problem* prob, const void* U_packed, int prec, int recon, int nrhs, void* ws,
+                    size_t ws_bytes, tmqcd_tune_result* result, void* stream);
 /* The table as JSON lines (one object per key).  Loading replaces the table and
  * fails with TMQCD_EINVAL on a malformed file or one tuned on another
  * architecture. */
 int tmqcd_tune_save(const char* path);
 int tmqcd_tune_load(const char* path);
 void tmqcd_tune_clear(void);
+/* Pins the shape of one class for this problem, precision and link
+ * compression, as a tuning run would: classes 0..2 take nrhs = 1 and block
+ * 128 or 256, class 3 takes nrhs in [2, 16] and block 256; order 0..3.
+ * TMQCD_EINVAL for any other value.  Host only. */
+int tmqcd_tune_set(const tmqcd_problem* prob, int prec, int recon, int kernel_class, int nrhs, int block,
+                   int order);
 
 /* ---- diagnostics ------------------------------------------------------------- */
 const char* tmqcd_error_string(int code);

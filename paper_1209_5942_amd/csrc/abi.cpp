@@ -16,8 +16,6 @@ using namespace tmqcd;
 
 namespace {
 
-constexpr int kMaxRhs = 16;
-
 bool valid_problem(const tmqcd_problem* p) {
     if (!p) return false;
     int64_t v = 1;
@@ -358,6 +356,34 @@ int tmqcd_tune(const tmqcd_problem* prob, const void* U_packed, int prec, int re
 int tmqcd_tune_save(const char* path) { return path ? tune_save(path) : TMQCD_EINVAL; }
 int tmqcd_tune_load(const char* path) { return path ? tune_load(path) : TMQCD_EINVAL; }
 void tmqcd_tune_clear(void) { tune_clear(); }
+
+int tmqcd_tune_set(const tmqcd_problem* prob, int prec, int recon, int kernel_class, int nrhs, int block,
+                   int order) {
+    if (!valid_problem(prob) || !valid_prec(prec) || !valid_recon(recon) ||
+        !valid_choice(kernel_class, nrhs, block, order))
+        return TMQCD_EINVAL;
+    tune_set(*prob, prec, recon, kernel_class, nrhs, block, order);
+    return TMQCD_OK;
+}
+
+size_t tmqcd_tune_mrhs_workspace_bytes(const tmqcd_problem* prob, int prec, int nrhs) {
+    if (!valid_problem(prob) || !valid_prec(prec) || nrhs < 2 || nrhs > kMaxRhs) return 0;
+    return (size_t)tune_mrhs_workspace_bytes(make_geom(*prob), prec, nrhs);
+}
+
+int tmqcd_tune_mrhs(const tmqcd_problem* prob, const void* U_packed, int prec, int recon, int nrhs, void* ws,
+                    size_t ws_bytes, tmqcd_tune_result* result, void* stream) {
+    if (!valid_problem(prob) || !valid_prec(prec) || !valid_recon(recon) || nrhs < 2 || nrhs > kMaxRhs ||
+        !U_packed || !result)
+        return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int64_t need = tune_mrhs_workspace_bytes(g, prec, nrhs);
+    if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
+    if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+    if (overlap(ws, need, U_packed, gauge_bytes(g, prec, recon))) return TMQCD_EALIAS;
+    return run_tune_mrhs(*prob, U_packed, prec, recon, nrhs, ws, (hipStream_t)stream, result);
+}
 
 const char* tmqcd_error_string(int code) {
     switch (code) {

@@ -2,10 +2,10 @@
 // paper section 2.1: a thermal lattice uses less parallelism).  Each stage of
 // a CG iteration on Mhat^+ Mhat is a single grid-stride launch over the tiles
 // of all lattices, every lattice with its own solver state; lattices that have
-// converged are skipped inside the launches.  One iteration (4 hop launches
-// and the search-direction update) can be captured once in a hipGraph and
-// replayed between host checks, which removes the per-kernel launch cost that
-// dominates at these volumes.
+// converged are skipped inside the launches.  One iteration (4 hop launches,
+// 2 reduction finishes with one block per lattice, and the search-direction
+// update) can be captured once in a hipGraph and replayed between host checks,
+// which removes the per-kernel launch cost that dominates at these volumes.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -104,11 +104,15 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
             e = hipMemcpyAsync(&hs[i], L[i].st, sizeof(CgState), hipMemcpyDeviceToHost, s);
         return e == hipSuccess ? hipStreamSynchronize(s) : e;
     };
+    std::vector<const double*> parts(n);
+    std::vector<int> nb(n);
     auto iteration = [&]() -> hipError_t {
         hipError_t e = launch_hop_batch(k1.data(), n, kPersistentGrid, s);
-        if (e == hipSuccess) e = launch_hop_batch(k2.data(), n, kPersistentGrid, s);
+        if (e == hipSuccess) e = launch_hop_batch(k2.data(), n, kPersistentGrid, s, nb.data());
+        if (e == hipSuccess) e = launch_cg_finish_batch(sp.data(), parts.data(), nb.data(), n, kFinishAlpha, s);
         if (e == hipSuccess) e = launch_hop_batch(k3.data(), n, kPersistentGrid, s);
-        if (e == hipSuccess) e = launch_hop_batch(k4.data(), n, kPersistentGrid, s);
+        if (e == hipSuccess) e = launch_hop_batch(k4.data(), n, kPersistentGrid, s, nb.data());
+        if (e == hipSuccess) e = launch_cg_finish_batch(sp.data(), parts.data(), nb.data(), n, kFinishBeta, s);
         if (e == hipSuccess) e = launch_xpay_batch(vs.data(), pp.data(), rp.data(), sp.data(), n, kPersistentGrid, s);
         return e;
     };
@@ -122,7 +126,7 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
         l.c = make_ctx(probs[i], TMQCD_F64, o.recon, gauge[i], s);
         vs[i] = VecSpec{&l.g, 1};
         StateInit v = none();
-        v.set_iter = v.set_max_iter = v.set_cycle_end = v.set_done = v.reset_counters = true;
+        v.set_iter = v.set_max_iter = v.set_cycle_end = v.set_done = true;
         v.max_iter = o.max_iter;
         v.cycle_end = o.max_iter;
         v.done = kDoneRunning;
@@ -133,10 +137,13 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
         TRY(launch_norm2(vs[i], l.r, TMQCD_F64, l.st, 0, l.partials, s));
         TRY(launch_norm2(vs[i], b[i], TMQCD_F64, l.st, 1, l.partials, s));
         k1[i] = hp_schur_first(l.c, l.p, l.t1, false, kOne);
+        k1[i].st = l.st;
         k2[i] = hp_schur_second(l.c, l.t1, l.p, l.t2, false, kEpiStoreNorm, l.st, l.partials, nullptr, nullptr, nullptr,
                                 kOne);
         k3[i] = hp_schur_first(l.c, l.t2, l.t3, true, kOne);
+        k3[i].st = l.st;
         k4[i] = hp_schur_second(l.c, l.t3, l.t2, nullptr, true, kEpiCgUpdate, l.st, l.partials, x[i], l.r, l.p, kOne);
+        parts[i] = l.partials;
         pp[i] = l.p;
         rp[i] = l.r;
         sp[i] = l.st;

@@ -59,8 +59,7 @@ __global__ __launch_bounds__(kBlock) void convert_kernel(VecK v, char* dst, int6
 }
 
 template <int P>
-__global__ __launch_bounds__(kBlock) void norm2_kernel(VecK v, const char* src, int64_t bytes, CgState* st, int slot,
-                                                       double* partials) {
+__global__ __launch_bounds__(kBlock) void norm2_kernel(VecK v, const char* src, int64_t bytes, double* partials) {
     int half, h;
     double red = 0;
     if (site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) {
@@ -71,13 +70,12 @@ __global__ __launch_bounds__(kBlock) void norm2_kernel(VecK v, const char* src, 
 #pragma unroll
             for (int c = 0; c < 3; ++c) red += (double)norm2(a.s[s][c]);
     }
-    double in[1] = {red}, tot[1];
-    if (grid_reduce<1>(in, tot, partials, &st->counter[2], blockIdx.x, v.nblocks) && threadIdx.x == 0)
-        st->result[slot] = tot[0];
+    const double in[1] = {red};
+    block_partial<1>(in, partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void residual_kernel(VecK v, char* r, const char* b, const char* ax,
-                                                          int64_t bytes, CgState* st, int slot, double* partials) {
+                                                          int64_t bytes, double* partials) {
     int half, h;
     double red = 0;
     if (site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) {
@@ -93,9 +91,8 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(VecK v, char* r, const
             }
         SpinorIO<TMQCD_F64>::store(r + half * bytes, v.stride, h, bv);
     }
-    double in[1] = {red}, tot[1];
-    if (grid_reduce<1>(in, tot, partials, &st->counter[3], blockIdx.x, v.nblocks) && threadIdx.x == 0)
-        st->result[slot] = tot[0];
+    const double in[1] = {red};
+    block_partial<1>(in, partials, blockIdx.x);
 }
 
 template <int PP, int PR>
@@ -220,8 +217,6 @@ __global__ void set_state_kernel(CgState* st, StateInit v) {
     if (v.set_max_iter) st->max_iter = v.max_iter;
     if (v.set_cycle_end) st->cycle_end = v.cycle_end;
     if (v.set_done) st->done = v.done;
-    if (v.reset_counters)
-        for (int i = 0; i < 8; ++i) st->counter[i] = 0u;
 }
 
 __global__ void rr_from_result_kernel(CgState* st, int slot, double stop_factor) {
@@ -229,6 +224,46 @@ __global__ void rr_from_result_kernel(CgState* st, int slot, double stop_factor)
     const double rr = st->result[slot];
     st->rr = rr;
     if (stop_factor > 0) st->stop_rr = stop_factor * rr;
+}
+
+// second pass of a standalone reduction: st->result[slot] = sum of the partials
+__global__ __launch_bounds__(kBlock) void result_finish_kernel(CgState* st, const double* partials, int n, int slot) {
+    double tot[1];
+    sum_partials<1>(partials, n, tot);
+    if (threadIdx.x == 0) st->result[slot] = tot[0];
+}
+
+// second pass of the CG reductions; block b serves lattice b
+constexpr int kMaxFinish = 8;
+struct FinishBatch {
+    CgState* st[kMaxFinish];
+    const double* partials[kMaxFinish];
+    int n[kMaxFinish];
+};
+
+__global__ __launch_bounds__(kBlock) void cg_finish_kernel(const FinishBatch f, int kind) {
+    CgState* st = f.st[blockIdx.x];
+    if (st->done) return;
+    double tot[1];
+    sum_partials<1>(f.partials[blockIdx.x], f.n[blockIdx.x], tot);
+    if (threadIdx.x != 0) return;
+    if (kind == kFinishAlpha) {
+        const double pap = tot[0];
+        st->pAp = pap;
+        if (!(pap > 0.0) || !isfinite(pap)) st->done = kDoneBreakdown;
+        else st->alpha = st->rr / pap;
+    } else {
+        const double rr = tot[0];
+        const double rr_old = st->rr;
+        st->rr_prev = rr_old;
+        st->rr = rr;
+        st->beta = rr / rr_old;
+        const int it = st->iter + 1;
+        st->iter = it;
+        if (!isfinite(rr)) st->done = kDoneBreakdown;
+        else if (rr <= st->stop_rr || it >= st->cycle_end) st->done = kDoneStop;
+        else if (it >= st->max_iter) st->done = kDoneMaxIter;
+    }
 }
 
 template <template <int> class F, typename... A>
@@ -269,12 +304,15 @@ hipError_t launch_convert(const VecSpec& v, void* dst, int pdst, const void* src
 namespace {
 template <int P>
 struct Norm2Run {
-    static hipError_t run(const VecK k, const char* src, int64_t bytes, CgState* st, int slot, double* partials,
-                          hipStream_t s) {
-        hipLaunchKernelGGL((norm2_kernel<P>), dim3(k.nblocks), dim3(kBlock), 0, s, k, src, bytes, st, slot, partials);
+    static hipError_t run(const VecK k, const char* src, int64_t bytes, double* partials, hipStream_t s) {
+        hipLaunchKernelGGL((norm2_kernel<P>), dim3(k.nblocks), dim3(kBlock), 0, s, k, src, bytes, partials);
         return hipGetLastError();
     }
 };
+hipError_t result_finish(CgState* st, const double* partials, int n, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(result_finish_kernel, dim3(1), dim3(kBlock), 0, s, st, partials, n, slot);
+    return hipGetLastError();
+}
 template <int P>
 struct ZeroRun {
     static hipError_t run(const VecK k, char* dst, int64_t bytes, hipStream_t s) {
@@ -286,8 +324,10 @@ struct ZeroRun {
 
 hipError_t launch_norm2(const VecSpec& v, const void* src, int prec, CgState* st, int slot, double* partials,
                         hipStream_t s) {
-    return by_prec<Norm2Run>(prec, make_veck(v), static_cast<const char*>(src), half_field_bytes(*v.g, prec), st, slot,
-                             partials, s);
+    const VecK k = make_veck(v);
+    const hipError_t e =
+        by_prec<Norm2Run>(prec, k, static_cast<const char*>(src), half_field_bytes(*v.g, prec), partials, s);
+    return e == hipSuccess ? result_finish(st, partials, k.nblocks, slot, s) : e;
 }
 
 hipError_t launch_zero(const VecSpec& v, void* dst, int prec, hipStream_t s) {
@@ -299,8 +339,9 @@ hipError_t launch_residual(const VecSpec& v, void* r, const void* b, const void*
     const VecK k = make_veck(v);
     hipLaunchKernelGGL(residual_kernel, dim3(k.nblocks), dim3(kBlock), 0, s, k, static_cast<char*>(r),
                        static_cast<const char*>(b), static_cast<const char*>(ax), half_field_bytes(*v.g, TMQCD_F64),
-                       st, slot, partials);
-    return hipGetLastError();
+                       partials);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? result_finish(st, partials, k.nblocks, slot, s) : e;
 }
 
 hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st, bool skip_if_done,
@@ -338,6 +379,23 @@ hipError_t launch_accumulate(const VecSpec& v, void* x64, void* xs, int ps, hipS
 hipError_t launch_set_state(CgState* st, const StateInit& v, hipStream_t s) {
     hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(64), 0, s, st, v);
     return hipGetLastError();
+}
+
+hipError_t launch_cg_finish_batch(CgState* const* st, const double* const* partials, const int* n, int count,
+                                  int kind, hipStream_t s) {
+    if (count < 1 || count > kMaxFinish) return hipErrorInvalidValue;
+    FinishBatch f;
+    for (int i = 0; i < count; ++i) {
+        f.st[i] = st[i];
+        f.partials[i] = partials[i];
+        f.n[i] = n[i];
+    }
+    hipLaunchKernelGGL(cg_finish_kernel, dim3(count), dim3(kBlock), 0, s, f, kind);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(CgState* st, const double* partials, int n, int kind, hipStream_t s) {
+    return launch_cg_finish_batch(&st, &partials, &n, 1, kind, s);
 }
 
 hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipStream_t s) {

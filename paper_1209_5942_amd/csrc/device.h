@@ -361,25 +361,17 @@ struct CgState {
     int cycle_end;    // the update kernel flags done when iter reaches it (reliable-update cycle cap)
     int done;         // 0 running, 1 reached stop_rr or cycle_end, 2 breakdown, 3 iteration cap
     double result[4]; // scratch results of standalone reductions
-    unsigned counter[8];
 };
 enum { kDoneRunning = 0, kDoneStop = 1, kDoneBreakdown = 2, kDoneMaxIter = 3 };
 
-__device__ __forceinline__ double coherent_load(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Deterministic grid reduction of N doubles.  Every block writes its partial
-// sums (in a fixed order) to partials[bid * N + i]; the last block to finish
-// sums them in the fixed order of block index and returns true, with the
-// totals in `tot` for every thread of that block.  The counter is reset for
-// the next use by the block that consumed it.
+// Deterministic two-pass reductions.  Pass 1: every block stores the sums of
+// its threads' values (in a fixed order) to partials[bid * N + i].  Pass 2
+// (a later launch, so the partials are visible without device-wide fences):
+// one block of kBlock threads adds the partials in a fixed order.
 template <int N, int BS = kBlock>
-__device__ __forceinline__ bool grid_reduce(double (&v)[N], double (&tot)[N], double* partials,
-                                            unsigned* counter, int bid, int nblocks) {
-    constexpr int kWaves = BS / 64;
-    __shared__ double sh[N][kWaves];
-    __shared__ int last;
+__device__ __forceinline__ void block_partial(const double (&v)[N], double* partials, int bid) {
+    constexpr int kW = BS / 64;
+    __shared__ double sh[N][kW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -392,23 +384,35 @@ __device__ __forceinline__ bool grid_reduce(double (&v)[N], double (&tot)[N], do
         for (int i = 0; i < N; ++i) {
             double s = 0;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) s += sh[i][w];
-            __hip_atomic_store(&partials[(int64_t)bid * N + i], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int w = 0; w < kW; ++w) s += sh[i][w];
+            partials[(int64_t)bid * N + i] = s;
         }
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        last = (prev == (unsigned)nblocks - 1);
     }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+}
+
+// Pass 2, for a block of kBlock threads: the totals, in every thread.
+template <int N>
+__device__ __forceinline__ void sum_partials(const double* partials, int nblocks, double (&tot)[N]) {
     double acc[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[i] = 0;
-    for (int b = threadIdx.x; b < nblocks; b += BS)
+    // eight independent loads in flight, added in the fixed order b = tid, tid + kBlock, ...
+    constexpr int kBatch = 8;
+    for (int b0 = threadIdx.x; b0 < nblocks; b0 += kBatch * kBlock) {
+        double v[kBatch][N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc[i] += coherent_load(&partials[(int64_t)b * N + i]);
-    __syncthreads();
+        for (int k = 0; k < kBatch; ++k) {
+            const int b = b0 + k * kBlock;
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[k][i] = b < nblocks ? partials[(int64_t)b * N + i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k)
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc[i] += v[k][i];
+    }
+    __shared__ double sh[N][kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const double s = wave_sum(acc[i]);
@@ -422,9 +426,6 @@ __device__ __forceinline__ bool grid_reduce(double (&v)[N], double (&tot)[N], do
         for (int w = 0; w < kWaves; ++w) s += sh[i][w];
         tot[i] = s;
     }
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
-    __syncthreads();   // `sh` is reused if the caller reduces again (grid-stride loops)
-    return true;
 }
 
 }  // namespace tmqcd

@@ -167,6 +167,53 @@ __global__ __launch_bounds__(kBlock) void force_kernel(const ForceK a) {
     }
 }
 
+// The same force with four times the parallelism: a block covers 64 sites and
+// its wave w computes direction w (a wave-uniform branch), so each thread
+// holds one direction's operands.  The four waves read the same X(x), Y(x)
+// (cache hits after the first).  Launch bounds ask for two waves per SIMD
+// (at most 256 registers; the kernel does not spill).
+template <int R>
+__global__ __launch_bounds__(kBlock, 2) void force_dir_kernel(const ForceK a) {
+    const int bid = blockIdx.x;
+    const int par = bid >= a.nb_half ? 1 : 0;
+    const int h = (bid - par * a.nb_half) * 64 + (threadIdx.x & 63);
+    const int mu = threadIdx.x >> 6;
+    if (h >= a.vh) return;
+    const int lxh = a.lxh, lx = a.L[0], ly = a.L[1], lz = a.L[2], lt = a.L[3];
+    const int xh = h % lxh;
+    int rest = h / lxh;
+    const int y = rest % ly;
+    rest /= ly;
+    const int z = rest % lz;
+    const int t = rest / lz;
+    const int bit = (par + y + z + t) & 1;
+    const int x = 2 * xh + bit;
+    const int64_t s = 2 * (int64_t)h + bit;
+
+    Spinor<double> xo, yo;
+    SpinorIO<TMQCD_F64>::load(xo, a.X + (int64_t)par * a.hbytes, a.stride, h);
+    SpinorIO<TMQCD_F64>::load(yo, a.Y + (int64_t)par * a.hbytes, a.stride, h);
+    double g[8];
+    if (mu == 0) {
+        const int xf = x + 1 == lx ? 0 : x + 1;
+        force_dir<R, 0>(a, par, h, (h - xh) + (xf >> 1), x == lx - 1, xo, yo, g);
+    } else if (mu == 1) {
+        const int nf = y == ly - 1 ? h - (ly - 1) * lxh : h + lxh;
+        force_dir<R, 1>(a, par, h, nf, y == ly - 1, xo, yo, g);
+    } else if (mu == 2) {
+        const int st = lxh * ly;
+        const int nf = z == lz - 1 ? h - (lz - 1) * st : h + st;
+        force_dir<R, 2>(a, par, h, nf, z == lz - 1, xo, yo, g);
+    } else {
+        const int st = lxh * ly * lz;
+        const int nf = t == lt - 1 ? h - (lt - 1) * st : h + st;
+        force_dir<R, 3>(a, par, h, nf, t == lt - 1, xo, yo, g);
+    }
+    double* o = a.out + s * 32 + mu * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = a.accumulate ? o[i] + a.scale * g[i] : a.scale * g[i];
+}
+
 }  // namespace
 
 hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* X, const void* Y, double* out,
@@ -185,13 +232,13 @@ hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void*
     }
     k.lxh = g.lxh;
     k.vh = (int)g.vh;
-    k.nb_half = (int)((g.vh + kBlock - 1) / kBlock);
+    k.nb_half = (int)((g.vh + 63) / 64);
     k.kappa = kappa;
     k.scale = scale;
     k.accumulate = accumulate;
     const dim3 grid(2 * k.nb_half);
-    if (recon == TMQCD_RECON12) hipLaunchKernelGGL((force_kernel<TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k);
-    else hipLaunchKernelGGL((force_kernel<TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k);
+    if (recon == TMQCD_RECON12) hipLaunchKernelGGL((force_dir_kernel<TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k);
+    else hipLaunchKernelGGL((force_dir_kernel<TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k);
     return hipGetLastError();
 }
 

@@ -228,51 +228,12 @@ __global__ __launch_bounds__(kBlock) void update_links_kernel(LatK k, char* gaug
 
 // ----------------------------------------------------------- reductions ---
 template <int N>
-__device__ __forceinline__ void block_partial(double (&v)[N], double* partials) {
-    __shared__ double sh[N][kWaves];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const double s = wave_sum(v[i]);
-        if (lane == 0) sh[i][wave] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            double s = 0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) s += sh[i][w];
-            partials[(int64_t)blockIdx.x * N + i] = s;
-        }
-    }
-}
-
-template <int N>
 __global__ __launch_bounds__(kBlock) void finalize_kernel(const double* partials, int nblocks, double* result) {
-    double acc[N];
+    double tot[N];
+    sum_partials<N>(partials, nblocks, tot);
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc[i] = 0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock)
-#pragma unroll
-        for (int i = 0; i < N; ++i) acc[i] += partials[(int64_t)b * N + i];
-    __shared__ double sh[N][kWaves];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const double s = wave_sum(acc[i]);
-        if (lane == 0) sh[i][wave] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            double s = 0;
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) s += sh[i][w];
-            result[i] = s;
-        }
-    }
+        for (int i = 0; i < N; ++i) result[i] = tot[i];
 }
 
 __global__ __launch_bounds__(kBlock) void plaquette_kernel(LatK k, const char* gauge, double* partials) {
@@ -302,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void plaquette_kernel(LatK k, const char* g
                     for (int j = 0; j < 3; ++j) v[0] += t1.m[i][j].re * t2.m[i][j].re + t1.m[i][j].im * t2.m[i][j].im;
             }
     }
-    block_partial<1>(v, partials);
+    block_partial<1>(v, partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void mom_norm2_kernel(const double* mom, int64_t n, double* partials) {
@@ -312,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void mom_norm2_kernel(const double* mom, in
 #pragma unroll
         for (int a = 0; a < 8; ++a) v[0] += mom[i * 8 + a] * mom[i * 8 + a];
     }
-    block_partial<1>(v, partials);
+    block_partial<1>(v, partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void spinor_dot_kernel(const char* x, const char* y, int64_t stride, int vh,
@@ -333,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void spinor_dot_kernel(const char* x, const
                 v[1] += z.im;
             }
     }
-    block_partial<2>(v, partials);
+    block_partial<2>(v, partials, blockIdx.x);
 }
 
 }  // namespace

@@ -1,0 +1,125 @@
+// Multi-RHS hop (several right-hand sides share every link load).
+#include "stencil.h"
+
+namespace tmqcd {
+namespace stencil {
+namespace {
+
+// Multi-RHS hop: a block owns 64 output sites; its four waves first copy the
+// eight links of those sites into LDS (each link read from HBM once), then
+// loop over the right-hand sides, wave w handling rhs w, w+4, w+8, ...
+// Fields of consecutive right-hand sides are `*_fstride` bytes apart.
+struct MrhsK {
+    int nrhs;
+    int64_t in_fstride, own_fstride, out_fstride;
+};
+
+template <int P, int R, bool DAG, bool OWN>
+__global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const MrhsK m) {
+    using T = typename Prec<P>::T;
+    using LIO = LinkIO<P, R>;
+    using Unit = typename LIO::Unit;
+    constexpr int NU = LIO::kUnits;
+    __shared__ Unit tile[8 * NU * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int par, h;
+    const bool valid = block_site(a, blockIdx.x, lane, par, h);
+    const bool two = a.nparity == 2;
+    Nbr n;
+    if (valid) {
+        neighbours(a, par, h, n);
+        // links 0..3: U_mu(x) (parity par, index h); 4..7: U_mu(x - mu) (other parity)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int l = 2 * wave + q;
+            const int mu = l & 3;
+            const int lp = l < 4 ? par : 1 - par;
+            // select, not an indexed load: a private array indexed at run time would live in scratch
+            const int nbm = mu == 0 ? n.b[0] : mu == 1 ? n.b[1] : mu == 2 ? n.b[2] : n.b[3];
+            const int lh = l < 4 ? h : nbm;
+            const Unit* src = reinterpret_cast<const Unit*>(a.gauge) + (int64_t)((lp * 4 + mu) * NU) * a.gstride + lh;
+#pragma unroll
+            for (int k = 0; k < NU; ++k) tile[(l * NU + k) * 64 + lane] = ld_stream(src + k * a.gstride);
+        }
+    }
+    __syncthreads();
+    if (!valid) return;
+    const char* lt = reinterpret_cast<const char*>(tile);
+    const C<T> cuh = cvt<T>(a.cu_hop), cdh = cvt<T>(a.cd_hop);
+    const int64_t hoff = two ? (int64_t)par * a.hbytes : 0;
+    const int64_t ioff = two ? (int64_t)(1 - par) * a.hbytes : 0;
+#pragma unroll 1
+    for (int r = wave; r < m.nrhs; r += kWaves) {
+        // The link reads from the tile do not depend on r; without this barrier
+        // the compiler hoists all eight links out of the loop into registers.
+        __asm__ volatile("" ::: "memory");
+        const char* in = a.in + r * m.in_fstride + ioff;
+        Spinor<T> acc;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc.s[s][c] = {T(0), T(0)};
+#define TMQCD_TERMS(MU)                                                                                     \
+    {                                                                                                       \
+        const C<T> ph = cvt<T>(a.bc[MU]);                                                                   \
+        hop_term_at<P, R, MU, true, DAG, false>(acc, in, a.stride, n.f[MU], lt, 64, 0, lane, n.cf[MU], ph);       \
+        hop_term_at<P, R, MU, false, DAG, false>(acc, in, a.stride, n.b[MU], lt, 64, 1, lane, n.cb[MU], conj(ph)); \
+    }
+        TMQCD_TERMS(0)
+        TMQCD_TERMS(1)
+        TMQCD_TERMS(2)
+        TMQCD_TERMS(3)
+#undef TMQCD_TERMS
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc.s[0][c] = cuh * acc.s[0][c];
+            acc.s[1][c] = cuh * acc.s[1][c];
+            acc.s[2][c] = cdh * acc.s[2][c];
+            acc.s[3][c] = cdh * acc.s[3][c];
+        }
+        if constexpr (OWN) {
+            Spinor<T> o;
+            SpinorIO<P>::load(o, a.own + r * m.own_fstride + hoff, a.stride, h);
+            const C<T> cuo = cvt<T>(a.cu_own), cdo = cvt<T>(a.cd_own);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                acc.s[0][c] = acc.s[0][c] + cuo * o.s[0][c];
+                acc.s[1][c] = acc.s[1][c] + cuo * o.s[1][c];
+                acc.s[2][c] = acc.s[2][c] + cdo * o.s[2][c];
+                acc.s[3][c] = acc.s[3][c] + cdo * o.s[3][c];
+            }
+        }
+        SpinorIO<P>::store(a.out + r * m.out_fstride + hoff, a.stride, h, acc);
+    }
+}
+
+template <int P, int R>
+hipError_t launch_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
+    MrhsK m;
+    m.nrhs = a.nrhs;
+    m.in_fstride = a.in_fstride;
+    m.own_fstride = a.own_fstride;
+    m.out_fstride = a.out_fstride;
+    const bool own = a.own != nullptr;
+    const dim3 grid(k.nblocks), block(kBlock);
+    if (!a.dag && !own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, false>), grid, block, 0, s, k, m);
+    else if (a.dag && !own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, false>), grid, block, 0, s, k, m);
+    else if (!a.dag && own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, true>), grid, block, 0, s, k, m);
+    else hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, true>), grid, block, 0, s, k, m);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_hop_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
+    const bool r12 = a.recon == TMQCD_RECON12;
+    switch (a.prec) {
+        case TMQCD_F64: return r12 ? launch_mrhs<TMQCD_F64, TMQCD_RECON12>(a, k, s) : launch_mrhs<TMQCD_F64, TMQCD_RECON18>(a, k, s);
+        case TMQCD_F32: return r12 ? launch_mrhs<TMQCD_F32, TMQCD_RECON12>(a, k, s) : launch_mrhs<TMQCD_F32, TMQCD_RECON18>(a, k, s);
+        case TMQCD_F16: return r12 ? launch_mrhs<TMQCD_F16, TMQCD_RECON12>(a, k, s) : launch_mrhs<TMQCD_F16, TMQCD_RECON18>(a, k, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace stencil
+}  // namespace tmqcd

@@ -18,8 +18,8 @@ struct Cplx {
 // Epilogue kinds of the hop kernel.
 enum HopEpilogue {
     kEpiStore = 0,      // out = own-term + hop-term
-    kEpiStoreNorm = 1,  // ... and |out|^2 -> pAp; alpha = rr / pAp
-    kEpiCgUpdate = 2,   // out not stored: x += alpha p; r -= alpha out; |r|^2 -> rr, beta
+    kEpiStoreNorm = 1,  // ... and the partial sums of |out|^2 (then cg_finish: pAp, alpha)
+    kEpiCgUpdate = 2,   // out not stored: x += alpha p; r -= alpha out; partial sums of |r|^2 (cg_finish: rr, beta)
 };
 
 // out_p = [c_own * own_p] + c_hop * (H in)_p, where c = diag(cu, cu, cd, cd) in
@@ -39,7 +39,7 @@ struct HopParams {
     Cplx bc[4];
     Cplx cu_own, cd_own, cu_hop, cd_hop;
     int epi;
-    // reductions and CG update (epi != kEpiStore)
+    // reductions and CG update (epi != kEpiStore); with st set, the launch returns at once once st->done
     CgState* st;
     double* partials;
     void* x;          // vector precision
@@ -49,23 +49,32 @@ struct HopParams {
     // several right-hand sides (epi == kEpiStore): fields nrhs apart by these byte strides
     int nrhs;
     int64_t in_fstride, own_fstride, out_fstride;
-    // launch shape: block 128 or 256 threads and the XCD remap; block = 0 takes the tuned choice
+    // launch shape: block 128 or 256 threads and the block order (kOrder*); block = 0 takes the tuned choice
     int block;
-    int swizzle;
+    int order;
 };
+
+// Block orders of the hop launches (which sites a block covers, see block_site in stencil.h).
+enum BlockOrder { kOrderLinear = 0, kOrderXcdRemap = 1, kOrderSlab = 2, kOrderColumn = 3, kNumOrders = 4 };
+
+constexpr int kMaxRhs = 16;   // right-hand sides of one multi-RHS launch
 
 // ---- autotuning (tune.cpp) ------------------------------------------------------
+// kernel classes: 0 hop (store), 1 hop + |out|^2, 2 hop + CG update, 3 multi-RHS hop
+constexpr int kClassMultiRhs = 3;
 struct TuneChoice {
     int block;
-    int swizzle;
+    int order;
     double us;
 };
-// the tuned launch shape for this hop (class from epi and own; single right-hand side)
+// the tuned launch shape for this hop (class from epi, or the multi-RHS class with its nrhs)
 bool tune_lookup(const HopParams& a, TuneChoice* out);
 
-hipError_t launch_hop(const HopParams& a, hipStream_t s);
-// one launch over the same stage for n <= 8 lattices (FP64), grid-stride over their tiles
-hipError_t launch_hop_batch(const HopParams* ps, int n, int max_grid, hipStream_t s);
+// *nblocks (if given): the number of blocks, i.e. of reduction partials this launch writes
+hipError_t launch_hop(const HopParams& a, hipStream_t s, int* nblocks = nullptr);
+// one launch over the same stage for n <= 8 lattices (FP64), grid-stride over their tiles;
+// nblocks[i] (if given): the number of reduction partials lattice i receives
+hipError_t launch_hop_batch(const HopParams* ps, int n, int max_grid, hipStream_t s, int* nblocks = nullptr);
 int hop_blocks(const Geom& g, int nparity);   // grid size (and partial count) of a hop launch
 
 // ---- BLAS-1 over packed fields of nhalf half fields -------------------------
@@ -98,10 +107,17 @@ hipError_t launch_compare(const void* a, const void* b, int64_t bytes, unsigned 
 struct StateInit {
     double rr, rr_prev, stop_rr, alpha, beta;
     int iter, max_iter, cycle_end, done;
-    bool set_rr, set_rr_prev, set_stop, set_alpha, set_beta, set_iter, set_max_iter, set_cycle_end, set_done,
-        reset_counters;
+    bool set_rr, set_rr_prev, set_stop, set_alpha, set_beta, set_iter, set_max_iter, set_cycle_end, set_done;
 };
 hipError_t launch_set_state(CgState* st, const StateInit& v, hipStream_t s);
+// Second pass of a CG reduction over n partials (one block per lattice):
+//   kFinishAlpha: pAp = sum, alpha = rr / pAp (done = breakdown unless pAp > 0)
+//   kFinishBeta:  rr_prev = rr, rr = sum, beta = rr / rr_prev, iter + 1, stop tests
+// Nothing happens for a lattice whose st->done is set.
+enum FinishKind { kFinishAlpha = 0, kFinishBeta = 1 };
+hipError_t launch_cg_finish(CgState* st, const double* partials, int n, int kind, hipStream_t s);
+hipError_t launch_cg_finish_batch(CgState* const* st, const double* const* partials, const int* n, int count,
+                                  int kind, hipStream_t s);
 // st->rr = st->result[slot]; optionally stop_rr = factor * rr
 hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipStream_t s);
 

@@ -7,13 +7,19 @@
 // the upper two spins as (1 - i w) and on the lower two as (1 + i w).  The
 // adjoints use H^+ (gamma_mu -> -gamma_mu) and A^+ = A(-mu).
 //
-// One CG iteration on Mhat^+ Mhat is four hop launches and one BLAS launch:
+// One CG iteration on Mhat^+ Mhat is four hop launches, two one-block
+// reduction finishes and one BLAS launch:
 //   t1 = A^{-1} H_oe p
-//   t2 = A p - kappa^2 H_eo t1                 and  p^+ A p = |t2|^2, alpha
+//   t2 = A p - kappa^2 H_eo t1                 and per-block sums of |t2|^2
+//   finish: p^+ A p = |t2|^2, alpha
 //   t3 = A(-mu)^{-1} H^+_oe t2
 //   (A p) = A(-mu) t2 - kappa^2 H^+_eo t3      fused with x += alpha p,
-//                                               r -= alpha A p, |r|^2, beta
+//                                               r -= alpha A p, per-block |r|^2
+//   finish: |r|^2, beta, stop tests
 //   p = r + beta p
+// The reductions finish in a launch of their own: a last-block-done scheme
+// would need a device-wide release in every block, which on this chip writes
+// back the XCD's L2 and costs more than the extra launch.
 // All scalars stay on the device; the host queues several iterations, then
 // reads the state once.  Kernels queued after convergence return at once.
 #include <algorithm>
@@ -91,8 +97,8 @@ hipError_t op_dslash_pq(const OpCtx& c, const void* in, void* out, int out_parit
 }
 
 // full field: out = A(+-mu) in - kappa H(^+) in
-hipError_t op_full(const OpCtx& c, const void* in, void* out, bool dag, int epi, CgState* st, double* partials,
-                   void* x, void* r, const void* p, const Rhs& rh = kOne) {
+static HopParams hp_full(const OpCtx& c, const void* in, void* out, bool dag, int epi, CgState* st, double* partials,
+                         void* x, void* r, const void* p, const Rhs& rh) {
     HopParams a = base_params(c);
     a.in = in;
     a.own = in;
@@ -108,7 +114,11 @@ hipError_t op_full(const OpCtx& c, const void* in, void* out, bool dag, int epi,
     a.r = r;
     a.p = p;
     set_rhs(a, Rhs{rh.n, rh.in, rh.in, rh.out});
-    return launch_hop(a, c.s);
+    return a;
+}
+hipError_t op_full(const OpCtx& c, const void* in, void* out, bool dag, int epi, CgState* st, double* partials,
+                   void* x, void* r, const void* p, const Rhs& rh = kOne) {
+    return launch_hop(hp_full(c, in, out, dag, epi, st, partials, x, r, p, rh), c.s);
 }
 
 // even sites: t_o = A(+-mu)^{-1} H(^+)_oe in_e
@@ -280,25 +290,36 @@ struct Fields {
     void* t3;
 };
 
-// Queue one CG iteration (all precisions): see the file header.
+// Queue one CG iteration (all precisions): see the file header.  Every stage
+// carries the solver state, so stages queued after the stop return at once.
 hipError_t queue_iteration(const OpCtx& c, bool full, const Fields& f, CgState* st, double* partials, int pv) {
     hipError_t e;
+    int nb = 0;
     VecSpec vs{&c.g, full ? 2 : 1};
     if (full) {
-        e = op_full(c, f.p, f.t1, false, kEpiStoreNorm, st, partials, nullptr, nullptr, nullptr);
-        if (e != hipSuccess) return e;
-        e = op_full(c, f.t1, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p);
-        if (e != hipSuccess) return e;
+        e = launch_hop(hp_full(c, f.p, f.t1, false, kEpiStoreNorm, st, partials, nullptr, nullptr, nullptr, kOne), c.s,
+                       &nb);
+        if (e == hipSuccess) e = launch_cg_finish(st, partials, nb, kFinishAlpha, c.s);
+        if (e == hipSuccess)
+            e = launch_hop(hp_full(c, f.t1, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p, kOne), c.s, &nb);
     } else {
-        e = op_schur_first(c, f.p, f.t1, false);
-        if (e != hipSuccess) return e;
-        e = op_schur_second(c, f.t1, f.p, f.t2, false, kEpiStoreNorm, st, partials, nullptr, nullptr, nullptr);
-        if (e != hipSuccess) return e;
-        e = op_schur_first(c, f.t2, f.t3, true);
-        if (e != hipSuccess) return e;
-        e = op_schur_second(c, f.t3, f.t2, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p);
-        if (e != hipSuccess) return e;
+        HopParams k1 = hp_schur_first(c, f.p, f.t1, false, kOne);
+        HopParams k3 = hp_schur_first(c, f.t2, f.t3, true, kOne);
+        k1.st = k3.st = st;
+        e = launch_hop(k1, c.s);
+        if (e == hipSuccess)
+            e = launch_hop(hp_schur_second(c, f.t1, f.p, f.t2, false, kEpiStoreNorm, st, partials, nullptr, nullptr,
+                                           nullptr, kOne),
+                           c.s, &nb);
+        if (e == hipSuccess) e = launch_cg_finish(st, partials, nb, kFinishAlpha, c.s);
+        if (e == hipSuccess) e = launch_hop(k3, c.s);
+        if (e == hipSuccess)
+            e = launch_hop(hp_schur_second(c, f.t3, f.t2, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p,
+                                           kOne),
+                           c.s, &nb);
     }
+    if (e == hipSuccess) e = launch_cg_finish(st, partials, nb, kFinishBeta, c.s);
+    if (e != hipSuccess) return e;
     return launch_xpay(vs, f.p, c.prec, f.r, pv, st, true, c.s);
 }
 
@@ -350,9 +371,9 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
     const double delta = o.reliable_delta > 0 ? o.reliable_delta : (q == TMQCD_F16 ? 1e-2 : 1e-4);
     char* tmp64 = static_cast<char*>(w.t1);   // t1 (and t2 for even-odd) are contiguous
 
-    // state: counters zero, iteration count, cap
+    // state: iteration count, cap
     StateInit si = no_change();
-    si.set_iter = si.set_max_iter = si.set_done = si.reset_counters = true;
+    si.set_iter = si.set_max_iter = si.set_done = true;
     si.iter = 0;
     si.max_iter = o.max_iter;
     si.done = kDoneRunning;

@@ -1,8 +1,9 @@
 // Autotuner for the hop launches.  The paper tuned its memory stride per GPU and
 // compiled lattice extents into the kernels (its implementation-strategy
 // section); here the launch shape of every hop class - 128 or 256 threads per
-// block, with or without the per-XCD block remap - is chosen by timing on the
-// caller's problem.  A variant may be chosen only if its output is bitwise
+// block, and the order in which blocks cover the sites (linear, linear with
+// the per-XCD remap, or t-slices cut into one range per XCD) - is chosen by
+// timing on the caller's problem.  A variant may be chosen only if its output is bitwise
 // identical to the default variant's (and its reduction equal within 1e-12):
 // the paper found compilers to miscompile large kernels, so every variant is
 // re-verified on the device it will run on.
@@ -27,7 +28,7 @@
 namespace tmqcd {
 namespace {
 
-using Key = std::tuple<std::string, int, int, int, int, int, int, int>;   // arch, class, prec, recon, L[4]
+using Key = std::tuple<std::string, int, int, int, int, int, int, int, int>;   // arch, class, prec, recon, L[4], nrhs
 
 std::mutex g_mu;
 std::map<Key, TuneChoice> g_table;
@@ -44,16 +45,33 @@ std::string current_arch() {
     return c == std::string::npos ? a : a.substr(0, c);
 }
 
-Key key_of(const std::string& arch, int cls, int prec, int recon, const int L[4]) {
-    return Key(arch, cls, prec, recon, L[0], L[1], L[2], L[3]);
+Key key_of(const std::string& arch, int cls, int prec, int recon, const int L[4], int nrhs) {
+    return Key(arch, cls, prec, recon, L[0], L[1], L[2], L[3], nrhs);
+}
+
+void record(const std::string& arch, const Key& key, const TuneChoice& c) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_arch != arch) {
+        g_table.clear();
+        g_arch = arch;
+    }
+    g_table[key] = c;
 }
 
 }  // namespace
 
+bool valid_choice(int cls, int nrhs, int block, int order) {
+    if (order < 0 || order >= kNumOrders) return false;
+    if (cls >= 0 && cls < kClassMultiRhs) return nrhs == 1 && (block == 128 || block == 256);
+    return cls == kClassMultiRhs && nrhs >= 2 && nrhs <= kMaxRhs && block == kBlock;
+}
+
 bool tune_lookup(const HopParams& a, TuneChoice* out) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_table.empty()) return false;
-    const auto it = g_table.find(key_of(g_arch, class_of(a.epi), a.prec, a.recon, a.g.L));
+    const bool multi = a.nrhs > 1;
+    const auto it = g_table.find(key_of(g_arch, multi ? kClassMultiRhs : class_of(a.epi), a.prec, a.recon, a.g.L,
+                                        multi ? a.nrhs : 1));
     if (it == g_table.end()) return false;
     *out = it->second;
     return true;
@@ -120,7 +138,10 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
     const OpCtx c = make_ctx(prob, prec, recon, gauge, s);
     const VecSpec vs{&g, 1};
     const int64_t hd = half_field_bytes(g, prec), hv = half_field_bytes(g, pv);
-    const int shapes[4][2] = {{256, 1}, {256, 0}, {128, 1}, {128, 0}};   // first: the default, the reference
+    // block size x block order; the first is the default and the reference
+    const int shapes[8][2] = {{256, kOrderXcdRemap}, {256, kOrderLinear}, {128, kOrderXcdRemap},
+                              {128, kOrderLinear},   {256, kOrderSlab},   {128, kOrderSlab},
+                              {256, kOrderColumn},   {128, kOrderColumn}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const std::string arch = current_arch();
     TRY(hipEventCreate(&e0));
@@ -135,7 +156,7 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
         res.kernel_class = cls;
         double ref_scalar = 0;
         double best = 1e30;
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < 8; ++v) {
             HopParams a;
             if (cls == 0) a = hp_schur_first(c, w.in_e, w.t_o, false, kOne);
             else if (cls == 1)
@@ -145,12 +166,12 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
                 a = hp_schur_second(c, w.t_o, w.in_e, nullptr, true, kEpiCgUpdate, w.st, w.partials, w.x, w.r,
                                     w.in_e, kOne);
             a.block = shapes[v][0];
-            a.swizzle = shapes[v][1];
+            a.order = shapes[v][1];
             // one verified run from a fixed state
             StateInit si;
             std::memset(&si, 0, sizeof(si));
             si.set_rr = si.set_alpha = si.set_stop = si.set_iter = si.set_max_iter = si.set_cycle_end =
-                si.set_done = si.reset_counters = true;
+                si.set_done = true;
             si.rr = 1.0;
             si.alpha = 0.37;
             si.stop_rr = 0.0;
@@ -161,7 +182,9 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
                 TRY(hipMemcpyAsync(w.x, w.x0, hv, hipMemcpyDeviceToDevice, s));
                 TRY(hipMemcpyAsync(w.r, w.r0, hv, hipMemcpyDeviceToDevice, s));
             }
-            TRY(launch_hop(a, s));
+            int nb = 0;
+            TRY(launch_hop(a, s, &nb));
+            if (cls > 0) TRY(launch_cg_finish(w.st, w.partials, nb, cls == 1 ? kFinishAlpha : kFinishBeta, s));
             CgState h;
             TRY(hipMemcpyAsync(&h, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
             TRY(hipStreamSynchronize(s));
@@ -207,19 +230,87 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
             if (us < best) {
                 best = us;
                 res.block = a.block;
-                res.swizzle = a.swizzle;
+                res.order = a.order;
                 res.us = us;
             }
         }
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            if (g_arch != arch) {
-                g_table.clear();
-                g_arch = arch;
-            }
-            g_table[key_of(arch, cls, prec, recon, g.L)] = TuneChoice{res.block, res.swizzle, res.us};
+        record(arch, key_of(arch, cls, prec, recon, g.L, 1), TuneChoice{res.block, res.order, res.us});
+    }
+    TRY(hipStreamSynchronize(s));
+done:
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    return rc;
+}
+
+
+// Multi-RHS class: the block orders of the link-sharing kernel (256 threads:
+// 64 sites x 4 waves) on nrhs fields, verified bitwise against the default.
+int64_t tune_mrhs_workspace_bytes(const Geom& g, int prec, int nrhs) {
+    const int64_t hd = round_up(half_field_bytes(g, prec), kAlignBytes);
+    return round_up(64, kAlignBytes) + 3 * nrhs * hd;
+}
+
+int run_tune_mrhs(const tmqcd_problem& prob, const void* gauge, int prec, int recon, int nrhs, void* ws,
+                  hipStream_t s, tmqcd_tune_result* res) {
+    int rc = TMQCD_OK;
+    const Geom g = make_geom(prob);
+    const int64_t hd = round_up(half_field_bytes(g, prec), kAlignBytes);
+    char* base = static_cast<char*>(ws);
+    auto* mism = reinterpret_cast<unsigned long long*>(base);
+    char* in = base + round_up(64, kAlignBytes);
+    char* out = in + nrhs * hd;
+    char* ref = out + nrhs * hd;
+    const OpCtx c = make_ctx(prob, prec, recon, gauge, s);
+    const VecSpec vs{&g, 1};
+    const int orders[kNumOrders] = {kOrderXcdRemap, kOrderLinear, kOrderSlab, kOrderColumn};   // first: default
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const std::string arch = current_arch();
+    double best = 1e30;
+    std::memset(res, 0, sizeof(*res));
+    res->kernel_class = kClassMultiRhs;
+    TRY(hipEventCreate(&e0));
+    TRY(hipEventCreate(&e1));
+    for (int r = 0; r < nrhs; ++r) TRY(launch_fill(vs, in + r * hd, prec, 21u + r, s));
+    for (int v = 0; v < kNumOrders; ++v) {
+        HopParams a = hp_schur_first(c, in, out, false, Rhs{nrhs, hd, 0, hd});
+        a.block = kBlock;
+        a.order = orders[v];
+        TRY(launch_hop(a, s));
+        bool ok = true;
+        if (v == 0) {
+            TRY(hipMemcpyAsync(ref, out, nrhs * hd, hipMemcpyDeviceToDevice, s));
+        } else {
+            unsigned long long m = 0;
+            TRY(hipMemsetAsync(mism, 0, 8, s));
+            TRY(launch_compare(ref, out, nrhs * hd, mism, s));
+            TRY(hipMemcpyAsync(&m, mism, 8, hipMemcpyDeviceToHost, s));
+            TRY(hipStreamSynchronize(s));
+            ok = m == 0;
+        }
+        ++res->candidates;
+        if (!ok) {
+            ++res->rejected;
+            continue;
+        }
+        constexpr int kReps = 8;
+        TRY(launch_hop(a, s));
+        TRY(hipEventRecord(e0, s));
+        for (int k = 0; k < kReps; ++k) TRY(launch_hop(a, s));
+        TRY(hipEventRecord(e1, s));
+        TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        TRY(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1e3 * ms / kReps;
+        if (v == 0) res->default_us = us;
+        if (us < best) {
+            best = us;
+            res->block = kBlock;
+            res->order = a.order;
+            res->us = us;
         }
     }
+    record(arch, key_of(arch, kClassMultiRhs, prec, recon, g.L, nrhs), TuneChoice{res->block, res->order, res->us});
     TRY(hipStreamSynchronize(s));
 done:
     if (e0) hipEventDestroy(e0);
@@ -237,10 +328,10 @@ int tune_save(const char* path) {
         const Key& k = kv.first;
         std::fprintf(f,
                      "{\"arch\": \"%s\", \"class\": %d, \"prec\": %d, \"recon\": %d, \"dims\": [%d, %d, %d, %d], "
-                     "\"block\": %d, \"swizzle\": %d, \"us\": %.3f}\n",
+                     "\"nrhs\": %d, \"block\": %d, \"order\": %d, \"us\": %.3f}\n",
                      std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
-                     std::get<5>(k), std::get<6>(k), std::get<7>(k), kv.second.block, kv.second.swizzle,
-                     kv.second.us);
+                     std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), kv.second.block,
+                     kv.second.order, kv.second.us);
     }
     std::fclose(f);
     return TMQCD_OK;
@@ -255,18 +346,18 @@ int tune_load(const char* path) {
     int rc = TMQCD_OK;
     while (std::fgets(line, sizeof line, f)) {
         char a[64];
-        int cls, prec, recon, L[4], block, sw;
+        int cls, prec, recon, L[4], nrhs, block, sw;
         double us;
         if (std::sscanf(line,
                         "{\"arch\": \"%63[^\"]\", \"class\": %d, \"prec\": %d, \"recon\": %d, \"dims\": [%d, %d, %d, "
-                        "%d], \"block\": %d, \"swizzle\": %d, \"us\": %lf}",
-                        a, &cls, &prec, &recon, &L[0], &L[1], &L[2], &L[3], &block, &sw, &us) != 11 ||
-            (block != 128 && block != 256) || (sw != 0 && sw != 1) || cls < 0 || cls > 2 || (!arch.empty() && arch != a)) {
+                        "%d], \"nrhs\": %d, \"block\": %d, \"order\": %d, \"us\": %lf}",
+                        a, &cls, &prec, &recon, &L[0], &L[1], &L[2], &L[3], &nrhs, &block, &sw, &us) != 12 ||
+            !valid_choice(cls, nrhs, block, sw) || (!arch.empty() && arch != a)) {
             rc = TMQCD_EINVAL;
             break;
         }
         arch = a;
-        t[key_of(arch, cls, prec, recon, L)] = TuneChoice{block, sw, us};
+        t[key_of(arch, cls, prec, recon, L, nrhs)] = TuneChoice{block, sw, us};
     }
     std::fclose(f);
     if (rc != TMQCD_OK) return rc;
@@ -280,6 +371,12 @@ int tune_load(const char* path) {
 void tune_clear() {
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.clear();
+}
+
+void tune_set(const tmqcd_problem& prob, int prec, int recon, int cls, int nrhs, int block, int order) {
+    const std::string arch = current_arch();
+    const Geom g = make_geom(prob);
+    record(arch, key_of(arch, cls, prec, recon, g.L, nrhs), TuneChoice{block, order, 0.0});
 }
 
 }  // namespace tmqcd

@@ -29,7 +29,8 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg", "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force",
                 "tmqcd_gauge_force", "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune",
-                "tmqcd_tune_save", "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot",
+                "tmqcd_tune_save", "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set",
+                "tmqcd_tune_mrhs_workspace_bytes", "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot",
                 "tmqcd_error_string", "tmqcd_last_hip_error")
 
 
@@ -64,7 +65,7 @@ class CCgStats(ctypes.Structure):
 
 
 class CTuneResult(ctypes.Structure):
-    _fields_ = [("kernel_class", ctypes.c_int32), ("block", ctypes.c_int32), ("swizzle", ctypes.c_int32),
+    _fields_ = [("kernel_class", ctypes.c_int32), ("block", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("rejected", ctypes.c_int32), ("us", ctypes.c_double),
                 ("default_us", ctypes.c_double)]
 
@@ -107,6 +108,9 @@ def lib():
             "tmqcd_tune_save": (I, [ctypes.c_char_p]),
             "tmqcd_tune_load": (I, [ctypes.c_char_p]),
             "tmqcd_tune_clear": (None, []),
+            "tmqcd_tune_set": (I, [P, I, I, I, I, I, I]),
+            "tmqcd_tune_mrhs_workspace_bytes": (S, [P, I, I]),
+            "tmqcd_tune_mrhs": (I, [P, V, I, I, I, V, S, ctypes.POINTER(CTuneResult), V]),
             "tmqcd_error_string": (ctypes.c_char_p, [I]),
             "tmqcd_last_hip_error": (I, []),
         }
@@ -300,6 +304,21 @@ def tune_load(path: str):
 
 def tune_clear():
     lib().tmqcd_tune_clear()
+
+
+def tune_set(prob: Problem, prec, recon, kernel_class, block, order, nrhs=1):
+    """Pin the launch shape (block 128/256, order 0..3) of one hop class (3: multi-RHS with nrhs) for this problem."""
+    _check(lib().tmqcd_tune_set(ctypes.byref(prob.c()), prec, recon, kernel_class, nrhs, block, order),
+           "tmqcd_tune_set")
+
+
+def tune_mrhs(prob: Problem, U_packed, nrhs, prec=F64, recon=RECON18, stream=None):
+    """Tune the block order of the multi-RHS hop for nrhs right-hand sides; returns the result dict."""
+    ws = _bytes(lib().tmqcd_tune_mrhs_workspace_bytes(ctypes.byref(prob.c()), prec, nrhs))
+    res = CTuneResult()
+    _check(lib().tmqcd_tune_mrhs(ctypes.byref(prob.c()), _ptr(U_packed), prec, recon, nrhs, _ptr(ws), ws.numel(),
+                                 ctypes.byref(res), _stream(stream)), "tmqcd_tune_mrhs")
+    return res.as_dict()
 
 
 def _mom(prob: Problem, out, like):

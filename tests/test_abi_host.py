@@ -137,7 +137,7 @@ def test_tune_table_file_validation(L, tmp_path):
     assert L.tmqcd_tune_load(str(bad).encode()) == T.EINVAL
     other = tmp_path / "other.jsonl"
     other.write_text('{"arch": "gfx000", "class": 0, "prec": 0, "recon": 0, "dims": [4, 4, 4, 4], '
-                     '"block": 128, "swizzle": 1, "us": 1.000}\n')
+                     '"nrhs": 1, "block": 128, "order": 1, "us": 1.000}\n')
     assert L.tmqcd_tune_load(str(other).encode()) == T.EINVAL      # another architecture
     assert L.tmqcd_tune_load(str(tmp_path / "missing").encode()) == T.EINVAL
     prob = T.Problem((4, 4, 4, 4), 0.15, 0.0)
@@ -145,3 +145,40 @@ def test_tune_table_file_validation(L, tmp_path):
     res = (T.CTuneResult * 3)()
     assert L.tmqcd_tune(ctypes.byref(prob.c()), 1 << 30, 0, 0, None, 0, res, None) == T.EWORKSPACE
     assert L.tmqcd_tune(ctypes.byref(prob.c()), 1 << 30, 5, 0, 1 << 32, 1 << 30, res, None) == T.EINVAL
+
+
+def test_tune_set_validation_and_roundtrip(L, tmp_path):
+    prob = T.Problem((4, 4, 4, 6), 0.15, 0.0)
+    p = ctypes.byref(prob.c())
+    assert L.tmqcd_tune_set(p, 0, 0, 4, 1, 128, 1) == T.EINVAL      # no class 4
+    assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 192, 1) == T.EINVAL      # block size
+    assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 128, 4) == T.EINVAL      # order
+    assert L.tmqcd_tune_set(p, 5, 0, 0, 1, 128, 1) == T.EINVAL      # precision
+    assert L.tmqcd_tune_set(p, 0, 0, 0, 2, 128, 1) == T.EINVAL      # single-RHS class with nrhs 2
+    assert L.tmqcd_tune_set(p, 0, 0, 3, 1, 256, 1) == T.EINVAL      # multi-RHS class with nrhs 1
+    assert L.tmqcd_tune_set(p, 0, 0, 3, 17, 256, 1) == T.EINVAL     # nrhs above 16
+    assert L.tmqcd_tune_set(p, 0, 0, 3, 12, 128, 1) == T.EINVAL     # multi-RHS kernel has 256 threads
+    try:
+        assert L.tmqcd_tune_set(p, 0, 1, 2, 1, 128, 3) == T.OK
+        assert L.tmqcd_tune_set(p, 1, 0, 3, 12, 256, 2) == T.OK
+        path = tmp_path / "t.jsonl"
+        assert L.tmqcd_tune_save(str(path).encode()) == T.OK
+        lines = path.read_text().strip().splitlines()
+        assert len(lines) == 2
+        assert any('"class": 2' in l and '"nrhs": 1' in l and '"order": 3' in l for l in lines)
+        assert any('"class": 3' in l and '"nrhs": 12' in l and '"order": 2' in l for l in lines)
+        assert all('"dims": [4, 4, 4, 6]' in l for l in lines)
+        assert L.tmqcd_tune_load(str(path).encode()) == T.OK
+    finally:
+        T.tune_clear()
+
+
+def test_tune_mrhs_validation(L):
+    prob = T.Problem((4, 4, 4, 4), 0.15, 0.0)
+    p = ctypes.byref(prob.c())
+    assert L.tmqcd_tune_mrhs_workspace_bytes(p, 0, 1) == 0
+    assert L.tmqcd_tune_mrhs_workspace_bytes(p, 0, 12) > 12 * 2 * T.spinor_bytes(prob, 0, T.EVEN)
+    res = T.CTuneResult()
+    assert L.tmqcd_tune_mrhs(p, 1 << 30, 0, 0, 1, 1 << 32, 1 << 30, ctypes.byref(res), None) == T.EINVAL
+    assert L.tmqcd_tune_mrhs(p, 1 << 30, 0, 0, 12, None, 0, ctypes.byref(res), None) == T.EWORKSPACE
+    assert L.tmqcd_tune_mrhs(p, 1 << 30, 0, 0, 12, 8, 1 << 30, ctypes.byref(res), None) == T.EALIGN
