@@ -67,13 +67,19 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle residual check and CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 32^3 x 64 FP64-vs-mixed comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-RHS, batch and HMC measurements")
-    ap.add_argument("--kernel-only", action="store_true",
-                    help="only a 1 GiB copy (counter calibration) and 10 FP64 hop launches at 24^3x48, for rocprofv3 --pmc")
+    ap.add_argument("--kernel-only", nargs="?", const="hop", choices=("hop", "mrhs"),
+                    help="only a 1 GiB copy (counter calibration), the tuner and 10 launches of one kernel at 24^3x48: "
+                         "the FP64 hop (default) or the 12-RHS hop in FP64 and FP32, for rocprofv3 --pmc")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
                     help="write the hop's measured HBM traffic from two --pmc runs of --kernel-only, then exit")
+    ap.add_argument("--durations-from", nargs=3, metavar=("KERNEL_TRACE_CSV", "NAME_SUBSTRING", "LAST_N"),
+                    help="mean/min/max duration of the last N dispatches of a kernel in a rocprofv3 kernel trace")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from_counters(*args.traffic_from)
+        return
+    if args.durations_from:
+        durations_from_trace(*args.durations_from)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and this build has no "
@@ -107,8 +113,11 @@ def main():
     ws = T.workspace(prob, T.MHATDAGMHAT)
     torch.cuda.synchronize()
 
-    if args.kernel_only:
+    if args.kernel_only == "hop":
         kernel_only(T, prob, gauges, b, dev)
+        return
+    if args.kernel_only == "mrhs":
+        kernel_only_mrhs(T, prob, gauges, dev)
         return
 
     # launch shapes of the hop kernels chosen by the autotuner on this problem
@@ -257,7 +266,7 @@ def main():
         log("CPU baseline: oracle hop")
         psi = synth.gaussian_spinor(prob.volume, 27)
         with threadpool_limits(1):
-            reps = 2
+            reps = 5
             t0 = time.perf_counter()
             for _ in range(reps):
                 D.hop(U, psi, dims, (1, 1, 1, -1))
@@ -286,6 +295,30 @@ def kernel_only(T, prob, gauges, b, dev):
     print(json.dumps({"copy_bytes": a.numel(), "hop_launches": 10, "hop_block": tuned["block"],
                       "hop_order": tuned["order"], "hop_algorithmic_bytes": prob.volume // 2 * 1536,
                       "hop_source_sha": hop_source_hash()}), flush=True)
+
+
+def kernel_only_mrhs(T, prob, gauges, dev):
+    """Calibration copy, then 10 tuned 12-RHS hops (point sources) in FP64 and in FP32, RECON18."""
+    import torch
+
+    from paper_1209_5942_amd import synth
+    a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    del a, c
+    src = torch.from_numpy(synth.point_sources(prob.volume // 2, 0)).to(dev)
+    info = {"copy_bytes": 1 << 30, "launches": 10}
+    for p, name in ((T.F64, "f64"), (T.F32, "f32")):
+        g = gauges[(p, 0)]
+        s = T.pack_spinor(prob, src, p, T.EVEN, nrhs=12)
+        o = torch.empty(T.spinor_bytes(prob, p, T.ODD, 12), dtype=torch.uint8, device=dev)
+        tuned = T.tune_mrhs(prob, g, 12, p, 0)
+        for _ in range(10):
+            T.dslash(prob, g, s, T.DSLASH_OE, p, 0, nrhs=12, out=o)
+        torch.cuda.synchronize()
+        info[name] = {"order": tuned["order"], "group": tuned["group"]}
+    print(json.dumps(info), flush=True)
 
 
 def traffic_from_counters(fetch_csv, write_csv, kernel_log):
@@ -329,6 +362,18 @@ def traffic_from_counters(fetch_csv, write_csv, kernel_log):
     print(json.dumps(rec))
 
 
+def durations_from_trace(path, name, last_n):
+    """Duration statistics of the last N dispatches whose kernel name contains `name`."""
+    import csv
+    with open(path) as fh:
+        rows = [r for r in csv.DictReader(fh) if name in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[-int(last_n):]]
+    print(json.dumps({"kernel": name, "dispatches": len(d), "mean_us": round(sum(d) / len(d), 2),
+                      "min_us": round(min(d), 2), "max_us": round(max(d), 2),
+                      "workgroup_size": rows[-1]["Workgroup_Size"], "grid_size": rows[-1]["Grid_Size"]}))
+
+
 def _events_time(fn, reps, warm=3):
     import torch
     for _ in range(warm):
@@ -357,6 +402,9 @@ def bench_multi_rhs(T, prob, U, dev):
         s = T.pack_spinor(prob, src, p, T.EVEN, nrhs=12)
         o = torch.empty(T.spinor_bytes(prob, p, T.ODD, 12), dtype=torch.uint8, device=dev)
         fi, fo = T.spinor_bytes(prob, p, T.EVEN), T.spinor_bytes(prob, p, T.ODD)
+        # both sides in their tuned launch shapes
+        tuned = T.tune_mrhs(prob, g, 12, p, r)
+        T.tune(prob, g, p, r)
         t_multi = _events_time(lambda: T.dslash(prob, g, s, T.DSLASH_OE, p, r, nrhs=12, out=o), 20)
 
         def singles():
@@ -365,7 +413,9 @@ def bench_multi_rhs(T, prob, U, dev):
         t_single = _events_time(singles, 10)
         link = BYTES_PER_SITE[(p, r)] - 2 * (192 if p == T.F64 else 96)
         spin = 2 * (192 if p == T.F64 else 96)
-        out[pn] = {"multi_us": round(t_multi * 1e6, 1), "twelve_single_us": round(t_single * 1e6, 1),
+        out[pn] = {"multi_us": round(t_multi * 1e6, 1), "multi_order": tuned["order"], "multi_group": tuned["group"],
+                   "multi_default_order_us": round(tuned["default_us"], 1),
+                   "twelve_single_us": round(t_single * 1e6, 1),
                    "speedup": round(t_single / t_multi, 3),
                    "bytes_per_site_rhs": round(link / 12 + spin, 1),
                    "multi_GB_s": round(vh * (link + 12 * spin) / t_multi / 1e9, 1)}
@@ -431,25 +481,35 @@ def bench_hmc(T, synth, dev):
     t_force = _events_time(lambda: T.force(prob, h.U, X, Y, out=G), 20)
     # compulsory bytes per site: 4 links, X and Y once each, the 4 x 8 outputs
     force_bytes = prob.volume * (4 * 144 + 2 * 192 + 256)
-    dh, acc = [], 0
-    t0 = time.perf_counter()
-    for k in range(10):
-        p = torch.from_numpy(synth.gaussian_momenta(prob.volume, 1000 + k)).to(dev)
-        eta = torch.from_numpy(synth.gaussian_spinor(prob.volume, 2000 + k)).to(dev)
-        u = float(np.random.default_rng(3000 + k).random())
-        out = h.trajectory(p, eta, u, 20, 0.05)
-        dh.append(out["dH"])
-        acc += int(out["accepted"])
-    torch.cuda.synchronize()
-    t_traj = (time.perf_counter() - t0) / 10
-    e = np.exp(-np.clip(np.array(dh), -700, 700))
+    def run(n_steps):
+        dh, acc = [], 0
+        t0 = time.perf_counter()
+        for k in range(10):
+            p = torch.from_numpy(synth.gaussian_momenta(prob.volume, 1000 + k)).to(dev)
+            eta = torch.from_numpy(synth.gaussian_spinor(prob.volume, 2000 + k)).to(dev)
+            u = float(np.random.default_rng(3000 + k).random())
+            h.U.copy_(U_start)     # every trajectory from the same start: dH of one field, two step sizes
+            out = h.trajectory(p, eta, u, n_steps, 1.0 / n_steps)
+            dh.append(out["dH"])
+            acc += int(out["accepted"])
+        torch.cuda.synchronize()
+        return dh, acc / 10, (time.perf_counter() - t0) / 10
+
+    U_start = h.U.clone()
+    dh20, acc20, t_traj = run(20)
+    dh40, acc40, _ = run(40)
+    e = np.exp(-np.clip(np.array(dh20), -700, 700))
+    ratio = float(np.mean(np.abs(dh20)) / np.mean(np.abs(dh40)))
     return {"force_us": round(t_force * 1e6, 1), "force_GB_s": round(force_bytes / t_force / 1e9, 1),
-            "trajectory_s": round(t_traj, 3), "dH": [round(x, 6) for x in dh], "acceptance": acc / 10,
+            "trajectory_s": round(t_traj, 3), "dH": [round(x, 6) for x in dh20], "acceptance": acc20,
             "exp_minus_dH_mean": round(float(e.mean()), 4),
             "exp_minus_dH_stderr": round(float(e.std(ddof=1) / math.sqrt(len(e))), 4),
+            "dH_40_steps": [round(x, 6) for x in dh40], "acceptance_40_steps": acc40,
+            "mean_abs_dH_ratio_20_to_40_steps": round(ratio, 3),
             "cg_iters_per_solve": round(h.cg_iters / max(1, h.solves), 1),
-            "setup": "two-flavour twisted-mass pseudofermion action (beta = 0), leapfrog 20 x 0.05 from the "
-                     "eps 0.4 start, force solves 1e-10, acceptance solves 1e-12"}
+            "setup": "two-flavour twisted-mass pseudofermion action (beta = 0), tau = 1 leapfrog with 20 steps "
+                     "(and 40: second-order integrator, mean |dH| ratio near 4) from the eps 0.4 start, force solves "
+                     "1e-10, acceptance solves 1e-12"}
 
 
 if __name__ == "__main__":

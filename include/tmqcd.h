@@ -240,9 +240,11 @@ int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subse
  *   3  the (y, z) plane cut into square regions sized to the L2, each XCD
  *      sweeping its regions one by one through all t.
  * Kernel classes: 0 hop (+ twisted-mass own term), 1 hop + |out|^2 (CG),
- * 2 hop + CG update, 3 multi-RHS hop (256 threads: 64 sites x 4 waves; only
- * the order is tuned).  Only shapes whose output is bitwise identical to the
- * default shape's (256 threads, order 1) are admitted (for classes 1 and 2
+ * 2 hop + CG update, 3 multi-RHS hop (256 threads: 64 sites x 4 waves; the
+ * order and the number of right-hand sides a block serves are tuned: with
+ * fewer per block the lattice is swept once per group, the links are read once
+ * per group, and fewer fields compete for the L2).  Only shapes whose output is bitwise identical to the
+ * default shape's (256 threads; order 1, or 2 for class 3) are admitted (for classes 1 and 2
  * the reduction may differ by 1e-12 relative: the partial sums group
  * differently).  The fastest shape is recorded in a process-wide table keyed by
  * (GPU architecture, class, prec, recon, extents, nrhs) that later
@@ -253,6 +255,7 @@ typedef struct {
     int32_t kernel_class;  /* 0..3 as above */
     int32_t block;         /* chosen threads per block */
     int32_t order;         /* chosen block order, 0..3 as above */
+    int32_t group;         /* class 3: right-hand sides per block (0: all of them); else 0 */
     int32_t candidates;    /* shapes tried */
     int32_t rejected;      /* shapes whose output differed from the default's */
     double  us;            /* time per launch of the chosen shape */
@@ -262,7 +265,8 @@ typedef struct {
 size_t tmqcd_tune_workspace_bytes(const tmqcd_problem* prob, int prec);
 int tmqcd_tune(const tmqcd_problem* prob, const void* U_packed, int prec, int recon, void* ws,
                size_t ws_bytes, tmqcd_tune_result results[3], void* stream);
-/* Class 3 for nrhs in [2, 16] (4 orders).  ws: at least
+/* Class 3 for nrhs in [2, 16] (4 orders x groups of all, about half and
+ * about a third of the right-hand sides).  ws: at least
  * tmqcd_tune_mrhs_workspace_bytes(prob, prec, nrhs) bytes. */
 size_t tmqcd_tune_mrhs_workspace_bytes(const tmqcd_problem* prob, int prec, int nrhs);
 int tmqcd_tune_mrhs(const tmqcd_problem* prob, const void* U_packed, int prec, int recon, int nrhs, void* ws,
@@ -274,11 +278,11 @@ int tmqcd_tune_save(const char* path);
 int tmqcd_tune_load(const char* path);
 void tmqcd_tune_clear(void);
 /* Pins the shape of one class for this problem, precision and link
- * compression, as a tuning run would: classes 0..2 take nrhs = 1 and block
- * 128 or 256, class 3 takes nrhs in [2, 16] and block 256; order 0..3.
- * TMQCD_EINVAL for any other value.  Host only. */
+ * compression, as a tuning run would: classes 0..2 take nrhs = 1, block 128
+ * or 256 and group 0; class 3 takes nrhs in [2, 16], block 256 and group in
+ * [0, nrhs]; order 0..3.  TMQCD_EINVAL for any other value.  Host only. */
 int tmqcd_tune_set(const tmqcd_problem* prob, int prec, int recon, int kernel_class, int nrhs, int block,
-                   int order);
+                   int order, int group);
 
 /* ---- diagnostics ------------------------------------------------------------- */
 const char* tmqcd_error_string(int code);

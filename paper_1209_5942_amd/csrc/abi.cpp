@@ -358,11 +358,11 @@ int tmqcd_tune_load(const char* path) { return path ? tune_load(path) : TMQCD_EI
 void tmqcd_tune_clear(void) { tune_clear(); }
 
 int tmqcd_tune_set(const tmqcd_problem* prob, int prec, int recon, int kernel_class, int nrhs, int block,
-                   int order) {
+                   int order, int group) {
     if (!valid_problem(prob) || !valid_prec(prec) || !valid_recon(recon) ||
-        !valid_choice(kernel_class, nrhs, block, order))
+        !valid_choice(kernel_class, nrhs, block, order, group))
         return TMQCD_EINVAL;
-    tune_set(*prob, prec, recon, kernel_class, nrhs, block, order);
+    tune_set(*prob, prec, recon, kernel_class, nrhs, block, order, group);
     return TMQCD_OK;
 }
 

@@ -3,9 +3,10 @@
 // a CG iteration on Mhat^+ Mhat is a single grid-stride launch over the tiles
 // of all lattices, every lattice with its own solver state; lattices that have
 // converged are skipped inside the launches.  One iteration (4 hop launches,
-// 2 reduction finishes with one block per lattice, and the search-direction
-// update) can be captured once in a hipGraph and replayed between host checks,
-// which removes the per-kernel launch cost that dominates at these volumes.
+// the first tile of a lattice finishing its alpha reduction in the third, a
+// one-block-per-lattice finish of beta, and the search-direction update) can
+// be captured once in a hipGraph and replayed between host checks, which
+// removes the per-kernel launch cost that dominates at these volumes.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -109,7 +110,11 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
     auto iteration = [&]() -> hipError_t {
         hipError_t e = launch_hop_batch(k1.data(), n, kPersistentGrid, s);
         if (e == hipSuccess) e = launch_hop_batch(k2.data(), n, kPersistentGrid, s, nb.data());
-        if (e == hipSuccess) e = launch_cg_finish_batch(sp.data(), parts.data(), nb.data(), n, kFinishAlpha, s);
+        for (int i = 0; i < n; ++i) {   // each lattice's first tile of the next stage finishes alpha
+            k3[i].fin_partials = parts[i];
+            k3[i].fin_n = nb[i];
+            k3[i].fin_kind = kFinishAlpha;
+        }
         if (e == hipSuccess) e = launch_hop_batch(k3.data(), n, kPersistentGrid, s);
         if (e == hipSuccess) e = launch_hop_batch(k4.data(), n, kPersistentGrid, s, nb.data());
         if (e == hipSuccess) e = launch_cg_finish_batch(sp.data(), parts.data(), nb.data(), n, kFinishBeta, s);

@@ -241,29 +241,10 @@ struct FinishBatch {
     int n[kMaxFinish];
 };
 
+static_assert(kFinishAlpha == 0 && kFinishBeta == 1, "finish kinds as cg_finish_update numbers them");
+
 __global__ __launch_bounds__(kBlock) void cg_finish_kernel(const FinishBatch f, int kind) {
-    CgState* st = f.st[blockIdx.x];
-    if (st->done) return;
-    double tot[1];
-    sum_partials<1>(f.partials[blockIdx.x], f.n[blockIdx.x], tot);
-    if (threadIdx.x != 0) return;
-    if (kind == kFinishAlpha) {
-        const double pap = tot[0];
-        st->pAp = pap;
-        if (!(pap > 0.0) || !isfinite(pap)) st->done = kDoneBreakdown;
-        else st->alpha = st->rr / pap;
-    } else {
-        const double rr = tot[0];
-        const double rr_old = st->rr;
-        st->rr_prev = rr_old;
-        st->rr = rr;
-        st->beta = rr / rr_old;
-        const int it = st->iter + 1;
-        st->iter = it;
-        if (!isfinite(rr)) st->done = kDoneBreakdown;
-        else if (rr <= st->stop_rr || it >= st->cycle_end) st->done = kDoneStop;
-        else if (it >= st->max_iter) st->done = kDoneMaxIter;
-    }
+    cg_finish_block<kBlock>(f.st[blockIdx.x], f.partials[blockIdx.x], f.n[blockIdx.x], kind);
 }
 
 template <template <int> class F, typename... A>

@@ -68,6 +68,32 @@ struct Prec<TMQCD_F64> {
     using T = double;
 };
 
+// ------------------------------------------------------- streaming access ---
+// Links are read exactly once per hop; nontemporal loads keep them from
+// displacing the neighbour spinors that other sites will read again.
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+    if constexpr (sizeof(V) == 16) {
+        typedef int v4 __attribute__((ext_vector_type(4)));
+        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const v4*>(p)));
+    } else if constexpr (sizeof(V) == 8) {
+        typedef int v2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const v2*>(p)));
+    } else {
+        static_assert(sizeof(V) == 4, "unsupported link unit");
+        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const int*>(p)));
+    }
+}
+
+// Nontemporal store: results written once and not read again by the launch
+// (the multi-RHS outputs) stay out of the way of the spinors it still reads.
+template <typename V>
+__device__ __forceinline__ void st_stream(V* p, const V& v) {
+    static_assert(sizeof(V) == 16, "16-byte units");
+    typedef int v4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(__builtin_bit_cast(v4, v), reinterpret_cast<v4*>(p));
+}
+
 // ------------------------------------------------------- spinor site I/O ---
 // `base` points at one packed half field; `stride` is its SoA stride.
 template <int P>
@@ -84,10 +110,15 @@ struct SpinorIO<TMQCD_F64> {
             v.s[k / 3][k % 3] = {w.x, w.y};
         }
     }
+    template <bool NT = false>
     __device__ __forceinline__ static void store(char* base, int64_t stride, int64_t h, const Spinor<T>& v) {
         double2* p = reinterpret_cast<double2*>(base) + h;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) p[k * stride] = make_double2(v.s[k / 3][k % 3].re, v.s[k / 3][k % 3].im);
+        for (int k = 0; k < 12; ++k) {
+            const double2 w = make_double2(v.s[k / 3][k % 3].re, v.s[k / 3][k % 3].im);
+            if constexpr (NT) st_stream(p + k * stride, w);
+            else p[k * stride] = w;
+        }
     }
 };
 
@@ -103,12 +134,15 @@ struct SpinorIO<TMQCD_F32> {
             v.s[(2 * k + 1) / 3][(2 * k + 1) % 3] = {w.z, w.w};
         }
     }
+    template <bool NT = false>
     __device__ __forceinline__ static void store(char* base, int64_t stride, int64_t h, const Spinor<T>& v) {
         float4* p = reinterpret_cast<float4*>(base) + h;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const C<T> a = v.s[(2 * k) / 3][(2 * k) % 3], b = v.s[(2 * k + 1) / 3][(2 * k + 1) % 3];
-            p[k * stride] = make_float4(a.re, a.im, b.re, b.im);
+            const float4 w = make_float4(a.re, a.im, b.re, b.im);
+            if constexpr (NT) st_stream(p + k * stride, w);
+            else p[k * stride] = w;
         }
     }
 };
@@ -136,6 +170,7 @@ struct SpinorIO<TMQCD_F16> {
             }
         }
     }
+    template <bool NT = false>
     __device__ __forceinline__ static void store(char* base, int64_t stride, int64_t h, const Spinor<T>& v) {
         float m = 0.f;
 #pragma unroll
@@ -151,28 +186,14 @@ struct SpinorIO<TMQCD_F16> {
                 w.h[2 * j] = __float2half_rn(v.s[c / 3][c % 3].re * inv);
                 w.h[2 * j + 1] = __float2half_rn(v.s[c / 3][c % 3].im * inv);
             }
-            p[k * stride] = w.u;
+            if constexpr (NT) st_stream(p + k * stride, w.u);
+            else p[k * stride] = w.u;
         }
         reinterpret_cast<float*>(base + 48 * stride)[h] = m;
     }
 };
 
 // --------------------------------------------------------- link site I/O ---
-// Links are read exactly once per hop; nontemporal loads keep them from
-// displacing the neighbour spinors that other sites will read again.
-template <typename V>
-__device__ __forceinline__ V ld_stream(const V* p) {
-    if constexpr (sizeof(V) == 16) {
-        typedef int v4 __attribute__((ext_vector_type(4)));
-        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const v4*>(p)));
-    } else if constexpr (sizeof(V) == 8) {
-        typedef int v2 __attribute__((ext_vector_type(2)));
-        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const v2*>(p)));
-    } else {
-        static_assert(sizeof(V) == 4, "unsupported link unit");
-        return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const int*>(p)));
-    }
-}
 
 // `base` points at the whole packed gauge field; the link of direction mu whose
 // origin site has parity `par` and half index h.
@@ -390,19 +411,20 @@ __device__ __forceinline__ void block_partial(const double (&v)[N], double* part
     }
 }
 
-// Pass 2, for a block of kBlock threads: the totals, in every thread.
-template <int N>
+// Pass 2, for a block of BS threads: the totals, in every thread.
+template <int N, int BS = kBlock>
 __device__ __forceinline__ void sum_partials(const double* partials, int nblocks, double (&tot)[N]) {
+    constexpr int kW = BS / 64;
     double acc[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[i] = 0;
     // eight independent loads in flight, added in the fixed order b = tid, tid + kBlock, ...
     constexpr int kBatch = 8;
-    for (int b0 = threadIdx.x; b0 < nblocks; b0 += kBatch * kBlock) {
+    for (int b0 = threadIdx.x; b0 < nblocks; b0 += kBatch * BS) {
         double v[kBatch][N];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
-            const int b = b0 + k * kBlock;
+            const int b = b0 + k * BS;
 #pragma unroll
             for (int i = 0; i < N; ++i) v[k][i] = b < nblocks ? partials[(int64_t)b * N + i] : 0.0;
         }
@@ -411,7 +433,7 @@ __device__ __forceinline__ void sum_partials(const double* partials, int nblocks
 #pragma unroll
             for (int i = 0; i < N; ++i) acc[i] += v[k][i];
     }
-    __shared__ double sh[N][kWaves];
+    __shared__ double sh[N][kW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -423,9 +445,49 @@ __device__ __forceinline__ void sum_partials(const double* partials, int nblocks
     for (int i = 0; i < N; ++i) {
         double s = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) s += sh[i][w];
+        for (int w = 0; w < kW; ++w) s += sh[i][w];
         tot[i] = s;
     }
+}
+
+// The solver-scalar update that finishes a CG reduction (one thread):
+// kind 0 (alpha): pAp = total, alpha = rr / pAp, breakdown unless pAp > 0;
+// kind 1 (beta):  rr_prev = rr, rr = total, beta = rr / rr_prev, iter + 1 and
+// the stop tests.
+__device__ __forceinline__ void cg_finish_update(CgState* st, double total, int kind) {
+    if (kind == 0) {
+        st->pAp = total;
+        if (!(total > 0.0) || !isfinite(total)) st->done = kDoneBreakdown;
+        else st->alpha = st->rr / total;
+    } else {
+        const double rr_old = st->rr;
+        st->rr_prev = rr_old;
+        st->rr = total;
+        st->beta = total / rr_old;
+        const int it = st->iter + 1;
+        st->iter = it;
+        if (!isfinite(total)) st->done = kDoneBreakdown;
+        else if (total <= st->stop_rr || it >= st->cycle_end) st->done = kDoneStop;
+        else if (it >= st->max_iter) st->done = kDoneMaxIter;
+    }
+}
+
+// A whole block finishes a CG reduction of n partials unless the solve has
+// stopped; returns (in every thread) whether the solve is stopped afterwards.
+template <int BS>
+__device__ __forceinline__ bool cg_finish_block(CgState* st, const double* partials, int n, int kind) {
+    __shared__ int stopped;
+    if (threadIdx.x == 0) stopped = st->done;
+    __syncthreads();
+    if (stopped) return true;
+    double tot[1];
+    sum_partials<1, BS>(partials, n, tot);
+    if (threadIdx.x == 0) {
+        cg_finish_update(st, tot[0], kind);
+        stopped = st->done;
+    }
+    __syncthreads();
+    return stopped != 0;
 }
 
 }  // namespace tmqcd

@@ -8,8 +8,8 @@
 //   G^a = -2 kappa Im Tr[T^a (b+ Q1 - conj(b+) Q2)]
 //   Q1 = sum_spin [(1 - gamma_mu) U X(x+mu)] (x) Y(x)^+
 //   Q2 = sum_spin X(x) (x) [U (1 + gamma_mu) Y(x+mu)]^+
-// One thread per site computes its four links; each output is written once,
-// so no atomics are needed.  The spin projectors are applied as in the hop.
+// One thread per (site, direction); each output is written once, so no
+// atomics are needed.  The spin projectors are applied as in the hop.
 #include "device.h"
 #include "internal.h"
 
@@ -117,61 +117,12 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
     g[7] = k * (q[0][0].im + q[1][1].im - 2.0 * q[2][2].im) * 0.57735026918962576451;   // 1/sqrt(3)
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) void force_kernel(const ForceK a) {
-    const int bid = blockIdx.x;
-    const int par = bid >= a.nb_half ? 1 : 0;
-    const int h = (bid - par * a.nb_half) * kBlock + threadIdx.x;
-    if (h >= a.vh) return;
-    const int lxh = a.lxh, lx = a.L[0], ly = a.L[1], lz = a.L[2], lt = a.L[3];
-    const int xh = h % lxh;
-    int rest = h / lxh;
-    const int y = rest % ly;
-    rest /= ly;
-    const int z = rest % lz;
-    const int t = rest / lz;
-    const int bit = (par + y + z + t) & 1;
-    const int x = 2 * xh + bit;
-    const int64_t s = 2 * (int64_t)h + bit;
-
-    Spinor<double> xo, yo;
-    SpinorIO<TMQCD_F64>::load(xo, a.X + (int64_t)par * a.hbytes, a.stride, h);
-    SpinorIO<TMQCD_F64>::load(yo, a.Y + (int64_t)par * a.hbytes, a.stride, h);
-    double g[8];
-    double* o = a.out + s * 32;
-    {
-        const int xf = x + 1 == lx ? 0 : x + 1;
-        force_dir<R, 0>(a, par, h, (h - xh) + (xf >> 1), x == lx - 1, xo, yo, g);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) o[i] = a.accumulate ? o[i] + a.scale * g[i] : a.scale * g[i];
-    }
-    {
-        const int nf = y == ly - 1 ? h - (ly - 1) * lxh : h + lxh;
-        force_dir<R, 1>(a, par, h, nf, y == ly - 1, xo, yo, g);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) o[8 + i] = a.accumulate ? o[8 + i] + a.scale * g[i] : a.scale * g[i];
-    }
-    {
-        const int st = lxh * ly;
-        const int nf = z == lz - 1 ? h - (lz - 1) * st : h + st;
-        force_dir<R, 2>(a, par, h, nf, z == lz - 1, xo, yo, g);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) o[16 + i] = a.accumulate ? o[16 + i] + a.scale * g[i] : a.scale * g[i];
-    }
-    {
-        const int st = lxh * ly * lz;
-        const int nf = t == lt - 1 ? h - (lt - 1) * st : h + st;
-        force_dir<R, 3>(a, par, h, nf, t == lt - 1, xo, yo, g);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) o[24 + i] = a.accumulate ? o[24 + i] + a.scale * g[i] : a.scale * g[i];
-    }
-}
-
-// The same force with four times the parallelism: a block covers 64 sites and
-// its wave w computes direction w (a wave-uniform branch), so each thread
-// holds one direction's operands.  The four waves read the same X(x), Y(x)
-// (cache hits after the first).  Launch bounds ask for two waves per SIMD
-// (at most 256 registers; the kernel does not spill).
+// A block covers 64 sites and its wave w computes direction w (a wave-uniform
+// branch), so each thread holds one direction's operands; the four waves read
+// the same X(x), Y(x) (cache hits after the first).  Launch bounds ask for two
+// waves per SIMD (at most 256 registers; the kernel does not spill).  Holding
+// all four directions per thread needed 260 registers, one wave per SIMD, and
+// ran 14 % slower.
 template <int R>
 __global__ __launch_bounds__(kBlock, 2) void force_dir_kernel(const ForceK a) {
     const int bid = blockIdx.x;

@@ -13,7 +13,11 @@ template <int P, int R, bool DAG, bool OWN, int EPI, int PV, int BS>
 __global__ __launch_bounds__(BS) void hop_kernel(const HopK a) {
     static_assert(std::is_same<typename Prec<P>::T, typename Prec<PV>::T>::value,
                   "vector and dslash compute types differ");
-    if (a.st != nullptr && a.st->done) return;   // a solver stage queued after its stop
+    if (a.fin_n > 0 && blockIdx.x == 0) {
+        if (cg_finish_block<BS>(a.st, a.fin_partials, a.fin_n, a.fin_kind)) return;
+    } else if (a.st != nullptr && a.st->done) {
+        return;   // a solver stage queued after its stop
+    }
     int par, h;
     const bool valid = block_site(a, blockIdx.x, threadIdx.x, par, h);
     const double red = valid ? hop_site<P, R, DAG, OWN, EPI, PV>(a, par, h) : 0.0;
@@ -72,14 +76,17 @@ int hop_blocks(const Geom& g, int nparity) {
 
 hipError_t launch_hop(const HopParams& a_in, hipStream_t s, int* nblocks) {
     HopParams a = a_in;
-    if (a.block == 0) {   // not chosen by the caller: the tuned choice, else 256 threads with the XCD remap
+    if (a.block == 0) {   // not chosen by the caller: the tuned choice, else the default shape
         TuneChoice t;
         if (tune_lookup(a, &t)) {
             a.block = t.block;
             a.order = t.order;
+            a.group = t.group;
         } else {
+            // 256 threads; the multi-RHS kernel in t-slab order (its 12 fields per site need the
+            // t-neighbours in flight), the others remapped per XCD
             a.block = 256;
-            a.order = kOrderXcdRemap;
+            a.order = a.nrhs > 1 ? kOrderSlab : kOrderXcdRemap;
         }
     }
     if (a.block != 128 && a.block != 256) return hipErrorInvalidValue;

@@ -22,7 +22,11 @@ __global__ __launch_bounds__(kBlock) void hop_batch_kernel(const HopBatch b) {
         int i = 0;
         while (tile >= b.tile_start[i + 1]) ++i;
         const HopK& a = b.lat[i];
-        if (a.st != nullptr && a.st->done) continue;
+        if (a.fin_n > 0 && tile == b.tile_start[i]) {   // the lattice's first tile finishes its reduction
+            if (cg_finish_block<kBlock>(a.st, a.fin_partials, a.fin_n, a.fin_kind)) continue;
+        } else if (a.st != nullptr && a.st->done) {
+            continue;
+        }
         const int lt = tile - b.tile_start[i];
         int par, h;
         const bool valid = block_site(a, lt, threadIdx.x, par, h);

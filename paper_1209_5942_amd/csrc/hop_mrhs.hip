@@ -5,12 +5,15 @@ namespace tmqcd {
 namespace stencil {
 namespace {
 
-// Multi-RHS hop: a block owns 64 output sites; its four waves first copy the
-// eight links of those sites into LDS (each link read from HBM once), then
-// loop over the right-hand sides, wave w handling rhs w, w+4, w+8, ...
+// Multi-RHS hop: a block owns 64 output sites and a group of right-hand sides;
+// its four waves first copy the eight links of those sites into LDS (read from
+// HBM once per group), then loop over the group, wave w handling its rhs w,
+// w+4, w+8, ...  Blocks [g*tiles, (g+1)*tiles) serve group g, so the whole
+// lattice is swept once per group: fewer fields in flight per sweep keep more
+// of their t-neighbours in the L2, at the price of re-reading the links.
 // Fields of consecutive right-hand sides are `*_fstride` bytes apart.
 struct MrhsK {
-    int nrhs;
+    int nrhs, group, tiles;
     int64_t in_fstride, own_fstride, out_fstride;
 };
 
@@ -22,8 +25,9 @@ __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const Mr
     constexpr int NU = LIO::kUnits;
     __shared__ Unit tile[8 * NU * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = blockIdx.x / m.tiles;
     int par, h;
-    const bool valid = block_site(a, blockIdx.x, lane, par, h);
+    const bool valid = block_site(a, blockIdx.x - g * m.tiles, lane, par, h);
     const bool two = a.nparity == 2;
     Nbr n;
     if (valid) {
@@ -48,8 +52,9 @@ __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const Mr
     const C<T> cuh = cvt<T>(a.cu_hop), cdh = cvt<T>(a.cd_hop);
     const int64_t hoff = two ? (int64_t)par * a.hbytes : 0;
     const int64_t ioff = two ? (int64_t)(1 - par) * a.hbytes : 0;
+    const int rend = min(m.nrhs, (g + 1) * m.group);
 #pragma unroll 1
-    for (int r = wave; r < m.nrhs; r += kWaves) {
+    for (int r = g * m.group + wave; r < rend; r += kWaves) {
         // The link reads from the tile do not depend on r; without this barrier
         // the compiler hoists all eight links out of the loop into registers.
         __asm__ volatile("" ::: "memory");
@@ -89,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const Mr
                 acc.s[3][c] = acc.s[3][c] + cdo * o.s[3][c];
             }
         }
-        SpinorIO<P>::store(a.out + r * m.out_fstride + hoff, a.stride, h, acc);
+        SpinorIO<P>::template store<true>(a.out + r * m.out_fstride + hoff, a.stride, h, acc);
     }
 }
 
@@ -97,11 +102,13 @@ template <int P, int R>
 hipError_t launch_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
     MrhsK m;
     m.nrhs = a.nrhs;
+    m.group = a.group > 0 && a.group < a.nrhs ? a.group : a.nrhs;
+    m.tiles = k.nblocks;
     m.in_fstride = a.in_fstride;
     m.own_fstride = a.own_fstride;
     m.out_fstride = a.out_fstride;
     const bool own = a.own != nullptr;
-    const dim3 grid(k.nblocks), block(kBlock);
+    const dim3 grid(k.nblocks * ((m.nrhs + m.group - 1) / m.group)), block(kBlock);
     if (!a.dag && !own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, false>), grid, block, 0, s, k, m);
     else if (a.dag && !own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, false>), grid, block, 0, s, k, m);
     else if (!a.dag && own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, true>), grid, block, 0, s, k, m);

@@ -49,9 +49,15 @@ struct HopParams {
     // several right-hand sides (epi == kEpiStore): fields nrhs apart by these byte strides
     int nrhs;
     int64_t in_fstride, own_fstride, out_fstride;
-    // launch shape: block 128 or 256 threads and the block order (kOrder*); block = 0 takes the tuned choice
+    // launch shape: block 128 or 256 threads and the block order (kOrder*); block = 0 takes the tuned choice;
+    // group: right-hand sides per block of the multi-RHS kernel (0: all)
     int block;
     int order;
+    int group;
+    // fin_n > 0: block 0 first finishes the CG reduction of the previous launch (fin_n partials,
+    // kind fin_kind of launch_cg_finish) on st
+    const double* fin_partials;
+    int fin_n, fin_kind;
 };
 
 // Block orders of the hop launches (which sites a block covers, see block_site in stencil.h).
@@ -65,6 +71,7 @@ constexpr int kClassMultiRhs = 3;
 struct TuneChoice {
     int block;
     int order;
+    int group;   // multi-RHS class: right-hand sides per block (0: all)
     double us;
 };
 // the tuned launch shape for this hop (class from epi, or the multi-RHS class with its nrhs)

@@ -7,19 +7,19 @@
 // the upper two spins as (1 - i w) and on the lower two as (1 + i w).  The
 // adjoints use H^+ (gamma_mu -> -gamma_mu) and A^+ = A(-mu).
 //
-// One CG iteration on Mhat^+ Mhat is four hop launches, two one-block
-// reduction finishes and one BLAS launch:
+// One CG iteration on Mhat^+ Mhat is four hop launches, a one-block
+// reduction finish and one BLAS launch:
 //   t1 = A^{-1} H_oe p
 //   t2 = A p - kappa^2 H_eo t1                 and per-block sums of |t2|^2
-//   finish: p^+ A p = |t2|^2, alpha
-//   t3 = A(-mu)^{-1} H^+_oe t2
+//   t3 = A(-mu)^{-1} H^+_oe t2                 its block 0 first finishes
+//                                               p^+ A p = |t2|^2 and alpha
 //   (A p) = A(-mu) t2 - kappa^2 H^+_eo t3      fused with x += alpha p,
 //                                               r -= alpha A p, per-block |r|^2
 //   finish: |r|^2, beta, stop tests
 //   p = r + beta p
-// The reductions finish in a launch of their own: a last-block-done scheme
-// would need a device-wide release in every block, which on this chip writes
-// back the XCD's L2 and costs more than the extra launch.
+// The reductions finish in a later launch: a last-block-done scheme would
+// need a device-wide release in every block, which on this chip writes back
+// the XCD's L2 and costs more than a launch.
 // All scalars stay on the device; the host queues several iterations, then
 // reads the state once.  Kernels queued after convergence return at once.
 #include <algorithm>
@@ -311,7 +311,10 @@ hipError_t queue_iteration(const OpCtx& c, bool full, const Fields& f, CgState* 
             e = launch_hop(hp_schur_second(c, f.t1, f.p, f.t2, false, kEpiStoreNorm, st, partials, nullptr, nullptr,
                                            nullptr, kOne),
                            c.s, &nb);
-        if (e == hipSuccess) e = launch_cg_finish(st, partials, nb, kFinishAlpha, c.s);
+        // the first block of the next hop finishes p^+ A p and alpha (the update hop after it needs alpha)
+        k3.fin_partials = partials;
+        k3.fin_n = nb;
+        k3.fin_kind = kFinishAlpha;
         if (e == hipSuccess) e = launch_hop(k3, c.s);
         if (e == hipSuccess)
             e = launch_hop(hp_schur_second(c, f.t3, f.t2, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p,

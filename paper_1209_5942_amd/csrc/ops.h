@@ -62,8 +62,8 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
 int tune_save(const char* path);
 int tune_load(const char* path);
 void tune_clear();
-void tune_set(const tmqcd_problem& prob, int prec, int recon, int cls, int nrhs, int block, int order);
-bool valid_choice(int cls, int nrhs, int block, int order);
+void tune_set(const tmqcd_problem& prob, int prec, int recon, int cls, int nrhs, int block, int order, int group);
+bool valid_choice(int cls, int nrhs, int block, int order, int group);
 int64_t tune_mrhs_workspace_bytes(const Geom& g, int prec, int nrhs);
 int run_tune_mrhs(const tmqcd_problem& prob, const void* gauge, int prec, int recon, int nrhs, void* ws,
                   hipStream_t s, tmqcd_tune_result* res);

@@ -72,6 +72,8 @@ struct HopK {
     int order, width;        // block order (kOrder*) and output sites per block
     int slice, q, tq, lt;    // slab order: half sites per t-slice, per XCD range, blocks per range
     int by, bz, nry, nreg;   // column order: region extent in y and z, regions in y, regions
+    const double* fin_partials;   // the previous launch's reduction, finished by block 0 first
+    int fin_n, fin_kind;
     C<double> bc[4];
     C<double> cu_own, cd_own, cu_hop, cd_hop;
 };
@@ -364,6 +366,9 @@ inline HopK make_hopk(const HopParams& a, int w) {
     k.vh = (int)a.g.vh;
     k.order = a.order;
     k.width = w;
+    k.fin_partials = a.fin_partials;
+    k.fin_n = a.fin_n;
+    k.fin_kind = a.fin_kind;
     k.lt = a.g.L[3];
     k.slice = (int)(a.g.vh / a.g.L[3]);
     k.q = (k.slice + kNumXcd - 1) / kNumXcd;

@@ -60,10 +60,10 @@ void record(const std::string& arch, const Key& key, const TuneChoice& c) {
 
 }  // namespace
 
-bool valid_choice(int cls, int nrhs, int block, int order) {
+bool valid_choice(int cls, int nrhs, int block, int order, int group) {
     if (order < 0 || order >= kNumOrders) return false;
-    if (cls >= 0 && cls < kClassMultiRhs) return nrhs == 1 && (block == 128 || block == 256);
-    return cls == kClassMultiRhs && nrhs >= 2 && nrhs <= kMaxRhs && block == kBlock;
+    if (cls >= 0 && cls < kClassMultiRhs) return nrhs == 1 && (block == 128 || block == 256) && group == 0;
+    return cls == kClassMultiRhs && nrhs >= 2 && nrhs <= kMaxRhs && block == kBlock && group >= 0 && group <= nrhs;
 }
 
 bool tune_lookup(const HopParams& a, TuneChoice* out) {
@@ -234,7 +234,7 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
                 res.us = us;
             }
         }
-        record(arch, key_of(arch, cls, prec, recon, g.L, 1), TuneChoice{res.block, res.order, res.us});
+        record(arch, key_of(arch, cls, prec, recon, g.L, 1), TuneChoice{res.block, res.order, 0, res.us});
     }
     TRY(hipStreamSynchronize(s));
 done:
@@ -263,7 +263,9 @@ int run_tune_mrhs(const tmqcd_problem& prob, const void* gauge, int prec, int re
     char* ref = out + nrhs * hd;
     const OpCtx c = make_ctx(prob, prec, recon, gauge, s);
     const VecSpec vs{&g, 1};
-    const int orders[kNumOrders] = {kOrderXcdRemap, kOrderLinear, kOrderSlab, kOrderColumn};   // first: default
+    const int orders[kNumOrders] = {kOrderSlab, kOrderLinear, kOrderXcdRemap, kOrderColumn};   // first: default
+    // right-hand sides per block: all (the default), about a half, about a third
+    const int groups[3] = {0, (nrhs + 1) / 2, (nrhs + 2) / 3};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const std::string arch = current_arch();
     double best = 1e30;
@@ -272,10 +274,13 @@ int run_tune_mrhs(const tmqcd_problem& prob, const void* gauge, int prec, int re
     TRY(hipEventCreate(&e0));
     TRY(hipEventCreate(&e1));
     for (int r = 0; r < nrhs; ++r) TRY(launch_fill(vs, in + r * hd, prec, 21u + r, s));
-    for (int v = 0; v < kNumOrders; ++v) {
+    for (int v = 0; v < 3 * kNumOrders; ++v) {
+        const int gi = v / kNumOrders;
+        if (gi > 0 && (groups[gi] >= nrhs || groups[gi] == groups[gi - 1])) continue;   // same as a shape tried
         HopParams a = hp_schur_first(c, in, out, false, Rhs{nrhs, hd, 0, hd});
         a.block = kBlock;
-        a.order = orders[v];
+        a.order = orders[v % kNumOrders];
+        a.group = groups[gi];
         TRY(launch_hop(a, s));
         bool ok = true;
         if (v == 0) {
@@ -307,10 +312,11 @@ int run_tune_mrhs(const tmqcd_problem& prob, const void* gauge, int prec, int re
             best = us;
             res->block = kBlock;
             res->order = a.order;
+            res->group = a.group;
             res->us = us;
         }
     }
-    record(arch, key_of(arch, kClassMultiRhs, prec, recon, g.L, nrhs), TuneChoice{res->block, res->order, res->us});
+    record(arch, key_of(arch, kClassMultiRhs, prec, recon, g.L, nrhs), TuneChoice{res->block, res->order, res->group, res->us});
     TRY(hipStreamSynchronize(s));
 done:
     if (e0) hipEventDestroy(e0);
@@ -328,10 +334,10 @@ int tune_save(const char* path) {
         const Key& k = kv.first;
         std::fprintf(f,
                      "{\"arch\": \"%s\", \"class\": %d, \"prec\": %d, \"recon\": %d, \"dims\": [%d, %d, %d, %d], "
-                     "\"nrhs\": %d, \"block\": %d, \"order\": %d, \"us\": %.3f}\n",
+                     "\"nrhs\": %d, \"block\": %d, \"order\": %d, \"group\": %d, \"us\": %.3f}\n",
                      std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
                      std::get<5>(k), std::get<6>(k), std::get<7>(k), std::get<8>(k), kv.second.block,
-                     kv.second.order, kv.second.us);
+                     kv.second.order, kv.second.group, kv.second.us);
     }
     std::fclose(f);
     return TMQCD_OK;
@@ -346,18 +352,18 @@ int tune_load(const char* path) {
     int rc = TMQCD_OK;
     while (std::fgets(line, sizeof line, f)) {
         char a[64];
-        int cls, prec, recon, L[4], nrhs, block, sw;
+        int cls, prec, recon, L[4], nrhs, block, sw, group;
         double us;
         if (std::sscanf(line,
                         "{\"arch\": \"%63[^\"]\", \"class\": %d, \"prec\": %d, \"recon\": %d, \"dims\": [%d, %d, %d, "
-                        "%d], \"nrhs\": %d, \"block\": %d, \"order\": %d, \"us\": %lf}",
-                        a, &cls, &prec, &recon, &L[0], &L[1], &L[2], &L[3], &nrhs, &block, &sw, &us) != 12 ||
-            !valid_choice(cls, nrhs, block, sw) || (!arch.empty() && arch != a)) {
+                        "%d], \"nrhs\": %d, \"block\": %d, \"order\": %d, \"group\": %d, \"us\": %lf}",
+                        a, &cls, &prec, &recon, &L[0], &L[1], &L[2], &L[3], &nrhs, &block, &sw, &group, &us) != 13 ||
+            !valid_choice(cls, nrhs, block, sw, group) || (!arch.empty() && arch != a)) {
             rc = TMQCD_EINVAL;
             break;
         }
         arch = a;
-        t[key_of(arch, cls, prec, recon, L, nrhs)] = TuneChoice{block, sw, us};
+        t[key_of(arch, cls, prec, recon, L, nrhs)] = TuneChoice{block, sw, group, us};
     }
     std::fclose(f);
     if (rc != TMQCD_OK) return rc;
@@ -373,10 +379,10 @@ void tune_clear() {
     g_table.clear();
 }
 
-void tune_set(const tmqcd_problem& prob, int prec, int recon, int cls, int nrhs, int block, int order) {
+void tune_set(const tmqcd_problem& prob, int prec, int recon, int cls, int nrhs, int block, int order, int group) {
     const std::string arch = current_arch();
     const Geom g = make_geom(prob);
-    record(arch, key_of(arch, cls, prec, recon, g.L, nrhs), TuneChoice{block, order, 0.0});
+    record(arch, key_of(arch, cls, prec, recon, g.L, nrhs), TuneChoice{block, order, group, 0.0});
 }
 
 }  // namespace tmqcd

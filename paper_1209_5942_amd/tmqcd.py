@@ -66,8 +66,8 @@ class CCgStats(ctypes.Structure):
 
 class CTuneResult(ctypes.Structure):
     _fields_ = [("kernel_class", ctypes.c_int32), ("block", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("rejected", ctypes.c_int32), ("us", ctypes.c_double),
-                ("default_us", ctypes.c_double)]
+                ("group", ctypes.c_int32), ("candidates", ctypes.c_int32), ("rejected", ctypes.c_int32),
+                ("us", ctypes.c_double), ("default_us", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,7 +108,7 @@ def lib():
             "tmqcd_tune_save": (I, [ctypes.c_char_p]),
             "tmqcd_tune_load": (I, [ctypes.c_char_p]),
             "tmqcd_tune_clear": (None, []),
-            "tmqcd_tune_set": (I, [P, I, I, I, I, I, I]),
+            "tmqcd_tune_set": (I, [P, I, I, I, I, I, I, I]),
             "tmqcd_tune_mrhs_workspace_bytes": (S, [P, I, I]),
             "tmqcd_tune_mrhs": (I, [P, V, I, I, I, V, S, ctypes.POINTER(CTuneResult), V]),
             "tmqcd_error_string": (ctypes.c_char_p, [I]),
@@ -306,9 +306,9 @@ def tune_clear():
     lib().tmqcd_tune_clear()
 
 
-def tune_set(prob: Problem, prec, recon, kernel_class, block, order, nrhs=1):
-    """Pin the launch shape (block 128/256, order 0..3) of one hop class (3: multi-RHS with nrhs) for this problem."""
-    _check(lib().tmqcd_tune_set(ctypes.byref(prob.c()), prec, recon, kernel_class, nrhs, block, order),
+def tune_set(prob: Problem, prec, recon, kernel_class, block, order, nrhs=1, group=0):
+    """Pin the launch shape (block 128/256, order 0..3; class 3: multi-RHS with nrhs and group) for this problem."""
+    _check(lib().tmqcd_tune_set(ctypes.byref(prob.c()), prec, recon, kernel_class, nrhs, block, order, group),
            "tmqcd_tune_set")
 
 

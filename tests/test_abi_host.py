@@ -137,7 +137,7 @@ def test_tune_table_file_validation(L, tmp_path):
     assert L.tmqcd_tune_load(str(bad).encode()) == T.EINVAL
     other = tmp_path / "other.jsonl"
     other.write_text('{"arch": "gfx000", "class": 0, "prec": 0, "recon": 0, "dims": [4, 4, 4, 4], '
-                     '"nrhs": 1, "block": 128, "order": 1, "us": 1.000}\n')
+                     '"nrhs": 1, "block": 128, "order": 1, "group": 0, "us": 1.000}\n')
     assert L.tmqcd_tune_load(str(other).encode()) == T.EINVAL      # another architecture
     assert L.tmqcd_tune_load(str(tmp_path / "missing").encode()) == T.EINVAL
     prob = T.Problem((4, 4, 4, 4), 0.15, 0.0)
@@ -150,23 +150,25 @@ def test_tune_table_file_validation(L, tmp_path):
 def test_tune_set_validation_and_roundtrip(L, tmp_path):
     prob = T.Problem((4, 4, 4, 6), 0.15, 0.0)
     p = ctypes.byref(prob.c())
-    assert L.tmqcd_tune_set(p, 0, 0, 4, 1, 128, 1) == T.EINVAL      # no class 4
-    assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 192, 1) == T.EINVAL      # block size
-    assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 128, 4) == T.EINVAL      # order
-    assert L.tmqcd_tune_set(p, 5, 0, 0, 1, 128, 1) == T.EINVAL      # precision
-    assert L.tmqcd_tune_set(p, 0, 0, 0, 2, 128, 1) == T.EINVAL      # single-RHS class with nrhs 2
-    assert L.tmqcd_tune_set(p, 0, 0, 3, 1, 256, 1) == T.EINVAL      # multi-RHS class with nrhs 1
-    assert L.tmqcd_tune_set(p, 0, 0, 3, 17, 256, 1) == T.EINVAL     # nrhs above 16
-    assert L.tmqcd_tune_set(p, 0, 0, 3, 12, 128, 1) == T.EINVAL     # multi-RHS kernel has 256 threads
+    assert L.tmqcd_tune_set(p, 0, 0, 4, 1, 128, 1, 0) == T.EINVAL      # no class 4
+    assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 192, 1, 0) == T.EINVAL      # block size
+    assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 128, 4, 0) == T.EINVAL      # order
+    assert L.tmqcd_tune_set(p, 5, 0, 0, 1, 128, 1, 0) == T.EINVAL      # precision
+    assert L.tmqcd_tune_set(p, 0, 0, 0, 2, 128, 1, 0) == T.EINVAL      # single-RHS class with nrhs 2
+    assert L.tmqcd_tune_set(p, 0, 0, 3, 1, 256, 1, 0) == T.EINVAL      # multi-RHS class with nrhs 1
+    assert L.tmqcd_tune_set(p, 0, 0, 3, 17, 256, 1, 0) == T.EINVAL     # nrhs above 16
+    assert L.tmqcd_tune_set(p, 0, 0, 3, 12, 128, 1, 0) == T.EINVAL     # multi-RHS kernel has 256 threads
+    assert L.tmqcd_tune_set(p, 0, 0, 3, 12, 256, 1, 13) == T.EINVAL    # group above nrhs
+    assert L.tmqcd_tune_set(p, 0, 0, 1, 1, 256, 1, 2) == T.EINVAL      # group on a single-RHS class
     try:
-        assert L.tmqcd_tune_set(p, 0, 1, 2, 1, 128, 3) == T.OK
-        assert L.tmqcd_tune_set(p, 1, 0, 3, 12, 256, 2) == T.OK
+        assert L.tmqcd_tune_set(p, 0, 1, 2, 1, 128, 3, 0) == T.OK
+        assert L.tmqcd_tune_set(p, 1, 0, 3, 12, 256, 2, 6) == T.OK
         path = tmp_path / "t.jsonl"
         assert L.tmqcd_tune_save(str(path).encode()) == T.OK
         lines = path.read_text().strip().splitlines()
         assert len(lines) == 2
         assert any('"class": 2' in l and '"nrhs": 1' in l and '"order": 3' in l for l in lines)
-        assert any('"class": 3' in l and '"nrhs": 12' in l and '"order": 2' in l for l in lines)
+        assert any('"class": 3' in l and '"nrhs": 12' in l and '"order": 2' in l and '"group": 6' in l for l in lines)
         assert all('"dims": [4, 4, 4, 6]' in l for l in lines)
         assert L.tmqcd_tune_load(str(path).encode()) == T.OK
     finally:

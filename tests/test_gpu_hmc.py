@@ -5,6 +5,7 @@
 * a whole leapfrog trajectory (same links, momenta, eta and Metropolis draw)
   compared with the oracle's trajectory: dH and the proposed links;
 * reversibility of the GPU leapfrog;
+* the Creutz equality <exp(-dH)> = 1 on a 4^4 Markov chain after burn-in;
 * on 16^3 x 32 (eps 0.4, kappa 0.155, mu 0.01, Gaussian phi): the gradient
   returned by FermionAction's backward pass (the force kernel) against central
   finite differences along all eight generators on 64 random links, with the
@@ -138,3 +139,28 @@ def test_fermion_force_vs_finite_differences_16x16x16x32():
             err = abs(diff / (2 * hstep) - G[site, m, a]) / scale
             worst = max(worst, err)
     assert worst < 1e-7, worst
+
+
+@pytest.mark.timeout(600)
+def test_creutz_equality_in_equilibrium_4x4x4x4():
+    """<exp(-dH)> = 1 holds for a reversible, area-preserving integrator when (U, p, phi) follow
+    exp(-H): a 4^4 chain (beta 5.5, kappa 0.15, mu 0.01, tau 0.5 in 10 steps) after 40 burn-in
+    trajectories, averaged over 160 more."""
+    dims = (4, 4, 4, 4)
+    prob = T.Problem(dims, 0.15, 0.01, BC_AP)
+    h = H.HMC(prob, dev(synth.random_links(dims, 0.3, 601).reshape(-1, 4, 3, 3)), beta=5.5, tol=1e-12,
+              md_tol=1e-10)
+    rng = np.random.default_rng(602)
+    dh, acc = [], 0
+    for k in range(200):
+        p = dev(synth.gaussian_momenta(prob.volume, 10000 + k))
+        eta = dev(synth.gaussian_spinor(prob.volume, 20000 + k))
+        out = h.trajectory(p, eta, float(rng.random()), 10, 0.05)
+        if k >= 40:
+            dh.append(out["dH"])
+            acc += int(out["accepted"])
+    e = np.exp(-np.array(dh))
+    mean, err = e.mean(), e.std(ddof=1) / np.sqrt(len(e))
+    assert acc / len(dh) > 0.5
+    assert err < 0.05
+    assert abs(mean - 1.0) < 4 * err, (mean, err)

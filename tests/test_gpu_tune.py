@@ -89,15 +89,16 @@ def test_pinned_shapes_match_oracle(block, order, dims, bc):
         T.tune_clear()
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
+@pytest.mark.parametrize("order,group", [(0, 0), (1, 0), (2, 0), (3, 0), (2, 5), (3, 4)])
 @pytest.mark.parametrize("dims,bc", [((12, 6, 4, 10), BC_TWIST), ((4, 4, 8, 8), BC_AP)])
-def test_pinned_multi_rhs_orders_match_oracle(order, dims, bc):
-    """The multi-RHS kernel in every block order: 12 Gaussian fields through M (both parities) and Mhat^dag Mhat."""
+def test_pinned_multi_rhs_orders_match_oracle(order, group, dims, bc):
+    """The multi-RHS kernel in every block order and with rhs groups (5 per block: 5 + 5 + 2): 12 Gaussian
+    fields through M (both parities) and Mhat^dag Mhat."""
     f = Fields(dims, 0.5, 531, 0.16, 0.02, bc)
     try:
         T.tune_clear()
         for prec in (T.F64, T.F32):
-            T.tune_set(f.prob, prec, T.RECON18, 3, 256, order, nrhs=12)
+            T.tune_set(f.prob, prec, T.RECON18, 3, 256, order, nrhs=12, group=group)
         for op in (T.M, T.MHATDAGMHAT):
             sub_in, sub_out = T.OP_SUBSETS[op]
             src = f.spinor(sub_in, 532 + op, nrhs=12)
@@ -121,8 +122,9 @@ def test_tune_mrhs_admits_equal_orders_and_keeps_results():
         T.tune_clear()
         before = host(T.dslash(f.prob, g, inp, T.MHATDAGMHAT, nrhs=12))
         r = T.tune_mrhs(f.prob, g, 12)
-        assert r["kernel_class"] == 3 and r["candidates"] == 4 and r["rejected"] == 0
-        assert r["block"] == 256 and r["order"] in (0, 1, 2, 3) and 0 < r["us"] <= r["default_us"] * 1.0001
+        assert r["kernel_class"] == 3 and r["candidates"] == 12 and r["rejected"] == 0
+        assert r["block"] == 256 and r["order"] in (0, 1, 2, 3) and r["group"] in (0, 6, 4)
+        assert 0 < r["us"] <= r["default_us"] * 1.0001
         after = host(T.dslash(f.prob, g, inp, T.MHATDAGMHAT, nrhs=12))
         assert np.array_equal(before, after)
     finally:
