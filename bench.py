@@ -74,12 +74,18 @@ def main():
                     help="write the hop's measured HBM traffic from two --pmc runs of --kernel-only, then exit")
     ap.add_argument("--durations-from", nargs=3, metavar=("KERNEL_TRACE_CSV", "NAME_SUBSTRING", "LAST_N"),
                     help="mean/min/max duration of the last N dispatches of a kernel in a rocprofv3 kernel trace")
+    ap.add_argument("--counters-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "NAME_SUBSTRING", "LAST_N"),
+                    help="HBM bytes of the last N dispatches of a kernel from two --pmc runs, scaled by the "
+                         "first copy kernel of each run (1 GiB)")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from_counters(*args.traffic_from)
         return
     if args.durations_from:
         durations_from_trace(*args.durations_from)
+        return
+    if args.counters_from:
+        counters_from(*args.counters_from)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and this build has no "
@@ -362,6 +368,50 @@ def traffic_from_counters(fetch_csv, write_csv, kernel_log):
     print(json.dumps(rec))
 
 
+def creutz_4x4x4x4(T, synth, dev):
+    """<exp(-dH)> over a 4^4 Markov chain (beta 5.5, kappa 0.15, mu 0.01, tau 0.5 in 10 steps) after burn-in."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1209_5942_amd.hmc import HMC
+    log("Creutz equality on 4^4")
+    dims = (4, 4, 4, 4)
+    prob = T.Problem(dims, 0.15, 0.01, (1, 1, 1, -1))
+    h = HMC(prob, torch.from_numpy(synth.random_links(dims, 0.3, 601).reshape(-1, 4, 3, 3)).to(dev), beta=5.5,
+            tol=1e-12, md_tol=1e-10)
+    rng = np.random.default_rng(602)
+    dh, acc = [], 0
+    for k in range(200):
+        p = torch.from_numpy(synth.gaussian_momenta(prob.volume, 10000 + k)).to(dev)
+        eta = torch.from_numpy(synth.gaussian_spinor(prob.volume, 20000 + k)).to(dev)
+        out = h.trajectory(p, eta, float(rng.random()), 10, 0.05)
+        if k >= 40:
+            dh.append(out["dH"])
+            acc += int(out["accepted"])
+    e = np.exp(-np.array(dh))
+    return {"exp_minus_dH_mean": round(float(e.mean()), 4),
+            "exp_minus_dH_stderr": round(float(e.std(ddof=1) / math.sqrt(len(e))), 4),
+            "acceptance": round(acc / len(dh), 3), "trajectories": len(dh), "burn_in": 40}
+
+
+def counters_from(fetch_csv, write_csv, name, last_n):
+    """Mean FETCH_SIZE and WRITE_SIZE bytes of the last N dispatches of a kernel, calibrated by the 1 GiB copy."""
+    import csv
+    out = {"kernel": name}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        with open(path) as fh:
+            rows = sorted((r for r in csv.DictReader(fh) if r["Counter_Name"] == counter),
+                          key=lambda r: int(r["Dispatch_Id"]))
+        copy = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer")][0]
+        factor = (1 << 30) / 1024.0 / copy
+        v = [float(r["Counter_Value"]) for r in rows if name in r["Kernel_Name"]][-int(last_n):]
+        out[counter] = {"factor": round(factor, 4), "dispatches": len(v),
+                        "bytes_mean": round(sum(v) / len(v) * 1024.0 * factor)}
+    print(json.dumps(out))
+
+
 def durations_from_trace(path, name, last_n):
     """Duration statistics of the last N dispatches whose kernel name contains `name`."""
     import csv
@@ -369,9 +419,11 @@ def durations_from_trace(path, name, last_n):
         rows = [r for r in csv.DictReader(fh) if name in r["Kernel_Name"]]
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[-int(last_n):]]
+    last = rows[-1]
     print(json.dumps({"kernel": name, "dispatches": len(d), "mean_us": round(sum(d) / len(d), 2),
                       "min_us": round(min(d), 2), "max_us": round(max(d), 2),
-                      "workgroup_size": rows[-1]["Workgroup_Size"], "grid_size": rows[-1]["Grid_Size"]}))
+                      "workgroup_size": last.get("Workgroup_Size", last.get("Workgroup_Size_X")),
+                      "grid_size": last.get("Grid_Size", last.get("Grid_Size_X"))}))
 
 
 def _events_time(fn, reps, warm=3):
@@ -498,6 +550,7 @@ def bench_hmc(T, synth, dev):
     U_start = h.U.clone()
     dh20, acc20, t_traj = run(20)
     dh40, acc40, _ = run(40)
+    creutz = creutz_4x4x4x4(T, synth, dev)
     e = np.exp(-np.clip(np.array(dh20), -700, 700))
     ratio = float(np.mean(np.abs(dh20)) / np.mean(np.abs(dh40)))
     return {"force_us": round(t_force * 1e6, 1), "force_GB_s": round(force_bytes / t_force / 1e9, 1),
@@ -507,6 +560,7 @@ def bench_hmc(T, synth, dev):
             "dH_40_steps": [round(x, 6) for x in dh40], "acceptance_40_steps": acc40,
             "mean_abs_dH_ratio_20_to_40_steps": round(ratio, 3),
             "cg_iters_per_solve": round(h.cg_iters / max(1, h.solves), 1),
+            "creutz_4x4x4x4": creutz,
             "setup": "two-flavour twisted-mass pseudofermion action (beta = 0), tau = 1 leapfrog with 20 steps "
                      "(and 40: second-order integrator, mean |dH| ratio near 4) from the eps 0.4 start, force solves "
                      "1e-10, acceptance solves 1e-12"}

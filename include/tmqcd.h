@@ -36,9 +36,12 @@
  *
  * Ownership and streams
  *   - Every pointer argument that names a field is a DEVICE pointer owned by
- *     the caller; the library never allocates device memory.  Scratch memory
- *     comes from the caller's workspace `ws` of `ws_bytes` bytes, sized by
- *     tmqcd_workspace_bytes.  Problem, option and stats structs are host memory.
+ *     the caller; the library allocates no device memory for fields or
+ *     scratch.  Scratch memory comes from the caller's workspace `ws` of
+ *     `ws_bytes` bytes, sized by tmqcd_workspace_bytes (tmqcd_cg_batch with
+ *     graphs creates a HIP graph, and on the null stream a stream, and destroys
+ *     them before it returns).  Problem, option and stats structs are host
+ *     memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     tmqcd_pack_*, tmqcd_unpack_spinor, tmqcd_dslash and tmqcd_force are
  *     stream-ordered and return without waiting.  tmqcd_cg synchronises the
@@ -47,7 +50,9 @@
  *     negative error code.  Arguments are validated on the host before any HIP
  *     call, so every argument error is reported without touching the device.
  *     The library keeps no state between calls other than the last HIP error
- *     code of the calling thread.
+ *     code of the calling thread and the process-wide table of tuned launch
+ *     shapes (see autotuning; guarded by a mutex, so calls from several host
+ *     threads are safe).
  */
 #ifndef TMQCD_H
 #define TMQCD_H

@@ -125,44 +125,66 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
 // ran 14 % slower.
 template <int R>
 __global__ __launch_bounds__(kBlock, 2) void force_dir_kernel(const ForceK a) {
+    // the block's 64 output records (32 doubles each, +1 against bank conflicts) and their sites
+    __shared__ double otile[64][33];
+    __shared__ int64_t srec[64];
     const int bid = blockIdx.x;
     const int par = bid >= a.nb_half ? 1 : 0;
-    const int h = (bid - par * a.nb_half) * 64 + (threadIdx.x & 63);
+    const int lane = threadIdx.x & 63;
+    const int h = (bid - par * a.nb_half) * 64 + lane;
     const int mu = threadIdx.x >> 6;
-    if (h >= a.vh) return;
-    const int lxh = a.lxh, lx = a.L[0], ly = a.L[1], lz = a.L[2], lt = a.L[3];
-    const int xh = h % lxh;
-    int rest = h / lxh;
-    const int y = rest % ly;
-    rest /= ly;
-    const int z = rest % lz;
-    const int t = rest / lz;
-    const int bit = (par + y + z + t) & 1;
-    const int x = 2 * xh + bit;
-    const int64_t s = 2 * (int64_t)h + bit;
+    if (h < a.vh) {
+        const int lxh = a.lxh, lx = a.L[0], ly = a.L[1], lz = a.L[2], lt = a.L[3];
+        const int xh = h % lxh;
+        int rest = h / lxh;
+        const int y = rest % ly;
+        rest /= ly;
+        const int z = rest % lz;
+        const int t = rest / lz;
+        const int bit = (par + y + z + t) & 1;
+        const int x = 2 * xh + bit;
 
-    Spinor<double> xo, yo;
-    SpinorIO<TMQCD_F64>::load(xo, a.X + (int64_t)par * a.hbytes, a.stride, h);
-    SpinorIO<TMQCD_F64>::load(yo, a.Y + (int64_t)par * a.hbytes, a.stride, h);
-    double g[8];
-    if (mu == 0) {
-        const int xf = x + 1 == lx ? 0 : x + 1;
-        force_dir<R, 0>(a, par, h, (h - xh) + (xf >> 1), x == lx - 1, xo, yo, g);
-    } else if (mu == 1) {
-        const int nf = y == ly - 1 ? h - (ly - 1) * lxh : h + lxh;
-        force_dir<R, 1>(a, par, h, nf, y == ly - 1, xo, yo, g);
-    } else if (mu == 2) {
-        const int st = lxh * ly;
-        const int nf = z == lz - 1 ? h - (lz - 1) * st : h + st;
-        force_dir<R, 2>(a, par, h, nf, z == lz - 1, xo, yo, g);
-    } else {
-        const int st = lxh * ly * lz;
-        const int nf = t == lt - 1 ? h - (lt - 1) * st : h + st;
-        force_dir<R, 3>(a, par, h, nf, t == lt - 1, xo, yo, g);
-    }
-    double* o = a.out + s * 32 + mu * 8;
+        Spinor<double> xo, yo;
+        SpinorIO<TMQCD_F64>::load(xo, a.X + (int64_t)par * a.hbytes, a.stride, h);
+        SpinorIO<TMQCD_F64>::load(yo, a.Y + (int64_t)par * a.hbytes, a.stride, h);
+        double g[8];
+        if (mu == 0) {
+            const int xf = x + 1 == lx ? 0 : x + 1;
+            force_dir<R, 0>(a, par, h, (h - xh) + (xf >> 1), x == lx - 1, xo, yo, g);
+        } else if (mu == 1) {
+            const int nf = y == ly - 1 ? h - (ly - 1) * lxh : h + lxh;
+            force_dir<R, 1>(a, par, h, nf, y == ly - 1, xo, yo, g);
+        } else if (mu == 2) {
+            const int st = lxh * ly;
+            const int nf = z == lz - 1 ? h - (lz - 1) * st : h + st;
+            force_dir<R, 2>(a, par, h, nf, z == lz - 1, xo, yo, g);
+        } else {
+            const int st = lxh * ly * lz;
+            const int nf = t == lt - 1 ? h - (lt - 1) * st : h + st;
+            force_dir<R, 3>(a, par, h, nf, t == lt - 1, xo, yo, g);
+        }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) o[i] = a.accumulate ? o[i] + a.scale * g[i] : a.scale * g[i];
+        for (int i = 0; i < 8; ++i) otile[lane][mu * 8 + i] = a.scale * g[i];
+        if (mu == 0) srec[lane] = 2 * (int64_t)h + bit;
+    } else if (mu == 0) {
+        srec[lane] = -1;
+    }
+    __syncthreads();
+    // each record is 256 contiguous bytes of the canonical [V][4][8] output: a wave
+    // writes four whole records in 16-byte units instead of 64 scattered 8-byte words
+    for (int u = threadIdx.x; u < 64 * 16; u += kBlock) {
+        const int rec = u >> 4, k = u & 15;
+        const int64_t sr = srec[rec];
+        if (sr < 0) continue;
+        double2* o = reinterpret_cast<double2*>(a.out + sr * 32) + k;
+        double2 v = make_double2(otile[rec][2 * k], otile[rec][2 * k + 1]);
+        if (a.accumulate) {
+            const double2 w = *o;
+            v.x = w.x + v.x;
+            v.y = w.y + v.y;
+        }
+        *o = v;
+    }
 }
 
 }  // namespace

@@ -56,19 +56,28 @@ class FermionAction(torch.autograd.Function):
 
 
 class HMC:
-    """Two-flavour twisted-mass HMC state on one GPU: packed FP64 links and solver buffers."""
+    """Two-flavour twisted-mass HMC state on one GPU: packed FP64 links and solver buffers.
+
+    inner_prec: storage precision of the hops inside every solve (T.F64: plain
+    FP64 CG; T.F32 or T.F16: defect correction with reliable updates to the
+    same FP64 tolerance on the true residual).  A low-precision copy of the
+    links is packed from the FP64 links whenever they change.
+    """
 
     def __init__(self, prob: T.Problem, U_canon, beta: float, tol: float = 1e-12, max_iter: int = 20000,
-                 md_tol: float | None = None):
+                 md_tol: float | None = None, inner_prec: int = T.F64):
         self.prob = prob
         self.beta = float(beta)
         self.tol = tol                      # solves that enter H (acceptance)
         self.md_tol = md_tol or tol         # solves that enter the force
         self.max_iter = max_iter
+        self.inner = inner_prec
         self.U = T.pack_gauge(prob, U_canon, T.F64, T.RECON18)
+        self.U_low = None
+        self.refresh_low()
         dev = self.U.device
         fb = T.spinor_bytes(prob, T.F64, T.FULL)
-        self.ws_cg = T.workspace(prob, T.MDAGM, 1)
+        self.ws_cg = T.workspace(prob, T.MDAGM, 1 | (1 << inner_prec))
         self.ws_dslash = T.workspace(prob, T.MDAGM, 1)
         self.ws_aux = T.aux_workspace(prob)
         self.X = torch.empty(fb, dtype=torch.uint8, device=dev)
@@ -83,12 +92,23 @@ class HMC:
         eta = T.pack_spinor(self.prob, eta_canon, T.F64, T.FULL)
         T.dslash(self.prob, self.U, eta, T.MDAG, out=self.phi, ws=self.ws_dslash)
 
+    def _low(self, U):
+        """The links U (packed FP64) packed in the inner precision."""
+        return T.pack_gauge(self.prob, T.unpack_gauge(self.prob, U), self.inner, T.RECON18)
+
+    def refresh_low(self):
+        """Re-pack the low-precision copy after the FP64 links changed."""
+        if self.inner != T.F64:
+            self.U_low = self._low(self.U)
+
     def solve(self, b, U=None, tol=None, x=None):
         """X = (M^+ M)^{-1} b on links U (default: the current links)."""
-        U = self.U if U is None else U
+        gauges = {T.F64: self.U if U is None else U}
+        if self.inner != T.F64:
+            gauges[self.inner] = self.U_low if U is None else self._low(U)
         x = self.X if x is None else x
-        _, st, _ = T.cg(self.prob, {T.F64: U}, b, x, x_is_zero=True, tol=tol or self.tol, max_iter=self.max_iter,
-                        op=T.MDAGM, ws=self.ws_cg)
+        _, st, _ = T.cg(self.prob, gauges, b, x, x_is_zero=True, tol=tol or self.tol, max_iter=self.max_iter,
+                        op=T.MDAGM, inner_prec=self.inner, ws=self.ws_cg)
         self.solves += 1
         self.cg_iters += st["iters"]
         return x
@@ -119,10 +139,12 @@ class HMC:
         self.add_gradient(p, -0.5 * dt)
         for i in range(n_steps):
             T.update_links(self.prob, self.U, p, dt)
+            self.refresh_low()
             self.add_gradient(p, -dt if i < n_steps - 1 else -0.5 * dt)
 
     def trajectory(self, p, eta_canon, uniform: float, n_steps: int, dt: float) -> dict:
         """One HMC trajectory from momenta p (modified in place) and a Gaussian eta."""
+        self.refresh_low()            # the links may have been set from outside
         self.set_pseudofermion(eta_canon)
         e0 = self.energies(p)
         U0 = self.U.clone()
@@ -132,4 +154,5 @@ class HMC:
         accepted = bool(uniform < math.exp(-dh)) if dh > 0 else True
         if not accepted:
             self.U.copy_(U0)
+            self.refresh_low()
         return {"dH": dh, "accepted": accepted, "H0": sum(e0), "H1": sum(e1), "energies0": e0, "energies1": e1}

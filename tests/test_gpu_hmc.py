@@ -58,14 +58,16 @@ def test_update_links_matches_oracle_exponential(dt):
     np.testing.assert_allclose(np.linalg.det(got), 1.0, atol=1e-13)
 
 
-def test_trajectory_matches_oracle():
+@pytest.mark.parametrize("inner", [T.F64, T.F32])
+def test_trajectory_matches_oracle(inner):
+    """Whole trajectory against the oracle, with FP64 solves and with FP32-inner defect correction."""
     dims, kappa, mu, beta = (2, 2, 2, 4), 0.155, 0.01, 5.0
     f = Fields(dims, 0.4, 221, kappa, mu, BC_AP)
     p = synth.gaussian_momenta(f.prob.volume, 222)
     eta = synth.gaussian_spinor(f.prob.volume, 223)
     n, dt = 8, 0.125
     want = OH.trajectory(f.U, p, eta, 0.5, dims, kappa, mu, BC_AP, beta, n, dt)
-    h = H.HMC(f.prob, f.U_dev, beta, tol=1e-14)
+    h = H.HMC(f.prob, f.U_dev, beta, tol=1e-14, inner_prec=inner)
     pd = dev(p)
     out = h.trajectory(pd, dev(eta), 0.5, n, dt)
     assert abs(out["dH"] - want["dH"]) < 1e-8
@@ -164,3 +166,19 @@ def test_creutz_equality_in_equilibrium_4x4x4x4():
     assert acc / len(dh) > 0.5
     assert err < 0.05
     assert abs(mean - 1.0) < 4 * err, (mean, err)
+
+
+def test_mixed_precision_trajectory_equals_fp64_16x16x16x32():
+    """FP32-inner solves reach the same FP64 tolerances: the trajectory's dH and links agree with FP64 solves."""
+    dims = (16, 16, 16, 32)
+    f = Fields(dims, 0.4, 611, 0.155, 0.01, BC_AP)
+    p = synth.gaussian_momenta(f.prob.volume, 612)
+    eta = synth.gaussian_spinor(f.prob.volume, 613)
+    out, links = [], []
+    for inner in (T.F64, T.F32):
+        h = H.HMC(f.prob, f.U_dev, 0.0, tol=1e-12, md_tol=1e-11, inner_prec=inner)
+        out.append(h.trajectory(dev(p), dev(eta), 0.0, 4, 0.05))
+        links.append(host(T.unpack_gauge(f.prob, h.U)))
+    assert abs(out[0]["H0"] - out[1]["H0"]) < 1e-9 * abs(out[0]["H0"])
+    assert abs(out[0]["dH"] - out[1]["dH"]) < 1e-6, (out[0]["dH"], out[1]["dH"])
+    assert np.abs(links[0] - links[1]).max() < 1e-9
