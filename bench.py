@@ -168,6 +168,10 @@ def main():
         return t, vh * BYTES_PER_SITE[(prec, recon)] / t / 1e9, vh * FLOPS_PER_SITE / t / 1e9
 
     t_hop, gbs_hop, gflops_hop = time_hop(T.F64, T.RECON18, 200)
+    for p in (T.F64, T.F32, T.F16):            # the sweep in tuned shapes too
+        for r in (0, 1):
+            if (p, r) != (T.F64, T.RECON18):
+                T.tune(prob, gauges[(p, r)], p, r)
     sweep = {}
     for p, pn in ((T.F64, "f64"), (T.F32, "f32"), (T.F16, "f16")):
         for r, rn in ((0, "rec18"), (1, "rec12")):
@@ -176,20 +180,17 @@ def main():
                                    "bytes_per_site": BYTES_PER_SITE[(p, r)]}
     log(f"hop f64: {t_hop * 1e6:.1f} us, {gbs_hop:.0f} GB/s, {gflops_hop:.0f} GFLOPS")
 
-    # HBM copy probe (torch copy of a 4 GiB buffer) for the measured peak
-    a = torch.empty(1 << 32, dtype=torch.uint8, device=dev)
+    # measured ceilings on a 4 GiB buffer (far beyond the 256 MB of MALL): the library's streaming
+    # probe (16-byte reads; copy) at two grid sizes, and torch's copy
+    a = torch.ones(1 << 32, dtype=torch.uint8, device=dev)
     c = torch.empty_like(a)
-    c.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(5):
-        c.copy_(a)
-    e1.record(stream)
-    e1.synchronize()
-    copy_gbs = 2 * a.numel() * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    read_gbs = max(a.numel() / _events_time(lambda: T.hbm_probe(a, grid=g), 5) / 1e9 for g in (1024, 2048))
+    probe_copy_gbs = max(2 * a.numel() / _events_time(lambda: T.hbm_probe(a, c, grid=g), 5) / 1e9
+                         for g in (1024, 2048))
+    copy_gbs = 2 * a.numel() / _events_time(lambda: c.copy_(a), 5) / 1e9
     del a, c
 
+    traffic = traffic_from_profile(vh)
     result = {
         "metric": "Dslash GB/s (% HBM peak); CG time to 1e-10 residual, FP64 vs mixed",
         "value": round(value, 1),
@@ -210,12 +211,14 @@ def main():
                                 "true_rel_residual": st0["true_rel_residual"],
                                 "hop_launches_per_solve": st0["hop_launches"]},
         "roofline": {"bound": "hbm", "achieved": round(gbs_hop, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(gbs_hop / PEAK_HBM_GBPS, 4), "traffic": traffic_from_profile(vh),
+                     "frac": round(gbs_hop / PEAK_HBM_GBPS, 4), "traffic": traffic,
                      "kernel": f"hop_kernel<F64,RECON18,dag=0,own=0,store> block {tuning['class0']['block']} "
                                "(DSLASH_OE / first Schur hop)",
                      "bytes_per_launch": vh * BYTES_PER_SITE[(0, 0)], "us_per_launch": round(t_hop * 1e6, 2),
-                     "gflops": round(gflops_hop, 1), "measured_copy_peak_GB_s": round(copy_gbs, 1),
-                     "frac_of_measured_copy": round(gbs_hop / copy_gbs, 4)},
+                     "gflops": round(gflops_hop, 1), "measured_read_peak_GB_s": round(read_gbs, 1),
+                     "measured_copy_peak_GB_s": round(max(copy_gbs, probe_copy_gbs), 1),
+                     "hbm_traffic_GB_s": round(traffic / (t_hop) / 1e9, 1) if traffic else None,
+                     "frac_of_measured_read": round(gbs_hop / read_gbs, 4)},
         "dslash_sweep_24x24x24x48": sweep,
         "tuning_f64_rec18": tuning,
         "context": {"paper_hd5870_dslash_dp_gflops": 60, "paper_hmc_speedup_vs_server_cpu": 4},
@@ -226,11 +229,14 @@ def main():
         m = MIXED
         pm = T.Problem(m["dims"], m["kappa"], m["mu"], (1, 1, 1, -1))
         log(f"drawing links {m['dims']}")
-        Um = torch.from_numpy(synth.random_links(m["dims"], m["eps"], m["seed"])).to(dev)
+        Um_host = synth.random_links(m["dims"], m["eps"], m["seed"])
+        Um = torch.from_numpy(Um_host).to(dev)
         gm = {p: T.pack_gauge(pm, Um, p, 0) for p in (T.F64, T.F32, T.F16)}
         del Um
-        bm = T.pack_spinor(pm, torch.from_numpy(synth.gaussian_spinor(pm.volume // 2, m["src_seed"])).to(dev),
-                           T.F64, T.EVEN)
+        for p in (T.F64, T.F32, T.F16):      # every precision in its tuned launch shapes
+            T.tune(pm, gm[p], p, 0)
+        bm_host = synth.gaussian_spinor(pm.volume // 2, m["src_seed"])
+        bm = T.pack_spinor(pm, torch.from_numpy(bm_host).to(dev), T.F64, T.EVEN)
         xm = torch.empty(T.spinor_bytes(pm, T.F64, T.EVEN), dtype=torch.uint8, device=dev)
         wsm = T.workspace(pm, T.MHATDAGMHAT)
         mixed = {}
@@ -253,7 +259,13 @@ def main():
             mixed[k]["speedup_vs_fp64"] = round(mixed["fp64"]["ms"] / mixed[k]["ms"], 3)
         mixed["workload"] = "Mhat^dag Mhat, 32^3x64, kappa 0.162, mu 0.003, eps 0.5, tol 1e-10 (FP64 true residual)"
         result["cg_32x32x32x64"] = mixed
-        del gm, bm, xm, wsm
+        if not args.no_oracle:   # the last solution is the FP16-inner one
+            from oracle import dirac as D
+            log("oracle check of the 32^3x64 FP16-inner solution")
+            xs = T.unpack_spinor(pm, xm, T.F64, T.EVEN).cpu().numpy()
+            Am = lambda v: D.apply_MhatdagMhat(Um_host, v, m["dims"], m["kappa"], m["mu"], (1, 1, 1, -1))
+            mixed["mixed_f16"]["oracle_rel_residual"] = D.true_rel_residual(Am, bm_host, xs)
+        del gm, bm, xm, wsm, Um_host
 
     if not args.no_extras:
         result["multi_rhs_24x24x24x48"] = bench_multi_rhs(T, prob, U, dev)
@@ -533,28 +545,33 @@ def bench_hmc(T, synth, dev):
     t_force = _events_time(lambda: T.force(prob, h.U, X, Y, out=G), 20)
     # compulsory bytes per site: 4 links, X and Y once each, the 4 x 8 outputs
     force_bytes = prob.volume * (4 * 144 + 2 * 192 + 256)
-    def run(n_steps):
+    def run(hmc, n_steps):
         dh, acc = [], 0
         t0 = time.perf_counter()
         for k in range(10):
             p = torch.from_numpy(synth.gaussian_momenta(prob.volume, 1000 + k)).to(dev)
             eta = torch.from_numpy(synth.gaussian_spinor(prob.volume, 2000 + k)).to(dev)
             u = float(np.random.default_rng(3000 + k).random())
-            h.U.copy_(U_start)     # every trajectory from the same start: dH of one field, two step sizes
-            out = h.trajectory(p, eta, u, n_steps, 1.0 / n_steps)
+            hmc.U.copy_(U_start)   # every trajectory from the same start: dH of one field, two step sizes
+            out = hmc.trajectory(p, eta, u, n_steps, 1.0 / n_steps)
             dh.append(out["dH"])
             acc += int(out["accepted"])
         torch.cuda.synchronize()
         return dh, acc / 10, (time.perf_counter() - t0) / 10
 
     U_start = h.U.clone()
-    dh20, acc20, t_traj = run(20)
-    dh40, acc40, _ = run(40)
+    dh20, acc20, t_traj = run(h, 20)
+    dh40, acc40, _ = run(h, 40)
+    # the same 20-step trajectories with FP32-inner solves (same FP64 tolerances)
+    h32 = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10, inner_prec=T.F32)
+    dh32, _, t_traj32 = run(h32, 20)
     creutz = creutz_4x4x4x4(T, synth, dev)
     e = np.exp(-np.clip(np.array(dh20), -700, 700))
     ratio = float(np.mean(np.abs(dh20)) / np.mean(np.abs(dh40)))
     return {"force_us": round(t_force * 1e6, 1), "force_GB_s": round(force_bytes / t_force / 1e9, 1),
-            "trajectory_s": round(t_traj, 3), "dH": [round(x, 6) for x in dh20], "acceptance": acc20,
+            "trajectory_s": round(t_traj, 3), "trajectory_s_fp32_inner": round(t_traj32, 3),
+            "dH_fp32_inner_max_abs_diff": float(np.max(np.abs(np.array(dh32) - np.array(dh20)))),
+            "dH": [round(x, 6) for x in dh20], "acceptance": acc20,
             "exp_minus_dH_mean": round(float(e.mean()), 4),
             "exp_minus_dH_stderr": round(float(e.std(ddof=1) / math.sqrt(len(e))), 4),
             "dH_40_steps": [round(x, 6) for x in dh40], "acceptance_40_steps": acc40,

@@ -27,10 +27,11 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
               MDAGM: (FULL, FULL), MHAT: (EVEN, EVEN), MHATDAG: (EVEN, EVEN), MHATDAGMHAT: (EVEN, EVEN)}
 
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
-                "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg", "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force",
-                "tmqcd_gauge_force", "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune",
-                "tmqcd_tune_save", "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set",
-                "tmqcd_tune_mrhs_workspace_bytes", "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot",
+                "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg",
+                "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force", "tmqcd_gauge_force",
+                "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune", "tmqcd_tune_save",
+                "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set", "tmqcd_tune_mrhs_workspace_bytes",
+                "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot", "tmqcd_hbm_probe",
                 "tmqcd_error_string", "tmqcd_last_hip_error")
 
 
@@ -111,6 +112,7 @@ def lib():
             "tmqcd_tune_set": (I, [P, I, I, I, I, I, I, I]),
             "tmqcd_tune_mrhs_workspace_bytes": (S, [P, I, I]),
             "tmqcd_tune_mrhs": (I, [P, V, I, I, I, V, S, ctypes.POINTER(CTuneResult), V]),
+            "tmqcd_hbm_probe": (I, [V, V, S, I, V]),
             "tmqcd_error_string": (ctypes.c_char_p, [I]),
             "tmqcd_last_hip_error": (I, []),
         }
@@ -300,6 +302,11 @@ def tune_save(path: str):
 
 def tune_load(path: str):
     _check(lib().tmqcd_tune_load(str(path).encode()), "tmqcd_tune_load")
+
+
+def hbm_probe(src, dst=None, grid=2048, stream=None):
+    """Stream src (uint8 device tensor, 16-byte multiple) with 16-byte reads, or copy it to dst."""
+    _check(lib().tmqcd_hbm_probe(_ptr(src), _ptr(dst), src.numel(), grid, _stream(stream)), "tmqcd_hbm_probe")
 
 
 def tune_clear():

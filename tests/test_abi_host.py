@@ -184,3 +184,12 @@ def test_tune_mrhs_validation(L):
     assert L.tmqcd_tune_mrhs(p, 1 << 30, 0, 0, 1, 1 << 32, 1 << 30, ctypes.byref(res), None) == T.EINVAL
     assert L.tmqcd_tune_mrhs(p, 1 << 30, 0, 0, 12, None, 0, ctypes.byref(res), None) == T.EWORKSPACE
     assert L.tmqcd_tune_mrhs(p, 1 << 30, 0, 0, 12, 8, 1 << 30, ctypes.byref(res), None) == T.EALIGN
+
+
+def test_hbm_probe_validation(L):
+    assert L.tmqcd_hbm_probe(None, None, 1 << 20, 64, None) == T.EINVAL
+    assert L.tmqcd_hbm_probe(1 << 30, None, 0, 64, None) == T.EINVAL
+    assert L.tmqcd_hbm_probe(1 << 30, None, 100, 64, None) == T.EINVAL          # not a multiple of 16
+    assert L.tmqcd_hbm_probe(1 << 30, None, 1 << 20, 0, None) == T.EINVAL
+    assert L.tmqcd_hbm_probe((1 << 30) + 8, None, 1 << 20, 64, None) == T.EALIGN
+    assert L.tmqcd_hbm_probe(1 << 30, (1 << 30) + 4096, 1 << 20, 64, None) == T.EALIAS
