@@ -184,7 +184,9 @@ def main():
     # probe (16-byte reads; copy) at two grid sizes, and torch's copy
     a = torch.ones(1 << 32, dtype=torch.uint8, device=dev)
     c = torch.empty_like(a)
-    read_gbs = max(a.numel() / _events_time(lambda: T.hbm_probe(a, grid=g), 5) / 1e9 for g in (1024, 2048))
+    word = torch.zeros(1, dtype=torch.int32, device=dev)
+    read_gbs = max(a.numel() / _events_time(lambda: T.hbm_probe(a, xor_out=word, grid=g), 5) / 1e9
+                   for g in (1024, 2048))
     probe_copy_gbs = max(2 * a.numel() / _events_time(lambda: T.hbm_probe(a, c, grid=g), 5) / 1e9
                          for g in (1024, 2048))
     copy_gbs = 2 * a.numel() / _events_time(lambda: c.copy_(a), 5) / 1e9

@@ -290,12 +290,14 @@ int tmqcd_tune_set(const tmqcd_problem* prob, int prec, int recon, int kernel_cl
                    int order, int group);
 
 /* ---- diagnostics ------------------------------------------------------------- */
-/* Bandwidth probe (a measurement aid, not part of the method): reads `bytes`
- * of src with 16-byte loads (dst == NULL) or copies them to dst, with `grid`
- * blocks of 256 threads striding over the buffer; stream-ordered.  bytes must
- * be a positive multiple of 16, grid in [1, 65536], pointers 16-byte aligned,
- * src and dst disjoint. */
-int tmqcd_hbm_probe(const void* src, void* dst, size_t bytes, int grid, void* stream);
+/* Bandwidth probe (a measurement aid, not part of the method): with dst ==
+ * NULL, reads `bytes` of src with 16-byte loads and xors every 32-bit word
+ * into *xor_out (a device word the caller sets beforehand; required then);
+ * otherwise copies src to dst (xor_out unused).  `grid` blocks of 256 threads
+ * stride over the buffer; stream-ordered.  bytes must be a positive multiple
+ * of 16, grid in [1, 65536], src and dst 16-byte aligned, xor_out 4-byte
+ * aligned, no two of them overlapping. */
+int tmqcd_hbm_probe(const void* src, void* dst, size_t bytes, int grid, uint32_t* xor_out, void* stream);
 
 const char* tmqcd_error_string(int code);
 int tmqcd_last_hip_error(void);   /* hipError_t of the last failed HIP call in this thread */

@@ -385,11 +385,13 @@ int tmqcd_tune_mrhs(const tmqcd_problem* prob, const void* U_packed, int prec, i
     return run_tune_mrhs(*prob, U_packed, prec, recon, nrhs, ws, (hipStream_t)stream, result);
 }
 
-int tmqcd_hbm_probe(const void* src, void* dst, size_t bytes, int grid, void* stream) {
-    if (!src || bytes == 0 || bytes % 16 || grid < 1 || grid > 65536) return TMQCD_EINVAL;
-    if (!aligned(src, 16) || (dst && !aligned(dst, 16))) return TMQCD_EALIGN;
+int tmqcd_hbm_probe(const void* src, void* dst, size_t bytes, int grid, uint32_t* xor_out, void* stream) {
+    if (!src || bytes == 0 || bytes % 16 || grid < 1 || grid > 65536 || (!dst && !xor_out)) return TMQCD_EINVAL;
+    if (!aligned(src, 16) || (dst && !aligned(dst, 16)) || (!dst && !aligned(xor_out, 4))) return TMQCD_EALIGN;
     if (dst && overlap(src, (int64_t)bytes, dst, (int64_t)bytes)) return TMQCD_EALIAS;
-    const hipError_t e = launch_hbm_probe(src, dst, (int64_t)bytes, grid, (hipStream_t)stream);
+    if (!dst && overlap(src, (int64_t)bytes, xor_out, 4)) return TMQCD_EALIAS;
+    const hipError_t e = launch_hbm_probe(src, dst, (int64_t)bytes, grid, reinterpret_cast<unsigned*>(xor_out),
+                                          (hipStream_t)stream);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 

@@ -2,11 +2,12 @@
 // paper section 2.1: a thermal lattice uses less parallelism).  Each stage of
 // a CG iteration on Mhat^+ Mhat is a single grid-stride launch over the tiles
 // of all lattices, every lattice with its own solver state; lattices that have
-// converged are skipped inside the launches.  One iteration (4 hop launches,
-// the first tile of a lattice finishing its alpha reduction in the third, a
-// one-block-per-lattice finish of beta, and the search-direction update) can
-// be captured once in a hipGraph and replayed between host checks, which
-// removes the per-kernel launch cost that dominates at these volumes.
+// converged are skipped inside the launches.  An iteration is 4 hop launches
+// (the first tile of a lattice finishing its alpha reduction in the third), a
+// one-block-per-lattice finish of beta and the search-direction update; the
+// iterations queued between two host checks can be captured once in a
+// hipGraph and replayed with one launch, which removes the per-kernel launch
+// cost of the host at these volumes.
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -174,9 +175,10 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
         }
         TRY(launch_set_state(L[i].st, v, s));
     }
-    if (use_graph) {
+    if (use_graph) {   // one graph holds all the iterations queued between two host checks
         TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const hipError_t ec = iteration();
+        hipError_t ec = hipSuccess;
+        for (int k = 0; k < check && ec == hipSuccess; ++k) ec = iteration();
         const hipError_t ee = hipStreamEndCapture(s, &graph);
         TRY(ec);
         TRY(ee);
@@ -188,10 +190,9 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
         if (!any) break;
         // iterate until every active lattice has stopped
         for (;;) {
-            for (int k = 0; k < check; ++k) {
-                if (use_graph) TRY(hipGraphLaunch(exec, s));
-                else TRY(iteration());
-            }
+            if (use_graph) TRY(hipGraphLaunch(exec, s));
+            else
+                for (int k = 0; k < check; ++k) TRY(iteration());
             TRY(read_states());
             bool running = false;
             for (int i = 0; i < n; ++i) running = running || (active[i] && hs[i].done == kDoneRunning);

@@ -139,8 +139,8 @@ hipError_t launch_pack_spinor(const Geom& g, const void* canon, void* packed, in
 hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* X, const void* Y, double* out,
                         const Cplx bc[4], double kappa, double scale, int accumulate, hipStream_t s);
 
-// ---- bandwidth probe (probe.hip): read (dst == nullptr) or copy `bytes` (a multiple of 16) ----
-hipError_t launch_hbm_probe(const void* src, void* dst, int64_t bytes, int grid, hipStream_t s);
+// ---- bandwidth probe (probe.hip): read (dst == nullptr; xor of the words into *xor_out) or copy
+hipError_t launch_hbm_probe(const void* src, void* dst, int64_t bytes, int grid, unsigned* xor_out, hipStream_t s);
 
 // ---- HMC kernels and auxiliary reductions (partials: aux_partials_doubles(g) doubles) ----
 int64_t aux_partials_doubles(const Geom& g);

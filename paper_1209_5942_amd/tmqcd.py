@@ -112,7 +112,7 @@ def lib():
             "tmqcd_tune_set": (I, [P, I, I, I, I, I, I, I]),
             "tmqcd_tune_mrhs_workspace_bytes": (S, [P, I, I]),
             "tmqcd_tune_mrhs": (I, [P, V, I, I, I, V, S, ctypes.POINTER(CTuneResult), V]),
-            "tmqcd_hbm_probe": (I, [V, V, S, I, V]),
+            "tmqcd_hbm_probe": (I, [V, V, S, I, V, V]),
             "tmqcd_error_string": (ctypes.c_char_p, [I]),
             "tmqcd_last_hip_error": (I, []),
         }
@@ -304,9 +304,11 @@ def tune_load(path: str):
     _check(lib().tmqcd_tune_load(str(path).encode()), "tmqcd_tune_load")
 
 
-def hbm_probe(src, dst=None, grid=2048, stream=None):
-    """Stream src (uint8 device tensor, 16-byte multiple) with 16-byte reads, or copy it to dst."""
-    _check(lib().tmqcd_hbm_probe(_ptr(src), _ptr(dst), src.numel(), grid, _stream(stream)), "tmqcd_hbm_probe")
+def hbm_probe(src, dst=None, xor_out=None, grid=2048, stream=None):
+    """Copy src (uint8 device tensor, 16-byte multiple) to dst, or with dst None stream it with 16-byte reads,
+    xoring its 32-bit words into xor_out (an int32 device tensor of one element)."""
+    _check(lib().tmqcd_hbm_probe(_ptr(src), _ptr(dst), src.numel(), grid, _ptr(xor_out), _stream(stream)),
+           "tmqcd_hbm_probe")
 
 
 def tune_clear():

@@ -187,9 +187,13 @@ def test_tune_mrhs_validation(L):
 
 
 def test_hbm_probe_validation(L):
-    assert L.tmqcd_hbm_probe(None, None, 1 << 20, 64, None) == T.EINVAL
-    assert L.tmqcd_hbm_probe(1 << 30, None, 0, 64, None) == T.EINVAL
-    assert L.tmqcd_hbm_probe(1 << 30, None, 100, 64, None) == T.EINVAL          # not a multiple of 16
-    assert L.tmqcd_hbm_probe(1 << 30, None, 1 << 20, 0, None) == T.EINVAL
-    assert L.tmqcd_hbm_probe((1 << 30) + 8, None, 1 << 20, 64, None) == T.EALIGN
-    assert L.tmqcd_hbm_probe(1 << 30, (1 << 30) + 4096, 1 << 20, 64, None) == T.EALIAS
+    w = 1 << 34
+    assert L.tmqcd_hbm_probe(None, None, 1 << 20, 64, w, None) == T.EINVAL
+    assert L.tmqcd_hbm_probe(1 << 30, None, 0, 64, w, None) == T.EINVAL
+    assert L.tmqcd_hbm_probe(1 << 30, None, 100, 64, w, None) == T.EINVAL        # not a multiple of 16
+    assert L.tmqcd_hbm_probe(1 << 30, None, 1 << 20, 0, w, None) == T.EINVAL
+    assert L.tmqcd_hbm_probe(1 << 30, None, 1 << 20, 64, None, None) == T.EINVAL   # read needs the xor word
+    assert L.tmqcd_hbm_probe((1 << 30) + 8, None, 1 << 20, 64, w, None) == T.EALIGN
+    assert L.tmqcd_hbm_probe(1 << 30, None, 1 << 20, 64, w + 2, None) == T.EALIGN
+    assert L.tmqcd_hbm_probe(1 << 30, (1 << 30) + 4096, 1 << 20, 64, None, None) == T.EALIAS
+    assert L.tmqcd_hbm_probe(1 << 30, None, 1 << 20, 64, (1 << 30) + 64, None) == T.EALIAS

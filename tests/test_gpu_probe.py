@@ -1,4 +1,5 @@
-"""The bandwidth probe: its copy reproduces the source bytes; its read leaves the buffer unchanged."""
+"""The bandwidth probe: its copy reproduces the source bytes; its read xors every word (checked on the host)."""
+import numpy as np
 import pytest
 import torch
 
@@ -14,7 +15,10 @@ def test_probe_copy_and_read(nbytes, grid):
     a = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda", generator=g)
     keep = a.clone()
     c = torch.zeros_like(a)
+    word = torch.zeros(1, dtype=torch.int32, device="cuda")
     T.hbm_probe(a, c, grid=grid)
-    T.hbm_probe(a, grid=grid)
+    T.hbm_probe(a, xor_out=word, grid=grid)
     torch.cuda.synchronize()
     assert torch.equal(c, a) and torch.equal(a, keep)
+    want = np.bitwise_xor.reduce(keep.cpu().numpy().view(np.uint32))
+    assert int(word.cpu().numpy().view(np.uint32)[0]) == int(want)
