@@ -270,6 +270,7 @@ def main():
         del gm, bm, xm, wsm, Um_host
 
     if not args.no_extras:
+        result["dslash_sizes_f64_rec18"] = bench_sizes(T, dev)
         result["multi_rhs_24x24x24x48"] = bench_multi_rhs(T, prob, U, dev)
         result["batch_cg"] = bench_batch(T, synth, dev)
         result["hmc_16x16x16x32"] = bench_hmc(T, synth, dev)
@@ -485,6 +486,32 @@ def bench_multi_rhs(T, prob, U, dev):
                    "speedup": round(t_single / t_multi, 3),
                    "bytes_per_site_rhs": round(link / 12 + spin, 1),
                    "multi_GB_s": round(vh * (link + 12 * spin) / t_multi / 1e9, 1)}
+    return out
+
+
+def bench_sizes(T, dev):
+    """FP64 R18 odd<-even hop over the paper's grid of lattice sizes (N_s in 16..48, N_t in 4..16) and
+    32^3x64, each in its tuned shape.  Timing only: links are random complex matrices drawn on the device."""
+    import torch
+    log("hop over lattice sizes")
+    out = {}
+    sizes = [(n, n, n, t) for n in (16, 24, 32, 48) for t in (4, 8, 12, 16)] + [(32, 32, 32, 64)]
+    for dims in sizes:
+        prob = T.Problem(dims, 0.16, 0.005, (1, 1, 1, -1))
+        vh = prob.volume // 2
+        g = torch.Generator(device=dev)
+        g.manual_seed(5)
+        gp = T.pack_gauge(prob, torch.randn((prob.volume, 4, 3, 3), dtype=torch.complex128, device=dev,
+                                            generator=g))
+        src = T.pack_spinor(prob, torch.randn((vh, 4, 3), dtype=torch.complex128, device=dev, generator=g),
+                            T.F64, T.EVEN)
+        o = torch.empty(T.spinor_bytes(prob, T.F64, T.ODD), dtype=torch.uint8, device=dev)
+        best = T.tune(prob, gp, T.F64, T.RECON18)[0]
+        t = _events_time(lambda: T.dslash(prob, gp, src, T.DSLASH_OE, out=o), 50)
+        out["x".join(map(str, dims))] = {"us": round(t * 1e6, 2), "GB_s": round(vh * 1536 / t / 1e9, 1),
+                                         "GFLOPS": round(vh * FLOPS_PER_SITE / t / 1e9, 1),
+                                         "block": best["block"], "order": best["order"]}
+        del gp, src, o
     return out
 
 
