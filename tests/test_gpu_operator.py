@@ -152,3 +152,35 @@ def test_production_shape_gamma5_hermiticity():
                                                   T.MHATDAG), 0, T.EVEN))
     a, b = np.vdot(chi, mpsi), np.vdot(mdchi, psi)
     assert abs(a - b) < 1e-12 * abs(a)
+
+
+@pytest.mark.timeout(600)
+def test_production_shape_tuned_launches_sampled():
+    """24^3 x 48 in the launch shapes the bench times (tuned single-RHS classes and the tuned 12-RHS
+    kernel, FP64 and FP32): the odd<-even hop against the oracle on sampled sites, every column."""
+    dims, kappa, mu = (24, 24, 24, 48), 0.16, 0.005
+    f = cached_fields(dims, 0.5, 24, kappa, mu, BC_AP)
+    rng = np.random.default_rng(11)
+    ev, od = D.half_sites(dims, 0), D.half_sites(dims, 1)
+    hs = np.unique(np.concatenate([rng.choice(od.size, 120, replace=False), [0, od.size - 1]]))
+    try:
+        T.tune_clear()
+        for prec in (T.F64, T.F32):
+            g = f.gauge(prec, T.RECON18)
+            T.tune(f.prob, g, prec, T.RECON18)
+            T.tune_mrhs(f.prob, g, 12, prec, T.RECON18)
+            psi = f.spinor(T.EVEN, 700 + prec, nrhs=12)
+            out1 = host(T.unpack_spinor(f.prob, T.dslash(f.prob, g, T.pack_spinor(f.prob, dev(psi[0]), prec, T.EVEN),
+                                                         T.DSLASH_OE, prec, T.RECON18), prec, T.ODD))
+            outm = host(T.unpack_spinor(f.prob, T.dslash(f.prob, g, T.pack_spinor(f.prob, dev(psi), prec, T.EVEN,
+                                                                                    nrhs=12),
+                                                         T.DSLASH_OE, prec, T.RECON18, nrhs=12), prec, T.ODD, 12))
+            for k in range(12):
+                full = np.zeros((f.prob.volume, 4, 3), dtype=np.complex128)
+                full[ev] = psi[k]
+                want = -kappa * D.hop_at_sites(f.U, full, dims, BC_AP, od[hs])
+                assert rel(outm[k][hs], want) < TOL[prec], (prec, k)
+                if k == 0:
+                    assert rel(out1[hs], want) < TOL[prec], prec
+    finally:
+        T.tune_clear()

@@ -113,11 +113,19 @@ def test_cg_bitwise_reproducible():
 
 
 @pytest.mark.timeout(300)
-def test_cg_production_shape_fp64():
-    """24^3 x 48, kappa = 0.16, mu = 0.005, Gaussian source: FP64 CG to 1e-10, checked by the oracle."""
+@pytest.mark.parametrize("tuned", [False, True])
+def test_cg_production_shape_fp64(tuned):
+    """24^3 x 48, kappa = 0.16, mu = 0.005, Gaussian source: FP64 CG to 1e-10, checked by the oracle, in the
+    default launch shapes and in the tuned ones the bench times."""
     f = cached_fields((24, 24, 24, 48), 0.5, 24, 0.16, 0.005, BC_AP)
     b = synth.gaussian_spinor(f.prob.volume // 2, 26)
-    x, st, rc = _solve(f, T.MHATDAGMHAT, b, tol=1e-10)
+    try:
+        T.tune_clear()
+        if tuned:
+            T.tune(f.prob, f.gauge(T.F64, 0), T.F64, T.RECON18)
+        x, st, rc = _solve(f, T.MHATDAGMHAT, b, tol=1e-10)
+    finally:
+        T.tune_clear()
     assert rc == T.OK
     assert D.true_rel_residual(_oracle_A(f, T.MHATDAGMHAT), b, x) <= 1e-10
 
@@ -133,3 +141,27 @@ def test_force_matches_oracle(dims, bc, recon):
     got = host(T.force(f.prob, f.gauge(T.F64, recon), Xp, Yp, recon))
     want = F.fermion_force(f.U, X, Y, dims, f.kappa, bc)
     assert rel(got, want) < 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_cg_mixed_production_shape_32x32x32x64():
+    """32^3 x 64, kappa = 0.162, mu = 0.003 (the mixed-precision workload): FP64, FP32- and FP16-inner CG in
+    their tuned launch shapes reach the FP64 1e-10 residual that the oracle recomputes, and the three
+    solutions agree as far as that residual bound allows."""
+    f = cached_fields((32, 32, 32, 64), 0.5, 32, 0.162, 0.003, BC_AP)
+    b = synth.gaussian_spinor(f.prob.volume // 2, 34)
+    xs = {}
+    try:
+        T.tune_clear()
+        for inner in (T.F64, T.F32, T.F16):
+            T.tune(f.prob, f.gauge(inner, 0), inner, T.RECON18)
+            x, st, rc = _solve(f, T.MHATDAGMHAT, b, inner=inner, tol=1e-10)
+            assert rc == T.OK and st["converged"] == 1
+            xs[inner] = x
+    finally:
+        T.tune_clear()
+    A = _oracle_A(f, T.MHATDAGMHAT)
+    for inner in (T.F64, T.F32, T.F16):
+        assert D.true_rel_residual(A, b, xs[inner]) <= 1e-10, inner
+    for inner in (T.F32, T.F16):
+        assert rel(xs[inner], xs[T.F64]) < 1e-6, inner
