@@ -148,6 +148,7 @@ def test_cg_mixed_production_shape_32x32x32x64():
     """32^3 x 64, kappa = 0.162, mu = 0.003 (the mixed-precision workload): FP64, FP32- and FP16-inner CG in
     their tuned launch shapes reach the FP64 1e-10 residual that the oracle recomputes, and the three
     solutions agree as far as that residual bound allows."""
+    print("drawing 32^3 x 64 links", flush=True)
     f = cached_fields((32, 32, 32, 64), 0.5, 32, 0.162, 0.003, BC_AP)
     b = synth.gaussian_spinor(f.prob.volume // 2, 34)
     xs = {}
@@ -158,10 +159,12 @@ def test_cg_mixed_production_shape_32x32x32x64():
             x, st, rc = _solve(f, T.MHATDAGMHAT, b, inner=inner, tol=1e-10)
             assert rc == T.OK and st["converged"] == 1
             xs[inner] = x
+            print(f"inner precision {inner}: {st['iters']} iterations", flush=True)
     finally:
         T.tune_clear()
     A = _oracle_A(f, T.MHATDAGMHAT)
     for inner in (T.F64, T.F32, T.F16):
         assert D.true_rel_residual(A, b, xs[inner]) <= 1e-10, inner
+        print(f"oracle residual checked for inner precision {inner}", flush=True)
     for inner in (T.F32, T.F16):
         assert rel(xs[inner], xs[T.F64]) < 1e-6, inner
