@@ -260,6 +260,33 @@ def main():
         for k in ("mixed_f32", "mixed_f16"):
             mixed[k]["speedup_vs_fp64"] = round(mixed["fp64"]["ms"] / mixed[k]["ms"], 3)
         mixed["workload"] = "Mhat^dag Mhat, 32^3x64, kappa 0.162, mu 0.003, eps 0.5, tol 1e-10 (FP64 true residual)"
+        # the same solves with 12-real links (the paper's compression) in every precision
+        Um = torch.from_numpy(Um_host).to(dev)
+        g12 = {p: T.pack_gauge(pm, Um, p, 1) for p in (T.F64, T.F32, T.F16)}
+        del Um
+        rec12 = {}
+        for p, name in ((T.F64, "fp64"), (T.F32, "mixed_f32"), (T.F16, "mixed_f16")):
+            T.tune(pm, g12[p], p, 1)
+        for p, name in ((T.F64, "fp64"), (T.F32, "mixed_f32"), (T.F16, "mixed_f16")):
+            best = None
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st, _ = T.cg(pm, g12, bm, xm, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT,
+                                inner_prec=p, recon=1, ws=wsm, check_every=16)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if best is None or dt < best[0]:
+                    best = (dt, st)
+            dt, st = best
+            rec12[name] = {"ms": round(1e3 * dt, 2), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
+                           "true_rel_residual": st["true_rel_residual"], "converged": st["converged"],
+                           "speedup_vs_fp64_rec18": round(mixed["fp64"]["ms"] / (1e3 * dt), 3)}
+        mixed["rec12"] = rec12
+        del g12
+        # the REC18 FP16-inner solution again, for the oracle check below
+        T.cg(pm, gm, bm, xm, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT, inner_prec=T.F16, ws=wsm,
+             check_every=16)
         result["cg_32x32x32x64"] = mixed
         if not args.no_oracle:   # the last solution is the FP16-inner one
             from oracle import dirac as D
