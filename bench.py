@@ -297,6 +297,7 @@ def main():
         del gm, bm, xm, wsm, Um_host
 
     if not args.no_extras:
+        result["small_4x4x4x4"] = bench_small(T, synth, dev, not args.no_oracle)
         result["dslash_sizes_f64_rec18"] = bench_sizes(T, dev)
         result["multi_rhs_24x24x24x48"] = bench_multi_rhs(T, prob, U, dev)
         result["batch_cg"] = bench_batch(T, synth, dev)
@@ -513,6 +514,43 @@ def bench_multi_rhs(T, prob, U, dev):
                    "speedup": round(t_single / t_multi, 3),
                    "bytes_per_site_rhs": round(link / 12 + spin, 1),
                    "multi_GB_s": round(vh * (link + 12 * spin) / t_multi / 1e9, 1)}
+    return out
+
+
+def bench_small(T, synth, dev, check):
+    """4^4 (eps 0.3, kappa 0.15, mu 0.01): every operator once (latency-bound: microseconds per call) and FP64 CG
+    on M^dag M and Mhat^dag Mhat to 1e-10, with the oracle's residuals."""
+    import torch
+    log("4^4 operators and solves")
+    dims, kappa, mu, bc = (4, 4, 4, 4), 0.15, 0.01, (1, 1, 1, -1)
+    prob = T.Problem(dims, kappa, mu, bc)
+    U = synth.random_links(dims, 0.3, 1)
+    g = T.pack_gauge(prob, torch.from_numpy(U).to(dev))
+    out = {"op_us": {}}
+    for name, op in T.OPS.items():
+        sub_in, _ = T.OP_SUBSETS[op]
+        n = prob.volume // (1 if sub_in == T.FULL else 2)
+        src = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(n, 3)).to(dev), T.F64, sub_in)
+        ws = T.workspace(prob, op, 1)
+        out["op_us"][name] = round(_events_time(lambda: T.dslash(prob, g, src, op, ws=ws), 50) * 1e6, 2)
+    for op, name in ((T.MDAGM, "cg_MdagM"), (T.MHATDAGMHAT, "cg_MhatdagMhat")):
+        n = prob.volume if op == T.MDAGM else prob.volume // 2
+        b = synth.gaussian_spinor(n, 4)
+        bp = T.pack_spinor(prob, torch.from_numpy(b).to(dev), T.F64, T.FULL if op == T.MDAGM else T.EVEN)
+        T.cg(prob, {T.F64: g}, bp, tol=1e-10, op=op)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, _ = T.cg(prob, {T.F64: g}, bp, tol=1e-10, op=op)
+        torch.cuda.synchronize()
+        rec = {"us": round((time.perf_counter() - t0) * 1e6, 1), "iters": st["iters"],
+               "true_rel_residual": st["true_rel_residual"]}
+        if check:
+            from oracle import dirac as D
+            xs = T.unpack_spinor(prob, x, T.F64, T.FULL if op == T.MDAGM else T.EVEN).cpu().numpy()
+            A = (lambda v: D.apply_MdagM(U, v, dims, kappa, mu, bc)) if op == T.MDAGM else \
+                (lambda v: D.apply_MhatdagMhat(U, v, dims, kappa, mu, bc))
+            rec["oracle_rel_residual"] = D.true_rel_residual(A, b, xs)
+        out[name] = rec
     return out
 
 
