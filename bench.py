@@ -659,12 +659,19 @@ def bench_hmc(T, synth, dev):
     # the same 20-step trajectories with FP32-inner solves (same FP64 tolerances)
     h32 = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10, inner_prec=T.F32)
     dh32, _, t_traj32 = run(h32, 20)
+    # and with every solve started from the previous solution
+    h32g = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10, inner_prec=T.F32, guess=True)
+    dh32g, _, t_traj32g = run(h32g, 20)
     creutz = creutz_4x4x4x4(T, synth, dev)
     e = np.exp(-np.clip(np.array(dh20), -700, 700))
     ratio = float(np.mean(np.abs(dh20)) / np.mean(np.abs(dh40)))
     return {"force_us": round(t_force * 1e6, 1), "force_GB_s": round(force_bytes / t_force / 1e9, 1),
             "trajectory_s": round(t_traj, 3), "trajectory_s_fp32_inner": round(t_traj32, 3),
             "dH_fp32_inner_max_abs_diff": float(np.max(np.abs(np.array(dh32) - np.array(dh20)))),
+            "trajectory_s_fp32_inner_guess": round(t_traj32g, 3),
+            "dH_fp32_inner_guess_max_abs_diff": float(np.max(np.abs(np.array(dh32g) - np.array(dh20)))),
+            "cg_iters_per_solve_fp32_inner": round(h32.cg_iters / max(1, h32.solves), 1),
+            "cg_iters_per_solve_fp32_inner_guess": round(h32g.cg_iters / max(1, h32g.solves), 1),
             "dH": [round(x, 6) for x in dh20], "acceptance": acc20,
             "exp_minus_dH_mean": round(float(e.mean()), 4),
             "exp_minus_dH_stderr": round(float(e.std(ddof=1) / math.sqrt(len(e))), 4),

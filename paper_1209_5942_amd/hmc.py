@@ -62,16 +62,23 @@ class HMC:
     FP64 CG; T.F32 or T.F16: defect correction with reliable updates to the
     same FP64 tolerance on the true residual).  A low-precision copy of the
     links is packed from the FP64 links whenever they change.
+
+    guess: start every solve with the same right-hand side phi from the last
+    solution instead of zero (the links moved by one step since); the result
+    still meets the tolerance on the true residual, so only the iteration
+    count changes (and, at the level of the tolerance, the reversibility).
     """
 
     def __init__(self, prob: T.Problem, U_canon, beta: float, tol: float = 1e-12, max_iter: int = 20000,
-                 md_tol: float | None = None, inner_prec: int = T.F64):
+                 md_tol: float | None = None, inner_prec: int = T.F64, guess: bool = False):
         self.prob = prob
         self.beta = float(beta)
         self.tol = tol                      # solves that enter H (acceptance)
         self.md_tol = md_tol or tol         # solves that enter the force
         self.max_iter = max_iter
         self.inner = inner_prec
+        self.guess = guess
+        self._have_x = False      # self.X holds a solution for the current phi
         self.U = T.pack_gauge(prob, U_canon, T.F64, T.RECON18)
         self.U_low = None
         self.refresh_low()
@@ -91,6 +98,7 @@ class HMC:
         """phi = M^+ eta for a Gaussian eta (complex128 device tensor (V, 4, 3))."""
         eta = T.pack_spinor(self.prob, eta_canon, T.F64, T.FULL)
         T.dslash(self.prob, self.U, eta, T.MDAG, out=self.phi, ws=self.ws_dslash)
+        self._have_x = False
 
     def _low(self, U):
         """The links U (packed FP64) packed in the inner precision."""
@@ -106,9 +114,13 @@ class HMC:
         gauges = {T.F64: self.U if U is None else U}
         if self.inner != T.F64:
             gauges[self.inner] = self.U_low if U is None else self._low(U)
-        x = self.X if x is None else x
-        _, st, _ = T.cg(self.prob, gauges, b, x, x_is_zero=True, tol=tol or self.tol, max_iter=self.max_iter,
+        own = x is None
+        x = self.X if own else x
+        start_zero = not (own and self.guess and self._have_x and b is self.phi)
+        _, st, _ = T.cg(self.prob, gauges, b, x, x_is_zero=start_zero, tol=tol or self.tol, max_iter=self.max_iter,
                         op=T.MDAGM, inner_prec=self.inner, ws=self.ws_cg)
+        if own:
+            self._have_x = b is self.phi
         self.solves += 1
         self.cg_iters += st["iters"]
         return x

@@ -169,16 +169,20 @@ def test_creutz_equality_in_equilibrium_4x4x4x4():
 
 
 def test_mixed_precision_trajectory_equals_fp64_16x16x16x32():
-    """FP32-inner solves reach the same FP64 tolerances: the trajectory's dH and links agree with FP64 solves."""
+    """FP32-inner solves reach the same FP64 tolerances: the trajectory's dH and links agree with FP64 solves,
+    also when every solve starts from the previous solution (which must save iterations)."""
     dims = (16, 16, 16, 32)
     f = Fields(dims, 0.4, 611, 0.155, 0.01, BC_AP)
     p = synth.gaussian_momenta(f.prob.volume, 612)
     eta = synth.gaussian_spinor(f.prob.volume, 613)
-    out, links = [], []
-    for inner in (T.F64, T.F32):
-        h = H.HMC(f.prob, f.U_dev, 0.0, tol=1e-12, md_tol=1e-11, inner_prec=inner)
+    out, links, iters = [], [], []
+    for inner, guess in ((T.F64, False), (T.F32, False), (T.F32, True)):
+        h = H.HMC(f.prob, f.U_dev, 0.0, tol=1e-12, md_tol=1e-11, inner_prec=inner, guess=guess)
         out.append(h.trajectory(dev(p), dev(eta), 0.0, 4, 0.05))
         links.append(host(T.unpack_gauge(f.prob, h.U)))
-    assert abs(out[0]["H0"] - out[1]["H0"]) < 1e-9 * abs(out[0]["H0"])
-    assert abs(out[0]["dH"] - out[1]["dH"]) < 1e-6, (out[0]["dH"], out[1]["dH"])
-    assert np.abs(links[0] - links[1]).max() < 1e-9
+        iters.append(h.cg_iters)
+    for k in (1, 2):   # FP32-inner solves, from zero and from the previous solution
+        assert abs(out[0]["H0"] - out[k]["H0"]) < 1e-9 * abs(out[0]["H0"])
+        assert abs(out[0]["dH"] - out[k]["dH"]) < 1e-6, (out[0]["dH"], out[k]["dH"])
+        assert np.abs(links[0] - links[k]).max() < 1e-9
+    assert iters[2] < iters[1]
