@@ -14,6 +14,17 @@ the benchmark may import this module.
       G^a = -2 kappa Im Tr_c[ T^a ( b+ Q1 - conj(b+) Q2 ) ]
       Q1  = sum_spin [(1 - gamma_mu) U_mu(x) X(x+mu)] (x) Y(x)^dag
       Q2  = sum_spin X(x) (x) [U_mu(x) (1 + gamma_mu) Y(x+mu)]^dag
+* Even-odd pseudofermion action (the paper's even-odd preconditioning applied to
+  the HMC): det(M^dag M) = det(A^dag A)_oo det(Mhat^dag Mhat), and the first
+  factor does not depend on U, so the two-flavour action may be taken as
+  S_f^eo = phi_e^dag (Mhat^dag Mhat)^{-1} phi_e on even sites.  Only the hops in
+  Mhat = A_ee - kappa^2 H_eo A_oo^{-1} H_oe depend on U:
+      dMhat = -kappa^2 (dH_eo A^{-1} H_oe + H_eo A^{-1} dH_oe),
+  so with X_e = (Mhat^dag Mhat)^{-1} phi_e, Y_e = Mhat X_e, X_o = A^{-1} H_oe X_e
+  and Y_o = A^{-dag} (H_eo)^dag Y_e,
+      dS = -2 Re(Y_e^dag dMhat X_e) = 2 kappa^2 Re(Y_e^dag dH_eo X_o + Y_o^dag dH_oe X_e),
+  which is the full-lattice form 2 kappa Re(Y^dag dH X) for the full fields
+  X = (X_e, X_o) and Y = kappa (Y_e, Y_o): the same per-link formula.
 * Gauge action: the paper's tree-level Symanzik action with c1 = 0 (its
   unimproved limit), normalised S_g = (beta/3) sum_{x, mu<nu} (3 - Re Tr P_mu_nu(x)).
   Its gradient is G^a = (beta/3) Im Tr[T^a U_mu(x) V_mu(x)] with V_mu(x) the sum
@@ -25,10 +36,11 @@ import numpy as np
 
 from paper_1209_5942_amd.synth import gell_mann
 
-from .dirac import AXIS, GAMMA, ID4, apply_MdagM, cg, shape4
+from .dirac import (AXIS, GAMMA, ID4, apply_MdagM, apply_Mhat, apply_MhatdagMhat, cg, hop_pq, shape4, to_full,
+                    twist_inv)
 
-__all__ = ["T_GEN", "fermion_force", "fermion_action", "plaquette_sum", "gauge_action",
-           "gauge_force", "staple_sum"]
+__all__ = ["T_GEN", "fermion_force", "fermion_action", "fermion_action_eo", "fermion_force_eo", "plaquette_sum",
+           "gauge_action", "gauge_force", "staple_sum"]
 
 T_GEN = gell_mann() / 2
 
@@ -70,6 +82,22 @@ def fermion_action(U, phi, dims, kappa, mu, bc, tol: float = 1e-14, solve=None):
     else:
         x = solve(U, phi)
     return float(np.vdot(phi, x).real), x
+
+
+def fermion_action_eo(U, phi_e, dims, kappa, mu, bc, tol: float = 1e-14):
+    """S_f^eo = Re phi_e^dag (Mhat^dag Mhat)^{-1} phi_e.  Returns (S_f^eo, X_e)."""
+    x, _ = cg(lambda v: apply_MhatdagMhat(U, v, dims, kappa, mu, bc), phi_e, tol)
+    return float(np.vdot(phi_e, x).real), x
+
+
+def fermion_force_eo(U, X_e, dims, kappa, mu, bc) -> np.ndarray:
+    """dS_f^eo/dw^a for every link, shape (V, 4, 8), from X_e = (Mhat^dag Mhat)^{-1} phi_e."""
+    y_e = apply_Mhat(U, X_e, dims, kappa, mu, bc)
+    x_o = twist_inv(hop_pq(U, X_e, dims, bc, 1), kappa, mu)
+    y_o = twist_inv(hop_pq(U, y_e, dims, bc, 1, dagger=True), kappa, -mu)
+    x = to_full(X_e, dims, 0) + to_full(x_o, dims, 1)
+    y = kappa * (to_full(y_e, dims, 0) + to_full(y_o, dims, 1))
+    return fermion_force(U, x, y, dims, kappa, bc)
 
 
 def _shift(a, dims, mu, step):

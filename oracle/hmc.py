@@ -13,16 +13,29 @@ the benchmark may import this module.
   balance requires.
 * Metropolis: accept with probability min(1, exp(-(H' - H))); the paper prints
   the exponent without its minus sign.
+* The paper's production integrator (its HMC section): the second-order
+  minimal-norm (2MN, Omelyan) scheme on two timescales, the fermion force on
+  the outer scale and the gauge force on the inner one (Sexton-Weingarten
+  nesting).  One outer step of dt, with lam = 0.1931833275037836:
+      p -= lam dt G_f;  inner(dt/2);  p -= (1 - 2 lam) dt G_f;  inner(dt/2);  p -= lam dt G_f
+  and inner(tau) = n_inner steps of h = tau/n_inner of the same scheme with the
+  gauge force and the link updates U <- exp(i (h/2) p^a T^a) U in place of inner.
+  Without a gauge force inner(tau) is the link update over tau.
+* Even-odd HMC: the pseudofermion lives on even sites, phi_e = Mhat^dag eta_e,
+  and the action is S_f^eo (see force.py).
 Random numbers (momenta, eta, the Metropolis uniform) are inputs.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .dirac import apply_M, apply_Mdag, apply_MdagM, cg
-from .force import T_GEN, fermion_force, gauge_action, gauge_force
+from .dirac import apply_M, apply_Mdag, apply_MdagM, apply_Mhatdag, apply_MhatdagMhat, cg
+from .force import T_GEN, fermion_force, fermion_force_eo, gauge_action, gauge_force
 
-__all__ = ["su3_exp", "hamiltonian", "total_gradient", "leapfrog", "trajectory"]
+__all__ = ["su3_exp", "hamiltonian", "total_gradient", "leapfrog", "trajectory", "LAMBDA_2MN", "omelyan",
+           "hamiltonian_eo", "trajectory_eo"]
+
+LAMBDA_2MN = 0.1931833275037836
 
 
 def su3_exp(p, dt) -> np.ndarray:
@@ -87,3 +100,76 @@ def trajectory(U, p, eta, uniform, dims, kappa, mu, bc, beta, n_steps, dt, tol=1
     accepted = bool(uniform < np.exp(-dh))
     return {"U": u1 if accepted else U, "accepted": accepted, "dH": dh, "H0": h0, "H1": h1,
             "phi": phi, "U_proposed": u1, "p_proposed": p1}
+
+
+class _ActionEO:
+    """The even-odd pseudofermion action and, separately, the Wilson gauge action."""
+
+    def __init__(self, dims, kappa, mu, bc, beta, tol):
+        self.dims, self.kappa, self.mu, self.bc, self.beta, self.tol = dims, kappa, mu, bc, beta, tol
+
+    def solve(self, U, phi_e):
+        a = lambda v: apply_MhatdagMhat(U, v, self.dims, self.kappa, self.mu, self.bc)
+        x, _ = cg(a, phi_e, self.tol)
+        return x
+
+    def s_fermion(self, U, phi_e):
+        return float(np.vdot(phi_e, self.solve(U, phi_e)).real)
+
+    def fermion_gradient(self, U, phi_e):
+        return fermion_force_eo(U, self.solve(U, phi_e), self.dims, self.kappa, self.mu, self.bc)
+
+    def gauge_gradient(self, U):
+        return gauge_force(U, self.dims, self.beta)
+
+
+def omelyan(U, p, grad_outer, grad_inner, n_outer, dt, n_inner=1, lam=LAMBDA_2MN):
+    """Two-level 2MN integration of (U, p) over n_outer * dt; returns new copies.
+
+    grad_outer(U) is the gradient integrated on the outer scale, grad_inner(U)
+    (or None) the one integrated on the inner scale.
+    """
+    def inner(u, q, tau):
+        if grad_inner is None:
+            return su3_exp(q, tau) @ u, q
+        h = tau / n_inner
+        for _ in range(n_inner):
+            q = q - lam * h * grad_inner(u)
+            u = su3_exp(q, 0.5 * h) @ u
+            q = q - (1.0 - 2.0 * lam) * h * grad_inner(u)
+            u = su3_exp(q, 0.5 * h) @ u
+            q = q - lam * h * grad_inner(u)
+        return u, q
+
+    u, q = U.copy(), p.copy()
+    for _ in range(n_outer):
+        q = q - lam * dt * grad_outer(u)
+        u, q = inner(u, q, 0.5 * dt)
+        q = q - (1.0 - 2.0 * lam) * dt * grad_outer(u)
+        u, q = inner(u, q, 0.5 * dt)
+        q = q - lam * dt * grad_outer(u)
+    return u, q
+
+
+def hamiltonian_eo(U, p, phi_e, dims, kappa, mu, bc, beta, tol=1e-14) -> float:
+    act = _ActionEO(dims, kappa, mu, bc, beta, tol)
+    h = 0.5 * float(np.sum(p * p)) + act.s_fermion(U, phi_e)
+    if beta != 0:
+        h += gauge_action(U, dims, beta)
+    return h
+
+
+def trajectory_eo(U, p, eta_e, uniform, dims, kappa, mu, bc, beta, n_outer, dt, n_inner=1, tol=1e-14):
+    """One even-odd HMC trajectory with the two-level 2MN integrator (fermion force outer, gauge force inner).
+
+    Returns dict(U, accepted, dH, H0, H1, phi_e, U_proposed, p_proposed)."""
+    act = _ActionEO(dims, kappa, mu, bc, beta, tol)
+    phi_e = apply_Mhatdag(U, eta_e, dims, kappa, mu, bc)
+    h0 = hamiltonian_eo(U, p, phi_e, dims, kappa, mu, bc, beta, tol)
+    grad_inner = act.gauge_gradient if beta != 0 else None
+    u1, p1 = omelyan(U, p, lambda u: act.fermion_gradient(u, phi_e), grad_inner, n_outer, dt, n_inner)
+    h1 = hamiltonian_eo(u1, p1, phi_e, dims, kappa, mu, bc, beta, tol)
+    dh = h1 - h0
+    accepted = bool(uniform < np.exp(-dh))
+    return {"U": u1 if accepted else U, "accepted": accepted, "dH": dh, "H0": h0, "H1": h1,
+            "phi_e": phi_e, "U_proposed": u1, "p_proposed": p1}

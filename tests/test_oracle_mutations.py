@@ -7,10 +7,12 @@ of test_oracle_operator and test_oracle_force_hmc, called unchanged.
 import numpy as np
 import pytest
 
+import test_oracle_eo_hmc as PE
 import test_oracle_force_hmc as PF
 import test_oracle_operator as PO
 from oracle import dirac as D
 from oracle import force as F
+from oracle import hmc as H
 
 OPERATOR_PINS = [
     lambda: PO.test_free_field_spectrum_M_2x2x2x2(0.15, 0.01),
@@ -76,3 +78,68 @@ def test_planted_force_mistake_fails_a_pin(monkeypatch, name):
     FORCE_MUTATIONS[name](monkeypatch)
     pins = [lambda: PF.test_fermion_force_vs_finite_differences(PF.BC), PF.test_gauge_force_vs_finite_differences]
     assert _caught(pins), f"no pin caught the planted mistake: {name}"
+
+
+def _eo_force_with(y_odd=1.0, y_mu_sign=-1.0, y_kappa=True, x_odd_dag=False):
+    """The even-odd force with one planted change to how the odd halves or the kappa factor are formed."""
+    def f(U, X_e, dims, kappa, mu, bc):
+        y_e = D.apply_Mhat(U, X_e, dims, kappa, mu, bc)
+        x_o = D.twist_inv(D.hop_pq(U, X_e, dims, bc, 1, dagger=x_odd_dag), kappa, mu)
+        y_o = D.twist_inv(D.hop_pq(U, y_e, dims, bc, 1, dagger=True), kappa, y_mu_sign * mu)
+        x = D.to_full(X_e, dims, 0) + D.to_full(x_o, dims, 1)
+        y = D.to_full(y_e, dims, 0) + y_odd * D.to_full(y_o, dims, 1)
+        return F.fermion_force(U, x, (kappa if y_kappa else 1.0) * y, dims, kappa, bc)
+    return f
+
+
+EO_FORCE_MUTATIONS = {
+    "odd half of Y dropped": dict(y_odd=0.0),
+    "Y_o with A(mu)^-1 in place of A(-mu)^-1": dict(y_mu_sign=1.0),
+    "kappa factor on Y dropped": dict(y_kappa=False),
+    "X_o from the daggered hop": dict(x_odd_dag=True),
+}
+
+
+def test_unmutated_eo_force_copy_passes():
+    import unittest.mock as um
+    with um.patch.object(F, "fermion_force_eo", _eo_force_with()):
+        PE.test_eo_force_vs_finite_differences(PE.BC_TWIST, 0.2, PE.SITES[:2])
+
+
+@pytest.mark.parametrize("name", list(EO_FORCE_MUTATIONS))
+def test_planted_eo_force_mistake_fails_a_pin(monkeypatch, name):
+    monkeypatch.setattr(F, "fermion_force_eo", _eo_force_with(**EO_FORCE_MUTATIONS[name]))
+    pins = [lambda: PE.test_eo_force_vs_finite_differences(PE.BC_TWIST, 0.2, PE.SITES[:2])]
+    assert _caught(pins), f"no pin caught the planted mistake: {name}"
+
+
+def _omelyan_with(w_mid):
+    """2MN with the middle fermion-force weight replaced by w_mid(lam) (the scheme needs 1 - 2 lam)."""
+    def integ(U, p, grad_outer, grad_inner, n_outer, dt, n_inner=1, lam=H.LAMBDA_2MN):
+        def inner(u, q, tau):
+            if grad_inner is None:
+                return H.su3_exp(q, tau) @ u, q
+            h = tau / n_inner
+            for _ in range(n_inner):
+                q = q - lam * h * grad_inner(u)
+                u = H.su3_exp(q, 0.5 * h) @ u
+                q = q - w_mid(lam) * h * grad_inner(u)
+                u = H.su3_exp(q, 0.5 * h) @ u
+                q = q - lam * h * grad_inner(u)
+            return u, q
+        u, q = U.copy(), p.copy()
+        for _ in range(n_outer):
+            q = q - lam * dt * grad_outer(u)
+            u, q = inner(u, q, 0.5 * dt)
+            q = q - w_mid(lam) * dt * grad_outer(u)
+            u, q = inner(u, q, 0.5 * dt)
+            q = q - lam * dt * grad_outer(u)
+        return u, q
+    return integ
+
+
+@pytest.mark.parametrize("w_mid", [lambda lam: 1.0 - 2.0 * lam, lambda lam: 1.0 - lam, lambda lam: 2.0 * lam])
+def test_planted_2mn_weight_mistake_fails_a_pin(monkeypatch, w_mid):
+    monkeypatch.setattr(H, "omelyan", _omelyan_with(w_mid))
+    caught = _caught([lambda: PE.test_omelyan_energy_error_is_second_order(3)])
+    assert caught == (abs(2.0 * H.LAMBDA_2MN + w_mid(H.LAMBDA_2MN) - 1.0) > 1e-12), "the dt^2 pin must fail exactly when the weights do not sum to one"
