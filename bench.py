@@ -411,25 +411,30 @@ def traffic_from_counters(fetch_csv, write_csv, kernel_log):
     print(json.dumps(rec))
 
 
-def creutz_4x4x4x4(T, synth, dev):
-    """<exp(-dH)> over a 4^4 Markov chain (beta 5.5, kappa 0.15, mu 0.01, tau 0.5 in 10 steps) after burn-in."""
+def creutz_4x4x4x4(T, synth, dev, eo=False):
+    """<exp(-dH)> over a 4^4 Markov chain (beta 5.5, kappa 0.15, mu 0.01, tau 0.5) after burn-in: the
+    full-lattice action with 10 leapfrog steps, or (eo) the even-odd action with 4 outer 2MN steps of 2
+    inner steps each."""
     import math
 
     import numpy as np
     import torch
 
     from paper_1209_5942_amd.hmc import HMC
-    log("Creutz equality on 4^4")
+    log(f"Creutz equality on 4^4 ({'even-odd, 2MN' if eo else 'leapfrog'})")
     dims = (4, 4, 4, 4)
     prob = T.Problem(dims, 0.15, 0.01, (1, 1, 1, -1))
     h = HMC(prob, torch.from_numpy(synth.random_links(dims, 0.3, 601).reshape(-1, 4, 3, 3)).to(dev), beta=5.5,
-            tol=1e-12, md_tol=1e-10)
+            tol=1e-12, md_tol=1e-10, eo=eo)
     rng = np.random.default_rng(602)
     dh, acc = [], 0
     for k in range(200):
         p = torch.from_numpy(synth.gaussian_momenta(prob.volume, 10000 + k)).to(dev)
-        eta = torch.from_numpy(synth.gaussian_spinor(prob.volume, 20000 + k)).to(dev)
-        out = h.trajectory(p, eta, float(rng.random()), 10, 0.05)
+        eta = torch.from_numpy(synth.gaussian_spinor(prob.volume // 2 if eo else prob.volume, 20000 + k)).to(dev)
+        if eo:
+            out = h.trajectory(p, eta, float(rng.random()), 4, 0.125, integrator="2mn", n_inner=2)
+        else:
+            out = h.trajectory(p, eta, float(rng.random()), 10, 0.05)
         if k >= 40:
             dh.append(out["dH"])
             acc += int(out["accepted"])
@@ -621,7 +626,8 @@ def bench_batch(T, synth, dev):
 
 
 def bench_hmc(T, synth, dev):
-    """16^3x32, eps 0.4, kappa 0.155, mu 0.01: force kernel time and 10 leapfrog trajectories (tau 1, 20 steps)."""
+    """16^3x32, eps 0.4, kappa 0.155, mu 0.01: force kernel times, 10 leapfrog trajectories (tau 1, 20 steps)
+    of the full-lattice action and 10 two-level 2MN trajectories (tau 1, 10 outer steps) of the even-odd one."""
     import math
 
     import numpy as np
@@ -639,15 +645,21 @@ def bench_hmc(T, synth, dev):
     t_force = _events_time(lambda: T.force(prob, h.U, X, Y, out=G), 20)
     # compulsory bytes per site: 4 links, X and Y once each, the 4 x 8 outputs
     force_bytes = prob.volume * (4 * 144 + 2 * 192 + 256)
-    def run(hmc, n_steps):
+    # the even-odd force: three hops (X_o, Y_e = Mhat X_e, Y_o) and the force kernel
+    Xe = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(prob.volume // 2, 83)).to(dev), T.F64, T.EVEN)
+    ws_eo = T._bytes(T.force_eo_workspace_bytes(prob), dev)
+    t_force_eo = _events_time(lambda: T.force_eo(prob, h.U, Xe, out=G, ws=ws_eo), 20)
+
+    def run(hmc, n_steps, integrator="leapfrog"):
         dh, acc = [], 0
+        n_eta = prob.volume // 2 if hmc.eo else prob.volume
         t0 = time.perf_counter()
         for k in range(10):
             p = torch.from_numpy(synth.gaussian_momenta(prob.volume, 1000 + k)).to(dev)
-            eta = torch.from_numpy(synth.gaussian_spinor(prob.volume, 2000 + k)).to(dev)
+            eta = torch.from_numpy(synth.gaussian_spinor(n_eta, 2000 + k)).to(dev)
             u = float(np.random.default_rng(3000 + k).random())
             hmc.U.copy_(U_start)   # every trajectory from the same start: dH of one field, two step sizes
-            out = hmc.trajectory(p, eta, u, n_steps, 1.0 / n_steps)
+            out = hmc.trajectory(p, eta, u, n_steps, 1.0 / n_steps, integrator=integrator)
             dh.append(out["dH"])
             acc += int(out["accepted"])
         torch.cuda.synchronize()
@@ -662,6 +674,15 @@ def bench_hmc(T, synth, dev):
     # and with every solve started from the previous solution
     h32g = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10, inner_prec=T.F32, guess=True)
     dh32g, _, t_traj32g = run(h32g, 20)
+    # the even-odd action with the two-level 2MN integrator: 10 outer steps take 21 fermion forces, as
+    # 20 leapfrog steps do; 20 outer steps for the dt^2 scaling; and with FP32-inner solves from the
+    # previous solution
+    heo = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10, eo=True)
+    dh_eo, acc_eo, t_eo = run(heo, 10, "2mn")
+    it_eo = heo.cg_iters / max(1, heo.solves)
+    dh_eo20, _, _ = run(heo, 20, "2mn")
+    heo32g = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10, eo=True, inner_prec=T.F32, guess=True)
+    dh_eo32g, acc_eo32g, t_eo32g = run(heo32g, 10, "2mn")
     creutz = creutz_4x4x4x4(T, synth, dev)
     e = np.exp(-np.clip(np.array(dh20), -700, 700))
     ratio = float(np.mean(np.abs(dh20)) / np.mean(np.abs(dh40)))
@@ -679,9 +700,22 @@ def bench_hmc(T, synth, dev):
             "mean_abs_dH_ratio_20_to_40_steps": round(ratio, 3),
             "cg_iters_per_solve": round(h.cg_iters / max(1, h.solves), 1),
             "creutz_4x4x4x4": creutz,
+            "force_eo_us": round(t_force_eo * 1e6, 1),
+            "eo_2mn": {"trajectory_s": round(t_eo, 3), "dH": [round(x, 6) for x in dh_eo], "acceptance": acc_eo,
+                       "mean_abs_dH": round(float(np.mean(np.abs(dh_eo))), 6),
+                       "mean_abs_dH_ratio_10_to_20_outer_steps":
+                           round(float(np.mean(np.abs(dh_eo)) / np.mean(np.abs(dh_eo20))), 3),
+                       "cg_iters_per_solve": round(it_eo, 1),
+                       "trajectory_s_fp32_inner_guess": round(t_eo32g, 3),
+                       "acceptance_fp32_inner_guess": acc_eo32g,
+                       "dH_fp32_inner_guess_max_abs_diff": float(np.max(np.abs(np.array(dh_eo32g) - np.array(dh_eo)))),
+                       "cg_iters_per_solve_fp32_inner_guess": round(heo32g.cg_iters / max(1, heo32g.solves), 1),
+                       "creutz_4x4x4x4": creutz_4x4x4x4(T, synth, dev, eo=True)},
+            "leapfrog_mean_abs_dH": round(float(np.mean(np.abs(dh20))), 6),
             "setup": "two-flavour twisted-mass pseudofermion action (beta = 0), tau = 1 leapfrog with 20 steps "
                      "(and 40: second-order integrator, mean |dH| ratio near 4) from the eps 0.4 start, force solves "
-                     "1e-10, acceptance solves 1e-12"}
+                     "1e-10, acceptance solves 1e-12; eo_2mn: the even-odd action and the two-level 2MN "
+                     "integrator with 10 outer steps (and 20), the same solver tolerances"}
 
 
 if __name__ == "__main__":

@@ -210,6 +210,24 @@ int tmqcd_cg_batch(int n, const tmqcd_problem* probs, const void* const* U_packe
 int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X,
                 const void* Y, double* dSdw, double scale, int accumulate, void* stream);
 
+/* The force of the even-odd pseudofermion action S_f = phi_e^+ (Mhat^+ Mhat)^{-1} phi_e
+ * (the paper's force section for the Schur complement of its even-odd
+ * preconditioning; the hybrid Monte-Carlo of its ensemble-generation section runs
+ * on this action), given X_e = (Mhat^+ Mhat)^{-1} phi_e as a packed FP64 even
+ * field.  The links enter only through H_eo and H_oe, so G is the full-lattice
+ * formula of tmqcd_force evaluated at
+ *   X = (X_e, A(mu)^{-1} H_oe X_e),   Y = kappa (Y_e, A(-mu)^{-1} (H^+)_oe Y_e),  Y_e = Mhat X_e.
+ * Three hops build X_o, Y_e and Y_o in ws (tmqcd_force_eo_workspace_bytes(prob)
+ * bytes, device, 256-byte aligned, caller-owned, overwritten), then the force
+ * kernel writes or accumulates scale * G into dSdw[V][4][8] as tmqcd_force does.
+ * U_packed: FP64, RECON18 or RECON12.  dSdw may not overlap X_e, U_packed or ws.
+ * Errors: TMQCD_EINVAL (bad problem, recon, null pointer, non-finite scale,
+ * accumulate not 0/1), TMQCD_EALIGN, TMQCD_EWORKSPACE (ws missing or short),
+ * TMQCD_EALIAS; TMQCD_EHIP if a launch fails. */
+size_t tmqcd_force_eo_workspace_bytes(const tmqcd_problem* prob);
+int tmqcd_force_eo(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X_e, double* dSdw,
+                   double scale, int accumulate, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- hybrid Monte-Carlo helpers (the paper's ensemble-generation section) ----- */
 /* Gradient of the Wilson plaquette action S_g = (beta/3) sum_{x,mu<nu} (3 - Re Tr P_mu_nu(x))
  * (the paper's tree-level Symanzik action at c1 = 0; no boundary phases):

@@ -264,8 +264,36 @@ int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, cons
         return TMQCD_EALIAS;
     Cplx bc[4];
     for (int i = 0; i < 4; ++i) bc[i] = {prob->bc[i][0], prob->bc[i][1]};
+    const int64_t hb = half_field_bytes(g, TMQCD_F64);
+    const void* const Xp[2] = {X, static_cast<const char*>(X) + hb};
+    const void* const Yp[2] = {Y, static_cast<const char*>(Y) + hb};
     const hipError_t e =
-        launch_force(g, U_packed, recon, X, Y, dSdw, bc, prob->kappa, scale, accumulate, (hipStream_t)stream);
+        launch_force(g, U_packed, recon, Xp, Yp, dSdw, bc, prob->kappa, scale, accumulate, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+size_t tmqcd_force_eo_workspace_bytes(const tmqcd_problem* prob) {
+    if (!valid_problem(prob)) return 0;
+    return (size_t)force_eo_tmp_bytes(make_geom(*prob));
+}
+
+int tmqcd_force_eo(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X_e, double* dSdw,
+                   double scale, int accumulate, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_problem(prob) || !valid_recon(recon) || !U_packed || !X_e || !dSdw || !std::isfinite(scale) ||
+        (accumulate != 0 && accumulate != 1))
+        return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes) || !aligned(X_e, kAlignBytes) || !aligned(dSdw, 16)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int64_t need = force_eo_tmp_bytes(g);
+    if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
+    if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+    const int64_t fe = field_bytes(g, TMQCD_F64, TMQCD_EVEN), ob = mom_bytes(g),
+                  gb = gauge_bytes(g, TMQCD_F64, recon);
+    if (overlap(dSdw, ob, X_e, fe) || overlap(dSdw, ob, U_packed, gb) || overlap(dSdw, ob, ws, need) ||
+        overlap(ws, need, X_e, fe) || overlap(ws, need, U_packed, gb))
+        return TMQCD_EALIAS;
+    const OpCtx c = make_ctx(*prob, TMQCD_F64, recon, U_packed, (hipStream_t)stream);
+    const hipError_t e = force_eo(c, X_e, dSdw, scale, accumulate, static_cast<char*>(ws));
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 

@@ -67,10 +67,10 @@ __device__ __forceinline__ void proj_mul(Spinor<double>& out, const Su3<double>&
 
 struct ForceK {
     const char* gauge;
-    const char* X;
-    const char* Y;
+    const char* X[2];   // by parity: the even and the odd half of X
+    const char* Y[2];
     double* out;
-    int64_t stride, gstride, hbytes;
+    int64_t stride, gstride;
     int L[4];
     int lxh, vh, nb_half;
     C<double> bc[4];
@@ -82,8 +82,8 @@ struct ForceK {
 template <int R, int MU>
 __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int nh, bool cross,
                                           const Spinor<double>& xo, const Spinor<double>& yo, double* g) {
-    const char* Xn = a.X + (int64_t)(1 - par) * a.hbytes;
-    const char* Yn = a.Y + (int64_t)(1 - par) * a.hbytes;
+    const char* Xn = a.X[1 - par];
+    const char* Yn = a.Y[1 - par];
     Su3<double> u;
     LinkIO<TMQCD_F64, R>::template load<true>(u, a.gauge, a.gstride, par, MU, h);
     Spinor<double> xn, yn, v1, v2;
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(kBlock, 2) void force_dir_kernel(const ForceK a) {
         const int x = 2 * xh + bit;
 
         Spinor<double> xo, yo;
-        SpinorIO<TMQCD_F64>::load(xo, a.X + (int64_t)par * a.hbytes, a.stride, h);
-        SpinorIO<TMQCD_F64>::load(yo, a.Y + (int64_t)par * a.hbytes, a.stride, h);
+        SpinorIO<TMQCD_F64>::load(xo, a.X[par], a.stride, h);
+        SpinorIO<TMQCD_F64>::load(yo, a.Y[par], a.stride, h);
         double g[8];
         if (mu == 0) {
             const int xf = x + 1 == lx ? 0 : x + 1;
@@ -189,16 +189,17 @@ __global__ __launch_bounds__(kBlock, 2) void force_dir_kernel(const ForceK a) {
 
 }  // namespace
 
-hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* X, const void* Y, double* out,
-                        const Cplx bc[4], double kappa, double scale, int accumulate, hipStream_t s) {
+hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* const X[2], const void* const Y[2],
+                        double* out, const Cplx bc[4], double kappa, double scale, int accumulate, hipStream_t s) {
     ForceK k;
     k.gauge = static_cast<const char*>(gauge);
-    k.X = static_cast<const char*>(X);
-    k.Y = static_cast<const char*>(Y);
+    for (int p = 0; p < 2; ++p) {
+        k.X[p] = static_cast<const char*>(X[p]);
+        k.Y[p] = static_cast<const char*>(Y[p]);
+    }
     k.out = out;
     k.stride = g.stride;
     k.gstride = g.gstride;
-    k.hbytes = half_field_bytes(g, TMQCD_F64);
     for (int i = 0; i < 4; ++i) {
         k.L[i] = g.L[i];
         k.bc[i] = {bc[i].re, bc[i].im};

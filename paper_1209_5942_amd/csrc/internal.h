@@ -135,9 +135,10 @@ hipError_t launch_pack_spinor(const Geom& g, const void* canon, void* packed, in
                               bool unpack, hipStream_t s);
 
 // ---- fermion force ---------------------------------------------------------------
-// out = scale * G (accumulate = 0) or out += scale * G (accumulate = 1)
-hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* X, const void* Y, double* out,
-                        const Cplx bc[4], double kappa, double scale, int accumulate, hipStream_t s);
+// out = scale * G (accumulate = 0) or out += scale * G (accumulate = 1); X[p], Y[p]: the
+// parity-p halves of the two FP64 fields (of one full field, or from separate buffers)
+hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void* const X[2], const void* const Y[2],
+                        double* out, const Cplx bc[4], double kappa, double scale, int accumulate, hipStream_t s);
 
 // ---- bandwidth probe (probe.hip): read (dst == nullptr; xor of the words into *xor_out) or copy
 hipError_t launch_hbm_probe(const void* src, void* dst, int64_t bytes, int grid, unsigned* xor_out, hipStream_t s);

@@ -230,6 +230,33 @@ int64_t dslash_tmp_bytes(const Geom& g, int op, int prec) {
     return 0;
 }
 
+// ------------------------------------------------------ even-odd force ---
+// S = phi_e^+ (Mhat^+ Mhat)^{-1} phi_e with X_e = (Mhat^+ Mhat)^{-1} phi_e.  The
+// links enter Mhat only through H_eo and H_oe, and differentiating both hops gives
+// the full-lattice force formula with
+//   X = (X_e, X_o),        X_o = A(mu)^{-1} H_oe X_e,
+//   Y = kappa (Y_e, Y_o),  Y_e = Mhat X_e,  Y_o = A(-mu)^{-1} (H^+)_oe Y_e,
+// (the paper's force section applied to the Schur complement of its even-odd
+// preconditioning).  X_o is the first half of Mhat X_e, so three hops make all
+// three fields; the kappa of Y goes into the force's scale.
+hipError_t force_eo(const OpCtx& c, const void* X_e, double* out, double scale, int accumulate, char* tmp) {
+    const int64_t hb = half_field_bytes(c.g, TMQCD_F64);
+    char* x_o = tmp;
+    char* y_e = tmp + hb;
+    char* y_o = tmp + 2 * hb;
+    hipError_t e = op_schur_first(c, X_e, x_o, false);
+    if (e != hipSuccess) return e;
+    e = op_schur_second(c, x_o, X_e, y_e, false, kEpiStore, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (e != hipSuccess) return e;
+    e = op_schur_first(c, y_e, y_o, true);
+    if (e != hipSuccess) return e;
+    const void* const X[2] = {X_e, x_o};
+    const void* const Y[2] = {y_e, y_o};
+    return launch_force(c.g, c.gauge, c.recon, X, Y, out, c.bc, c.kappa, scale * c.kappa, accumulate, c.s);
+}
+
+int64_t force_eo_tmp_bytes(const Geom& g) { return 3 * half_field_bytes(g, TMQCD_F64); }
+
 // ------------------------------------------------------------- workspace ---
 static int64_t align(int64_t v) { return round_up(v, kAlignBytes); }
 

@@ -36,6 +36,11 @@ HopParams hp_schur_second(const OpCtx& c, const void* t_o, const void* own_e, vo
 hipError_t apply_operator(const OpCtx& c, int op, const void* in, void* out, char* tmp, int nrhs);
 int64_t dslash_tmp_bytes(const Geom& g, int op, int prec);
 
+// The even-odd fermion force (see ops.cpp): scale * G written into or added to out;
+// X_e: packed FP64 even field; tmp: force_eo_tmp_bytes(g) bytes.  c.prec must be FP64.
+hipError_t force_eo(const OpCtx& c, const void* X_e, double* out, double scale, int accumulate, char* tmp);
+int64_t force_eo_tmp_bytes(const Geom& g);
+
 struct CgWorkspace {
     CgState* st;
     double* partials;

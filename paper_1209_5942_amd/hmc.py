@@ -1,15 +1,23 @@
-"""Leapfrog hybrid Monte-Carlo and the differentiable pseudofermion action on the HIP library.
+"""Hybrid Monte-Carlo and the differentiable pseudofermion action on the HIP library.
 
 Paper, ensemble-generation section: H = 1/2 P^2 + S_g + S_f with momenta P
 conjugate to U, evolved with a symplectic integrator and followed by a
 Metropolis step.  Here:
 
-* S_f = phi^+ (M^+ M)^{-1} phi on the full lattice, phi = M^+ eta refreshed
-  from a Gaussian eta (random numbers are inputs);
+* S_f = phi^+ (M^+ M)^{-1} phi on the full lattice, phi = M^+ eta, or (eo=True)
+  the even-odd action S_f = phi_e^+ (Mhat^+ Mhat)^{-1} phi_e, phi_e = Mhat^+ eta_e,
+  with the pseudofermion on even sites only; eta Gaussian (random numbers are
+  inputs);
 * S_g = (beta/3) sum_{x,mu<nu} (3 - Re Tr P_mu_nu) (the tree-level Symanzik
   action at c1 = 0);
 * leapfrog: half momentum step, n times (link step, momentum step), the last
   momentum step a half step; U <- exp(i dt p^a T^a) U; p <- p - dt G;
+* the paper's production integrator, second-order minimal norm (2MN, Omelyan)
+  on two timescales: per outer step dt the fermion force kicks with weights
+  lam, 1 - 2 lam, lam around two inner integrations over dt/2, each n_inner
+  2MN steps of the gauge force (Sexton-Weingarten nesting); lam = LAMBDA_2MN.
+  Adjacent kicks at the same links are merged, so an outer step costs two
+  fermion forces (one solve each);
 * Metropolis: accept with probability min(1, exp(-(H' - H))).
 
 Every step runs in libtmqcd kernels (CG, force, gauge force, link update,
@@ -25,9 +33,13 @@ import torch
 
 from . import tmqcd as T
 
+# Omelyan, Mryglod and Folk's minimal-norm coefficient of the second-order scheme
+LAMBDA_2MN = 0.1931833275037836
+
 
 class FermionAction(torch.autograd.Function):
-    """S_f(omega) = phi^+ (M^+ M)^{-1} phi at links exp(i omega^a T^a) U.
+    """S_f(omega) = phi^+ (M^+ M)^{-1} phi (or the even-odd phi_e^+ (Mhat^+ Mhat)^{-1} phi_e
+    when the HMC state has eo=True) at links exp(i omega^a T^a) U.
 
     forward(omega, ctx_obj) with omega a float64 device tensor (V, 4, 8) and
     ctx_obj a :class:`HMC`; returns a 0-dim float64 tensor.  The backward pass
@@ -43,13 +55,15 @@ class FermionAction(torch.autograd.Function):
             U = h.U.clone()
             T.update_links(h.prob, U, omega, 1.0)
         X = h.solve(h.phi, U)
-        s = T.dot(h.prob, h.phi, X, T.FULL, ws=h.ws_aux)
+        s = T.dot(h.prob, h.phi, X, h.subset, ws=h.ws_aux)
         ctx.h, ctx.U, ctx.X = h, U, X
         return s[0].clone()
 
     @staticmethod
     def backward(ctx, grad_out):
         h = ctx.h
+        if h.eo:
+            return T.force_eo(h.prob, ctx.U, ctx.X, scale=float(grad_out), ws=h.ws_force), None
         Y = T.dslash(h.prob, ctx.U, ctx.X, T.M, ws=h.ws_dslash)
         G = T.force(h.prob, ctx.U, ctx.X, Y, scale=float(grad_out))
         return G, None
@@ -67,10 +81,13 @@ class HMC:
     solution instead of zero (the links moved by one step since); the result
     still meets the tolerance on the true residual, so only the iteration
     count changes (and, at the level of the tolerance, the reversibility).
+
+    eo: the even-odd pseudofermion action (solves on Mhat^+ Mhat over half the
+    sites, the force of tmqcd_force_eo) in place of the full-lattice one.
     """
 
     def __init__(self, prob: T.Problem, U_canon, beta: float, tol: float = 1e-12, max_iter: int = 20000,
-                 md_tol: float | None = None, inner_prec: int = T.F64, guess: bool = False):
+                 md_tol: float | None = None, inner_prec: int = T.F64, guess: bool = False, eo: bool = False):
         self.prob = prob
         self.beta = float(beta)
         self.tol = tol                      # solves that enter H (acceptance)
@@ -78,15 +95,19 @@ class HMC:
         self.max_iter = max_iter
         self.inner = inner_prec
         self.guess = guess
+        self.eo = eo
+        self.op = T.MHATDAGMHAT if eo else T.MDAGM
+        self.subset = T.EVEN if eo else T.FULL
         self._have_x = False      # self.X holds a solution for the current phi
         self.U = T.pack_gauge(prob, U_canon, T.F64, T.RECON18)
         self.U_low = None
         self.refresh_low()
         dev = self.U.device
-        fb = T.spinor_bytes(prob, T.F64, T.FULL)
-        self.ws_cg = T.workspace(prob, T.MDAGM, 1 | (1 << inner_prec))
-        self.ws_dslash = T.workspace(prob, T.MDAGM, 1)
+        fb = T.spinor_bytes(prob, T.F64, self.subset)
+        self.ws_cg = T.workspace(prob, self.op, 1 | (1 << inner_prec))
+        self.ws_dslash = T.workspace(prob, self.op, 1)
         self.ws_aux = T.aux_workspace(prob)
+        self.ws_force = T._bytes(T.force_eo_workspace_bytes(prob), dev) if eo else None
         self.X = torch.empty(fb, dtype=torch.uint8, device=dev)
         self.Y = torch.empty(fb, dtype=torch.uint8, device=dev)
         self.phi = torch.empty(fb, dtype=torch.uint8, device=dev)
@@ -95,9 +116,10 @@ class HMC:
 
     # --------------------------------------------------------------- pieces ---
     def set_pseudofermion(self, eta_canon):
-        """phi = M^+ eta for a Gaussian eta (complex128 device tensor (V, 4, 3))."""
-        eta = T.pack_spinor(self.prob, eta_canon, T.F64, T.FULL)
-        T.dslash(self.prob, self.U, eta, T.MDAG, out=self.phi, ws=self.ws_dslash)
+        """phi = M^+ eta for a Gaussian eta (complex128 device tensor (V, 4, 3)); with eo,
+        phi_e = Mhat^+ eta_e for eta_e on the even sites ((V/2, 4, 3))."""
+        eta = T.pack_spinor(self.prob, eta_canon, T.F64, self.subset)
+        T.dslash(self.prob, self.U, eta, T.MHATDAG if self.eo else T.MDAG, out=self.phi, ws=self.ws_dslash)
         self._have_x = False
 
     def _low(self, U):
@@ -110,7 +132,7 @@ class HMC:
             self.U_low = self._low(self.U)
 
     def solve(self, b, U=None, tol=None, x=None):
-        """X = (M^+ M)^{-1} b on links U (default: the current links)."""
+        """X = (M^+ M)^{-1} b (with eo, (Mhat^+ Mhat)^{-1} b_e) on links U (default: the current links)."""
         gauges = {T.F64: self.U if U is None else U}
         if self.inner != T.F64:
             gauges[self.inner] = self.U_low if U is None else self._low(U)
@@ -118,27 +140,38 @@ class HMC:
         x = self.X if own else x
         start_zero = not (own and self.guess and self._have_x and b is self.phi)
         _, st, _ = T.cg(self.prob, gauges, b, x, x_is_zero=start_zero, tol=tol or self.tol, max_iter=self.max_iter,
-                        op=T.MDAGM, inner_prec=self.inner, ws=self.ws_cg)
+                        op=self.op, inner_prec=self.inner, ws=self.ws_cg)
         if own:
             self._have_x = b is self.phi
         self.solves += 1
         self.cg_iters += st["iters"]
         return x
 
-    def add_gradient(self, p, scale):
-        """p += scale * (G_fermion + G_gauge) at the current links."""
+    def add_fermion_gradient(self, p, scale):
+        """p += scale * G_fermion at the current links (one solve)."""
         X = self.solve(self.phi, tol=self.md_tol)
-        T.dslash(self.prob, self.U, X, T.M, out=self.Y, ws=self.ws_dslash)
-        T.force(self.prob, self.U, X, self.Y, out=p, scale=scale, accumulate=True)
+        if self.eo:
+            T.force_eo(self.prob, self.U, X, out=p, scale=scale, accumulate=True, ws=self.ws_force)
+        else:
+            T.dslash(self.prob, self.U, X, T.M, out=self.Y, ws=self.ws_dslash)
+            T.force(self.prob, self.U, X, self.Y, out=p, scale=scale, accumulate=True)
+
+    def add_gauge_gradient(self, p, scale):
+        """p += scale * G_gauge at the current links."""
         if self.beta != 0.0:
             T.gauge_force(self.prob, self.U, self.beta, out=p, scale=scale, accumulate=True)
+
+    def add_gradient(self, p, scale):
+        """p += scale * (G_fermion + G_gauge) at the current links."""
+        self.add_fermion_gradient(p, scale)
+        self.add_gauge_gradient(p, scale)
 
     def energies(self, p):
         """(kinetic, S_g, S_f) as Python floats."""
         k = T.momentum_norm2(self.prob, p, ws=self.ws_aux)
         plaq = T.plaquette(self.prob, self.U, ws=self.ws_aux)
         X = self.solve(self.phi, tol=self.tol)
-        sf = T.dot(self.prob, self.phi, X, T.FULL, ws=self.ws_aux)
+        sf = T.dot(self.prob, self.phi, X, self.subset, ws=self.ws_aux)
         n_plaq = 6 * self.prob.volume
         s_g = self.beta / 3.0 * (3.0 * n_plaq - float(plaq[0])) if self.beta != 0.0 else 0.0
         return 0.5 * float(k[0]), s_g, float(sf[0])
@@ -154,13 +187,47 @@ class HMC:
             self.refresh_low()
             self.add_gradient(p, -dt if i < n_steps - 1 else -0.5 * dt)
 
-    def trajectory(self, p, eta_canon, uniform: float, n_steps: int, dt: float) -> dict:
-        """One HMC trajectory from momenta p (modified in place) and a Gaussian eta."""
+    def _inner(self, p, tau: float, n_inner: int, lam: float):
+        """The inner level of 2MN over tau: n_inner steps with the gauge force, or the
+        plain link update when there is no gauge action."""
+        if self.beta == 0.0:
+            T.update_links(self.prob, self.U, p, tau)
+        else:
+            h = tau / n_inner
+            self.add_gauge_gradient(p, -lam * h)
+            for j in range(n_inner):
+                T.update_links(self.prob, self.U, p, 0.5 * h)
+                self.add_gauge_gradient(p, -(1.0 - 2.0 * lam) * h)
+                T.update_links(self.prob, self.U, p, 0.5 * h)
+                self.add_gauge_gradient(p, -(2.0 * lam if j < n_inner - 1 else lam) * h)
+        self.refresh_low()
+
+    def omelyan(self, p, n_outer: int, dt: float, n_inner: int = 1, lam: float = LAMBDA_2MN):
+        """Integrate (U, p) in place over n_outer * dt with the two-level 2MN scheme
+        (fermion force on the outer scale, gauge force on the inner one)."""
+        self.add_fermion_gradient(p, -lam * dt)
+        for i in range(n_outer):
+            self._inner(p, 0.5 * dt, n_inner, lam)
+            self.add_fermion_gradient(p, -(1.0 - 2.0 * lam) * dt)
+            self._inner(p, 0.5 * dt, n_inner, lam)
+            self.add_fermion_gradient(p, -(2.0 * lam if i < n_outer - 1 else lam) * dt)
+
+    def trajectory(self, p, eta_canon, uniform: float, n_steps: int, dt: float, integrator: str = "leapfrog",
+                   n_inner: int = 1) -> dict:
+        """One HMC trajectory from momenta p (modified in place) and a Gaussian eta.
+
+        integrator "leapfrog" (n_steps steps) or "2mn" (n_steps outer steps of the
+        two-level scheme, n_inner inner steps per half outer step)."""
+        if integrator not in ("leapfrog", "2mn"):
+            raise ValueError(f"unknown integrator {integrator!r}")
         self.refresh_low()            # the links may have been set from outside
         self.set_pseudofermion(eta_canon)
         e0 = self.energies(p)
         U0 = self.U.clone()
-        self.leapfrog(p, n_steps, dt)
+        if integrator == "leapfrog":
+            self.leapfrog(p, n_steps, dt)
+        else:
+            self.omelyan(p, n_steps, dt, n_inner)
         e1 = self.energies(p)
         dh = sum(e1) - sum(e0)
         accepted = bool(uniform < math.exp(-dh)) if dh > 0 else True

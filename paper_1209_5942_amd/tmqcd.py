@@ -28,7 +28,8 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
 
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg",
-                "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force", "tmqcd_gauge_force",
+                "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force", "tmqcd_force_eo_workspace_bytes",
+                "tmqcd_force_eo", "tmqcd_gauge_force",
                 "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune", "tmqcd_tune_save",
                 "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set", "tmqcd_tune_mrhs_workspace_bytes",
                 "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot", "tmqcd_hbm_probe",
@@ -99,6 +100,8 @@ def lib():
             "tmqcd_cg_batch_workspace_bytes": (S, [I, P]),
             "tmqcd_cg_batch": (I, [I, P, V, V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats), I, V, S, V]),
             "tmqcd_force": (I, [P, V, I, V, V, V, D, I, V]),
+            "tmqcd_force_eo_workspace_bytes": (S, [P]),
+            "tmqcd_force_eo": (I, [P, V, I, V, V, D, I, V, S, V]),
             "tmqcd_gauge_force": (I, [P, V, D, V, D, I, V]),
             "tmqcd_update_links": (I, [P, V, V, D, V]),
             "tmqcd_plaquette": (I, [P, V, V, V, S, V]),
@@ -343,6 +346,23 @@ def force(prob: Problem, U_packed, X, Y, recon=RECON18, out=None, scale=1.0, acc
     out = _mom(prob, out, X)
     _check(lib().tmqcd_force(ctypes.byref(prob.c()), _ptr(U_packed), recon, _ptr(X), _ptr(Y), _ptr(out),
                              float(scale), int(accumulate), _stream(stream)), "tmqcd_force")
+    return out
+
+
+def force_eo_workspace_bytes(prob: Problem) -> int:
+    return lib().tmqcd_force_eo_workspace_bytes(ctypes.byref(prob.c()))
+
+
+def force_eo(prob: Problem, U_packed, X_e, recon=RECON18, out=None, scale=1.0, accumulate=False, ws=None,
+             stream=None):
+    """scale * dS_f^eo/dw^a (float64 device tensor (V, 4, 8)) of phi_e^+ (Mhat^+ Mhat)^{-1} phi_e from the
+    packed FP64 even field X_e = (Mhat^+ Mhat)^{-1} phi_e; with accumulate the result is added to `out`."""
+    out = _mom(prob, out, X_e)
+    if ws is None:
+        ws = _bytes(force_eo_workspace_bytes(prob), X_e.device)
+    _check(lib().tmqcd_force_eo(ctypes.byref(prob.c()), _ptr(U_packed), recon, _ptr(X_e), _ptr(out), float(scale),
+                                int(accumulate), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "tmqcd_force_eo")
     return out
 
 

@@ -125,6 +125,37 @@ def test_pack_and_force_argument_errors(L):
     assert L.tmqcd_dot(p, 1 << 30, 1 << 32, T.FULL, 1 << 36, 1 << 36, ws, None) == T.EALIAS
 
 
+def test_force_eo_argument_errors(L):
+    prob = T.Problem((4, 4, 4, 4), 0.15, 0.01)
+    p = ctypes.byref(prob.c())
+    hb = T.spinor_bytes(prob, T.F64, T.EVEN)
+    need = L.tmqcd_force_eo_workspace_bytes(p)
+    assert need == 3 * hb
+    bad = T.Problem((3, 4, 4, 4), 0.15, 0.01)
+    assert L.tmqcd_force_eo_workspace_bytes(ctypes.byref(bad.c())) == 0
+    U, X, out, ws = 1 << 30, 1 << 32, 1 << 34, 1 << 36
+
+    def call(U=U, recon=T.RECON18, X=X, out=out, scale=1.0, acc=0, ws=ws, wsb=need):
+        return L.tmqcd_force_eo(p, U, recon, X, out, scale, acc, ws, wsb, None)
+    assert call(U=None) == T.EINVAL
+    assert call(recon=5) == T.EINVAL
+    assert call(X=None) == T.EINVAL
+    assert call(out=None) == T.EINVAL
+    assert call(scale=float("inf")) == T.EINVAL
+    assert call(acc=2) == T.EINVAL
+    assert call(X=X + 8) == T.EALIGN
+    assert call(out=out + 8) == T.EALIGN
+    assert call(ws=None) == T.EWORKSPACE
+    assert call(wsb=need - 1) == T.EWORKSPACE
+    assert call(ws=ws + 16) == T.EALIGN
+    assert call(out=X) == T.EALIAS
+    assert call(out=U) == T.EALIAS
+    assert call(ws=X) == T.EALIAS
+    assert call(ws=out) == T.EALIAS
+    assert call(ws=U) == T.EALIAS
+    assert L.tmqcd_force_eo(ctypes.byref(bad.c()), U, 0, X, out, 1.0, 0, ws, need, None) == T.EINVAL
+
+
 def test_error_strings(L):
     for code in (T.OK, T.EINVAL, T.EALIAS, T.EALIGN, T.ENOCONV, T.EBREAKDOWN, T.EHIP, T.EWORKSPACE):
         assert T.error_string(code) and "unknown" not in T.error_string(code)
