@@ -235,6 +235,19 @@ int tmqcd_force_eo(const tmqcd_problem* prob, const void* U_packed, int recon, c
  * accumulated into dSdw[V][4][8] like tmqcd_force.  U_packed: FP64, RECON18. */
 int tmqcd_gauge_force(const tmqcd_problem* prob, const void* U_packed, double beta, double* dSdw,
                       double scale, int accumulate, void* stream);
+/* Gradient of the paper's tree-level Symanzik gauge action (its gauge-sector
+ * equation; the force splits into plaquette and rectangle parts as in its HMC
+ * section):
+ *   S_g = (beta/3) sum_x [ c0 sum_{mu<nu} (3 - Re Tr P_mu_nu(x)) + c1 sum_{mu!=nu} (3 - Re Tr R_mu_nu(x)) ],
+ * c0 = 1 - 8 c1, R_mu_nu(x) the rectangle two links long in mu and one in nu
+ * (each geometric rectangle counted once).  Tree-level improvement takes
+ * c1 = -1/12; c1 = 0 gives tmqcd_gauge_force's Wilson action.
+ *   G^a = (beta/3) Im Tr[T^a U_mu(x) V_mu(x)],  V_mu = c0 (6 plaquette staples) + c1 (18 rectangle staples),
+ * written or accumulated into dSdw[V][4][8] like tmqcd_force.  U_packed: FP64, RECON18.
+ * Errors: TMQCD_EINVAL (bad problem, null pointer, non-finite beta, c1 or scale,
+ * accumulate not 0/1), TMQCD_EALIGN, TMQCD_EALIAS (dSdw overlaps U_packed). */
+int tmqcd_gauge_force_tlsym(const tmqcd_problem* prob, const void* U_packed, double beta, double c1, double* dSdw,
+                            double scale, int accumulate, void* stream);
 /* U_mu(x) <- exp(i dt p^a T^a) U_mu(x) for every link, in place on the packed
  * FP64 RECON18 field; p[V][4][8] (device, float64).  The exponential is exact to
  * FP64 rounding (Taylor polynomial after scaling, then squaring). */
@@ -242,9 +255,13 @@ int tmqcd_update_links(const tmqcd_problem* prob, void* U_packed, const double* 
                        void* stream);
 /* Deterministic FP64 reductions into device memory.  ws: tmqcd_workspace_bytes(prob, -1, 1, 1) bytes.
  *   tmqcd_plaquette:      result[0] = sum_{x, mu<nu} Re Tr P_mu_nu(x)       (U_packed FP64 RECON18)
+ *   tmqcd_rectangle:      result[0] = sum_{x, mu!=nu} Re Tr R_mu_nu(x)      (the 12 V rectangles of
+ *                         tmqcd_gauge_force_tlsym; U_packed FP64 RECON18)
  *   tmqcd_momentum_norm2: result[0] = sum p^2 over all V*4*8 entries
  *   tmqcd_dot:            result[0] + i result[1] = x^+ y for packed FP64 fields of `subset` */
 int tmqcd_plaquette(const tmqcd_problem* prob, const void* U_packed, double* result, void* ws,
+                    size_t ws_bytes, void* stream);
+int tmqcd_rectangle(const tmqcd_problem* prob, const void* U_packed, double* result, void* ws,
                     size_t ws_bytes, void* stream);
 int tmqcd_momentum_norm2(const tmqcd_problem* prob, const double* p, double* result, void* ws,
                          size_t ws_bytes, void* stream);

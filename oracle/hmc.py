@@ -22,7 +22,8 @@ the benchmark may import this module.
   gauge force and the link updates U <- exp(i (h/2) p^a T^a) U in place of inner.
   Without a gauge force inner(tau) is the link update over tau.
 * Even-odd HMC: the pseudofermion lives on even sites, phi_e = Mhat^dag eta_e,
-  and the action is S_f^eo (see force.py).
+  and the action is S_f^eo (see force.py).  Its gauge action is the tree-level
+  Symanzik one of symanzik.py with coefficient c1 (c1 = 0: the Wilson action).
 Random numbers (momenta, eta, the Metropolis uniform) are inputs.
 """
 from __future__ import annotations
@@ -30,6 +31,7 @@ from __future__ import annotations
 import numpy as np
 
 from .dirac import apply_M, apply_Mdag, apply_MdagM, apply_Mhatdag, apply_MhatdagMhat, cg
+from . import symanzik
 from .force import T_GEN, fermion_force, fermion_force_eo, gauge_action, gauge_force
 
 __all__ = ["su3_exp", "hamiltonian", "total_gradient", "leapfrog", "trajectory", "LAMBDA_2MN", "omelyan",
@@ -103,10 +105,11 @@ def trajectory(U, p, eta, uniform, dims, kappa, mu, bc, beta, n_steps, dt, tol=1
 
 
 class _ActionEO:
-    """The even-odd pseudofermion action and, separately, the Wilson gauge action."""
+    """The even-odd pseudofermion action and, separately, the tree-level Symanzik gauge action."""
 
-    def __init__(self, dims, kappa, mu, bc, beta, tol):
+    def __init__(self, dims, kappa, mu, bc, beta, tol, c1=0.0):
         self.dims, self.kappa, self.mu, self.bc, self.beta, self.tol = dims, kappa, mu, bc, beta, tol
+        self.c1 = c1
 
     def solve(self, U, phi_e):
         a = lambda v: apply_MhatdagMhat(U, v, self.dims, self.kappa, self.mu, self.bc)
@@ -120,7 +123,10 @@ class _ActionEO:
         return fermion_force_eo(U, self.solve(U, phi_e), self.dims, self.kappa, self.mu, self.bc)
 
     def gauge_gradient(self, U):
-        return gauge_force(U, self.dims, self.beta)
+        return symanzik.force(U, self.dims, self.beta, self.c1)
+
+    def s_gauge(self, U):
+        return symanzik.action(U, self.dims, self.beta, self.c1)
 
 
 def omelyan(U, p, grad_outer, grad_inner, n_outer, dt, n_inner=1, lam=LAMBDA_2MN):
@@ -151,24 +157,25 @@ def omelyan(U, p, grad_outer, grad_inner, n_outer, dt, n_inner=1, lam=LAMBDA_2MN
     return u, q
 
 
-def hamiltonian_eo(U, p, phi_e, dims, kappa, mu, bc, beta, tol=1e-14) -> float:
-    act = _ActionEO(dims, kappa, mu, bc, beta, tol)
+def hamiltonian_eo(U, p, phi_e, dims, kappa, mu, bc, beta, tol=1e-14, c1=0.0) -> float:
+    act = _ActionEO(dims, kappa, mu, bc, beta, tol, c1)
     h = 0.5 * float(np.sum(p * p)) + act.s_fermion(U, phi_e)
     if beta != 0:
-        h += gauge_action(U, dims, beta)
+        h += act.s_gauge(U)
     return h
 
 
-def trajectory_eo(U, p, eta_e, uniform, dims, kappa, mu, bc, beta, n_outer, dt, n_inner=1, tol=1e-14):
-    """One even-odd HMC trajectory with the two-level 2MN integrator (fermion force outer, gauge force inner).
+def trajectory_eo(U, p, eta_e, uniform, dims, kappa, mu, bc, beta, n_outer, dt, n_inner=1, tol=1e-14, c1=0.0):
+    """One even-odd HMC trajectory with the two-level 2MN integrator (fermion force outer, gauge force of
+    the tree-level Symanzik action with coefficient c1 inner).
 
     Returns dict(U, accepted, dH, H0, H1, phi_e, U_proposed, p_proposed)."""
-    act = _ActionEO(dims, kappa, mu, bc, beta, tol)
+    act = _ActionEO(dims, kappa, mu, bc, beta, tol, c1)
     phi_e = apply_Mhatdag(U, eta_e, dims, kappa, mu, bc)
-    h0 = hamiltonian_eo(U, p, phi_e, dims, kappa, mu, bc, beta, tol)
+    h0 = hamiltonian_eo(U, p, phi_e, dims, kappa, mu, bc, beta, tol, c1)
     grad_inner = act.gauge_gradient if beta != 0 else None
     u1, p1 = omelyan(U, p, lambda u: act.fermion_gradient(u, phi_e), grad_inner, n_outer, dt, n_inner)
-    h1 = hamiltonian_eo(u1, p1, phi_e, dims, kappa, mu, bc, beta, tol)
+    h1 = hamiltonian_eo(u1, p1, phi_e, dims, kappa, mu, bc, beta, tol, c1)
     dh = h1 - h0
     accepted = bool(uniform < np.exp(-dh))
     return {"U": u1 if accepted else U, "accepted": accepted, "dH": dh, "H0": h0, "H1": h1,

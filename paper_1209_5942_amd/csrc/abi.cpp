@@ -309,6 +309,18 @@ int tmqcd_gauge_force(const tmqcd_problem* prob, const void* U_packed, double be
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
+int tmqcd_gauge_force_tlsym(const tmqcd_problem* prob, const void* U_packed, double beta, double c1, double* dSdw,
+                            double scale, int accumulate, void* stream) {
+    if (!valid_problem(prob) || !U_packed || !dSdw || !std::isfinite(beta) || !std::isfinite(c1) ||
+        !std::isfinite(scale) || (accumulate != 0 && accumulate != 1))
+        return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes) || !aligned(dSdw, 16)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    if (overlap(dSdw, mom_bytes(g), U_packed, gauge_bytes(g, TMQCD_F64, TMQCD_RECON18))) return TMQCD_EALIAS;
+    const hipError_t e = launch_gauge_force_sym(g, U_packed, beta, c1, dSdw, scale, accumulate, (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
 int tmqcd_update_links(const tmqcd_problem* prob, void* U_packed, const double* p, double dt, void* stream) {
     if (!valid_problem(prob) || !U_packed || !p || !std::isfinite(dt)) return TMQCD_EINVAL;
     if (!aligned(U_packed, kAlignBytes) || !aligned(p, 16)) return TMQCD_EALIGN;
@@ -334,6 +346,19 @@ int tmqcd_plaquette(const tmqcd_problem* prob, const void* U_packed, double* res
     if (overlap(ws, ws_bytes, U_packed, gauge_bytes(g, TMQCD_F64, TMQCD_RECON18)) || overlap(ws, ws_bytes, result, 8))
         return TMQCD_EALIAS;
     const hipError_t e = launch_plaquette(g, U_packed, result, static_cast<double*>(ws), (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_rectangle(const tmqcd_problem* prob, const void* U_packed, double* result, void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!valid_problem(prob) || !U_packed || !result) return TMQCD_EINVAL;
+    if (!aligned(U_packed, kAlignBytes) || !aligned(result, 8)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int rc = aux_ws_check(g, ws, ws_bytes);
+    if (rc != TMQCD_OK) return rc;
+    if (overlap(ws, ws_bytes, U_packed, gauge_bytes(g, TMQCD_F64, TMQCD_RECON18)) || overlap(ws, ws_bytes, result, 8))
+        return TMQCD_EALIAS;
+    const hipError_t e = launch_rectangle(g, U_packed, result, static_cast<double*>(ws), (hipStream_t)stream);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 

@@ -4,10 +4,12 @@
 //   * Wilson plaquette gauge force (the tree-level Symanzik action at c1 = 0),
 //     G^a = (beta/3) Im Tr[T^a U_mu(x) V_mu(x)] with V_mu the six staples,
 //     written or accumulated with a scale factor (momentum updates fuse here);
+//   * the tree-level Symanzik force, V_mu = c0 (6 plaquette staples) + c1 (18
+//     rectangle staples), c0 = 1 - 8 c1, and the rectangle sum of its action;
 //   * link update U_mu(x) <- exp(i dt p^a T^a) U_mu(x): the exponential of the
 //     anti-hermitian generator by a degree-16 Taylor polynomial after scaling
 //     by 2^-n (||dt P|| / 2^n <= 1/4) and n squarings;
-//   * deterministic two-pass reductions: the plaquette sum, sum p^2, and the
+//   * deterministic two-pass reductions: the plaquette and rectangle sums, sum p^2, and the
 //     complex inner product of two packed FP64 spinor fields.
 // Momenta and forces use the canonical layout double[V][4][8]; links are the
 // packed FP64 18-real field, updated in place.
@@ -150,6 +152,123 @@ __global__ __launch_bounds__(kBlock) void gauge_force_kernel(LatK k, const char*
     }
 }
 
+// ------------------------------------------- tree-level Symanzik action ---
+// Loops are walked as lists of signed 1-based directions: +(d+1) moves forwards
+// over U_d(y), -(d+1) backwards over U_d(y - d)^+.  The rectangle R_mu_nu(x) is
+// two links long in mu and one in nu; the loops through U_mu(x), walked forwards
+// over it, leave from x + mu as (m = mu+1, s = +-(nu+1)):
+//   plaquette           s, -m, -s
+//   rectangle, link 1   m, s, -m, -m, -s      (long in mu, U_mu(x) its first mu link)
+//   rectangle, link 2   s, -m, -m, -s, m      (long in mu, U_mu(x) its second mu link)
+//   rectangle, long nu  s, s, -m, -s, -s
+// and V_mu(x) = c0 sum(plaquette staples) + c1 sum(rectangle staples), so that
+// the loops' traces are Tr[U_mu(x) V_mu(x)].
+
+// moves pos one step along the signed direction (selects, so pos stays in registers)
+__device__ __forceinline__ void move(int pos[4], int st) {
+    const int d = (st > 0 ? st : -st) - 1, delta = st > 0 ? 1 : -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pos[i] += i == d ? delta : 0;
+}
+
+// r = product of the links along `steps` from the site c + pos (pos is advanced to the end)
+template <int N>
+__device__ __forceinline__ void walk(Su3<double>& r, const LatK& k, const char* gauge, const int c[4], int pos[4],
+                                     const int (&steps)[N]) {
+    Su3<double> u, t;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int st = steps[i];
+        const int d = (st > 0 ? st : -st) - 1;
+        if (st < 0) move(pos, st);
+        link_at(u, k, gauge, c, pos, d);
+        if (st > 0) move(pos, st);
+        if (i == 0) {
+            if (st > 0) {
+                r = u;
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) r.m[a][b] = conj(u.m[b][a]);
+            }
+        } else {
+            if (st > 0) mat_mul(t, r, u);
+            else mat_mul_nd(t, r, u);
+            r = t;
+        }
+    }
+}
+
+__device__ __forceinline__ void add_scaled(Su3<double>& v, double c, const Su3<double>& a) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v.m[i][j] = v.m[i][j] + scale(c, a.m[i][j]);
+}
+
+// One thread per link: block b covers kBlock sites of parity par = b / (4 nb_half)
+// in the direction mu = (b / nb_half) % 4, so every load of a block's wave goes to
+// neighbouring sites of one direction.
+__global__ __launch_bounds__(kBlock) void gauge_force_sym_kernel(LatK k, const char* gauge, double* out, double coef,
+                                                                 double c0, double c1, int accumulate) {
+    const int tile = blockIdx.x % k.nb_half;
+    const int mu = (blockIdx.x / k.nb_half) & 3;
+    const int par = blockIdx.x / (4 * k.nb_half);
+    const int h = tile * kBlock + threadIdx.x;
+    if (h >= k.vh) return;
+    int c[4];
+    coords_of(k, par, h, c);
+    const int m = mu + 1;
+    Su3<double> v, t;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v.m[i][j] = {0.0, 0.0};
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int sn = side ? -(nu + 1) : nu + 1;
+            {
+                int pos[4] = {mu == 0, mu == 1, mu == 2, mu == 3};
+                const int st[3] = {sn, -m, -sn};
+                walk(t, k, gauge, c, pos, st);
+                add_scaled(v, c0, t);
+            }
+            if (c1 != 0.0) {
+                {
+                    int pos[4] = {mu == 0, mu == 1, mu == 2, mu == 3};
+                    const int st[5] = {m, sn, -m, -m, -sn};
+                    walk(t, k, gauge, c, pos, st);
+                    add_scaled(v, c1, t);
+                }
+                {
+                    int pos[4] = {mu == 0, mu == 1, mu == 2, mu == 3};
+                    const int st[5] = {sn, -m, -m, -sn, m};
+                    walk(t, k, gauge, c, pos, st);
+                    add_scaled(v, c1, t);
+                }
+                {
+                    int pos[4] = {mu == 0, mu == 1, mu == 2, mu == 3};
+                    const int st[5] = {sn, sn, -m, -sn, -sn};
+                    walk(t, k, gauge, c, pos, st);
+                    add_scaled(v, c1, t);
+                }
+            }
+        }
+    }
+    Su3<double> u;
+    const int zero[4] = {0, 0, 0, 0};
+    link_at(u, k, gauge, c, zero, mu);
+    mat_mul(t, u, v);
+    double g[8];
+    im_tr_lambda(t, g);
+    double* o = out + (2 * (int64_t)h + (c[0] & 1)) * 32 + mu * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = accumulate ? o[i] + coef * g[i] : coef * g[i];
+}
+
 // exp(A) for anti-hermitian traceless A = i dt p^a T^a: scaling, Taylor, squaring
 __device__ void su3_exp_i(Su3<double>& e, const double p[8], double dt) {
     // Q = dt sum_a p^a lambda^a / 2 (hermitian); A = i Q
@@ -266,6 +385,28 @@ __global__ __launch_bounds__(kBlock) void plaquette_kernel(LatK k, const char* g
     block_partial<1>(v, partials, blockIdx.x);
 }
 
+// sum over the site's 12 rectangles R_mu_nu(x), mu != nu, of Re Tr
+__global__ __launch_bounds__(kBlock) void rectangle_kernel(LatK k, const char* gauge, double* partials) {
+    const int par = blockIdx.x >= (unsigned)k.nb_half ? 1 : 0;
+    const int h = (blockIdx.x - par * k.nb_half) * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (h < k.vh) {
+        int c[4];
+        coords_of(k, par, h, c);
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = 0; nu < 4; ++nu) {
+                if (nu == mu) continue;
+                const int m = mu + 1, n = nu + 1;
+                int pos[4] = {0, 0, 0, 0};
+                const int st[6] = {m, m, n, -m, -m, -n};
+                Su3<double> r;
+                walk(r, k, gauge, c, pos, st);
+                v[0] += r.m[0][0].re + r.m[1][1].re + r.m[2][2].re;
+            }
+    }
+    block_partial<1>(v, partials, blockIdx.x);
+}
+
 __global__ __launch_bounds__(kBlock) void mom_norm2_kernel(const double* mom, int64_t n, double* partials) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double v[1] = {0.0};
@@ -310,6 +451,22 @@ hipError_t launch_gauge_force(const Geom& g, const void* gauge, double beta, dou
     // G^a = (beta/3) Im Tr[T^a U V] = (beta/6) Im Tr[lambda^a U V]
     hipLaunchKernelGGL(gauge_force_kernel, dim3(2 * k.nb_half), dim3(kBlock), 0, s, k,
                        static_cast<const char*>(gauge), out, scale * beta / 6.0, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_force_sym(const Geom& g, const void* gauge, double beta, double c1, double* out, double scale,
+                                  int accumulate, hipStream_t s) {
+    const LatK k = make_latk(g);
+    hipLaunchKernelGGL(gauge_force_sym_kernel, dim3(8 * k.nb_half), dim3(kBlock), 0, s, k,
+                       static_cast<const char*>(gauge), out, scale * beta / 6.0, 1.0 - 8.0 * c1, c1, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_rectangle(const Geom& g, const void* gauge, double* result, double* partials, hipStream_t s) {
+    const LatK k = make_latk(g);
+    const int nb = 2 * k.nb_half;
+    hipLaunchKernelGGL(rectangle_kernel, dim3(nb), dim3(kBlock), 0, s, k, static_cast<const char*>(gauge), partials);
+    hipLaunchKernelGGL((finalize_kernel<1>), dim3(1), dim3(kBlock), 0, s, partials, nb, result);
     return hipGetLastError();
 }
 

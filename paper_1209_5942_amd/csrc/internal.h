@@ -149,6 +149,10 @@ hipError_t launch_gauge_force(const Geom& g, const void* gauge, double beta, dou
                               hipStream_t s);
 hipError_t launch_update_links(const Geom& g, void* gauge, const double* mom, double dt, hipStream_t s);
 hipError_t launch_plaquette(const Geom& g, const void* gauge, double* result, double* partials, hipStream_t s);
+// tree-level Symanzik gauge force (plaquettes with c0 = 1 - 8 c1, rectangles with c1) and the rectangle sum
+hipError_t launch_gauge_force_sym(const Geom& g, const void* gauge, double beta, double c1, double* out, double scale,
+                                  int accumulate, hipStream_t s);
+hipError_t launch_rectangle(const Geom& g, const void* gauge, double* result, double* partials, hipStream_t s);
 hipError_t launch_mom_norm2(const Geom& g, const double* mom, double* result, double* partials, hipStream_t s);
 hipError_t launch_spinor_dot(const Geom& g, const void* x, const void* y, int nhalf, double* result, double* partials,
                              hipStream_t s);

@@ -8,8 +8,9 @@ Metropolis step.  Here:
   the even-odd action S_f = phi_e^+ (Mhat^+ Mhat)^{-1} phi_e, phi_e = Mhat^+ eta_e,
   with the pseudofermion on even sites only; eta Gaussian (random numbers are
   inputs);
-* S_g = (beta/3) sum_{x,mu<nu} (3 - Re Tr P_mu_nu) (the tree-level Symanzik
-  action at c1 = 0);
+* S_g = (beta/3) sum_x [c0 sum_{mu<nu} (3 - Re Tr P_mu_nu) + c1 sum_{mu!=nu}
+  (3 - Re Tr R_mu_nu)], c0 = 1 - 8 c1: the paper's tree-level Symanzik action
+  (c1 = -1/12; c1 = 0, the default, is the Wilson plaquette action);
 * leapfrog: half momentum step, n times (link step, momentum step), the last
   momentum step a half step; U <- exp(i dt p^a T^a) U; p <- p - dt G;
 * the paper's production integrator, second-order minimal norm (2MN, Omelyan)
@@ -84,12 +85,16 @@ class HMC:
 
     eo: the even-odd pseudofermion action (solves on Mhat^+ Mhat over half the
     sites, the force of tmqcd_force_eo) in place of the full-lattice one.
+
+    c1: rectangle coefficient of the tree-level Symanzik gauge action.
     """
 
     def __init__(self, prob: T.Problem, U_canon, beta: float, tol: float = 1e-12, max_iter: int = 20000,
-                 md_tol: float | None = None, inner_prec: int = T.F64, guess: bool = False, eo: bool = False):
+                 md_tol: float | None = None, inner_prec: int = T.F64, guess: bool = False, eo: bool = False,
+                 c1: float = 0.0):
         self.prob = prob
         self.beta = float(beta)
+        self.c1 = float(c1)
         self.tol = tol                      # solves that enter H (acceptance)
         self.md_tol = md_tol or tol         # solves that enter the force
         self.max_iter = max_iter
@@ -158,7 +163,11 @@ class HMC:
 
     def add_gauge_gradient(self, p, scale):
         """p += scale * G_gauge at the current links."""
-        if self.beta != 0.0:
+        if self.beta == 0.0:
+            return
+        if self.c1 != 0.0:
+            T.gauge_force_tlsym(self.prob, self.U, self.beta, self.c1, out=p, scale=scale, accumulate=True)
+        else:
             T.gauge_force(self.prob, self.U, self.beta, out=p, scale=scale, accumulate=True)
 
     def add_gradient(self, p, scale):
@@ -173,7 +182,13 @@ class HMC:
         X = self.solve(self.phi, tol=self.tol)
         sf = T.dot(self.prob, self.phi, X, self.subset, ws=self.ws_aux)
         n_plaq = 6 * self.prob.volume
-        s_g = self.beta / 3.0 * (3.0 * n_plaq - float(plaq[0])) if self.beta != 0.0 else 0.0
+        s_g = 0.0
+        if self.beta != 0.0:
+            c0 = 1.0 - 8.0 * self.c1
+            s_g = self.beta / 3.0 * c0 * (3.0 * n_plaq - float(plaq[0]))
+            if self.c1 != 0.0:
+                rect = T.rectangle(self.prob, self.U, ws=self.ws_aux)
+                s_g += self.beta / 3.0 * self.c1 * (3.0 * 2 * n_plaq - float(rect[0]))
         return 0.5 * float(k[0]), s_g, float(sf[0])
 
     def hamiltonian(self, p) -> float:

@@ -29,7 +29,7 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg",
                 "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force", "tmqcd_force_eo_workspace_bytes",
-                "tmqcd_force_eo", "tmqcd_gauge_force",
+                "tmqcd_force_eo", "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle",
                 "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune", "tmqcd_tune_save",
                 "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set", "tmqcd_tune_mrhs_workspace_bytes",
                 "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot", "tmqcd_hbm_probe",
@@ -103,6 +103,8 @@ def lib():
             "tmqcd_force_eo_workspace_bytes": (S, [P]),
             "tmqcd_force_eo": (I, [P, V, I, V, V, D, I, V, S, V]),
             "tmqcd_gauge_force": (I, [P, V, D, V, D, I, V]),
+            "tmqcd_gauge_force_tlsym": (I, [P, V, D, D, V, D, I, V]),
+            "tmqcd_rectangle": (I, [P, V, V, V, S, V]),
             "tmqcd_update_links": (I, [P, V, V, D, V]),
             "tmqcd_plaquette": (I, [P, V, V, V, S, V]),
             "tmqcd_momentum_norm2": (I, [P, V, V, V, S, V]),
@@ -374,6 +376,15 @@ def gauge_force(prob: Problem, U_packed, beta, out=None, scale=1.0, accumulate=F
     return out
 
 
+def gauge_force_tlsym(prob: Problem, U_packed, beta, c1, out=None, scale=1.0, accumulate=False, stream=None):
+    """scale * dS_g/dw^a of the tree-level Symanzik action with rectangle coefficient c1, c0 = 1 - 8 c1
+    (FP64 RECON18 links)."""
+    out = _mom(prob, out, U_packed)
+    _check(lib().tmqcd_gauge_force_tlsym(ctypes.byref(prob.c()), _ptr(U_packed), float(beta), float(c1), _ptr(out),
+                                         float(scale), int(accumulate), _stream(stream)), "tmqcd_gauge_force_tlsym")
+    return out
+
+
 def update_links(prob: Problem, U_packed, p, dt, stream=None):
     """U <- exp(i dt p^a T^a) U in place (FP64 RECON18 packed links)."""
     _check(lib().tmqcd_update_links(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(p), float(dt), _stream(stream)),
@@ -396,6 +407,15 @@ def plaquette(prob: Problem, U_packed, ws=None, out=None, stream=None):
     out = _result(1, U_packed) if out is None else out
     _check(lib().tmqcd_plaquette(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(out), _ptr(ws), ws.numel(),
                                  _stream(stream)), "tmqcd_plaquette")
+    return out
+
+
+def rectangle(prob: Problem, U_packed, ws=None, out=None, stream=None):
+    """Device tensor [sum_{x, mu != nu} Re Tr R_mu_nu(x)] over the 12 V rectangles."""
+    ws = aux_workspace(prob) if ws is None else ws
+    out = _result(1, U_packed) if out is None else out
+    _check(lib().tmqcd_rectangle(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(out), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "tmqcd_rectangle")
     return out
 
 

@@ -156,6 +156,23 @@ def test_force_eo_argument_errors(L):
     assert L.tmqcd_force_eo(ctypes.byref(bad.c()), U, 0, X, out, 1.0, 0, ws, need, None) == T.EINVAL
 
 
+def test_tlsym_and_rectangle_argument_errors(L):
+    prob = T.Problem((4, 4, 4, 4), 0.15, 0.01)
+    p = ctypes.byref(prob.c())
+    U, out = 1 << 30, 1 << 34
+    assert L.tmqcd_gauge_force_tlsym(p, None, 5.0, -1 / 12, out, 1.0, 0, None) == T.EINVAL
+    assert L.tmqcd_gauge_force_tlsym(p, U, 5.0, float("nan"), out, 1.0, 0, None) == T.EINVAL
+    assert L.tmqcd_gauge_force_tlsym(p, U, float("inf"), -1 / 12, out, 1.0, 0, None) == T.EINVAL
+    assert L.tmqcd_gauge_force_tlsym(p, U, 5.0, -1 / 12, out, 1.0, 3, None) == T.EINVAL
+    assert L.tmqcd_gauge_force_tlsym(p, U + 16, 5.0, -1 / 12, out, 1.0, 0, None) == T.EALIGN
+    assert L.tmqcd_gauge_force_tlsym(p, U, 5.0, -1 / 12, U, 1.0, 0, None) == T.EALIAS
+    ws = T.workspace_bytes(prob, -1, 1, 1)
+    assert L.tmqcd_rectangle(p, None, out, 1 << 36, ws, None) == T.EINVAL
+    assert L.tmqcd_rectangle(p, U, out, 1 << 36, 8, None) == T.EWORKSPACE
+    assert L.tmqcd_rectangle(p, U, out + 4, 1 << 36, ws, None) == T.EALIGN
+    assert L.tmqcd_rectangle(p, U, 1 << 36, 1 << 36, ws, None) == T.EALIAS
+
+
 def test_error_strings(L):
     for code in (T.OK, T.EINVAL, T.EALIAS, T.EALIGN, T.ENOCONV, T.EBREAKDOWN, T.EHIP, T.EWORKSPACE):
         assert T.error_string(code) and "unknown" not in T.error_string(code)

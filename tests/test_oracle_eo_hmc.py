@@ -119,3 +119,19 @@ def test_2mn_lambda_is_the_minimal_norm_value():
     # Omelyan, Mryglod and Folk's closed form of the second-order minimal-norm coefficient
     c = (2.0 * np.sqrt(326.0) + 36.0) ** (1.0 / 3.0)
     assert abs(H.LAMBDA_2MN - (0.5 - c / 12.0 + 1.0 / (6.0 * c))) < 1e-15
+
+
+def test_omelyan_with_symanzik_inner_force_is_reversible_and_second_order():
+    dims, kappa, mu, beta, U, p, phi, _ = _eo_setup()
+    act = H._ActionEO(dims, kappa, mu, BC, beta, 1e-14, c1=-1.0 / 12.0)
+    go = lambda u: act.fermion_gradient(u, phi)
+    u1, p1 = H.omelyan(U, p, go, act.gauge_gradient, 2, 0.1, 2)
+    u2, p2 = H.omelyan(u1, -p1, go, act.gauge_gradient, 2, 0.1, 2)
+    assert np.abs(u2 - U).max() < 1e-11
+    assert np.abs(-p2 - p).max() < 1e-10
+    h0 = H.hamiltonian_eo(U, p, phi, dims, kappa, mu, BC, beta, c1=-1.0 / 12.0)
+    dh = []
+    for n in (4, 8):
+        u1, p1 = H.omelyan(U, p, go, act.gauge_gradient, n, 0.4 / n, 2)
+        dh.append(H.hamiltonian_eo(u1, p1, phi, dims, kappa, mu, BC, beta, c1=-1.0 / 12.0) - h0)
+    assert 3.0 < abs(dh[0] / dh[1]) < 5.5, dh

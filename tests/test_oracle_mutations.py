@@ -143,3 +143,40 @@ def test_planted_2mn_weight_mistake_fails_a_pin(monkeypatch, w_mid):
     monkeypatch.setattr(H, "omelyan", _omelyan_with(w_mid))
     caught = _caught([lambda: PE.test_omelyan_energy_error_is_second_order(3)])
     assert caught == (abs(2.0 * H.LAMBDA_2MN + w_mid(H.LAMBDA_2MN) - 1.0) > 1e-12), "the dt^2 pin must fail exactly when the weights do not sum to one"
+
+
+import test_oracle_symanzik as PS
+from oracle import symanzik as S
+
+
+def _rect_paths_swapped_side():
+    paths = {mu: [list(p) for p in ps] for mu, ps in S.RECTANGLE_STAPLE_PATHS.items()}
+    s, m = paths[1][1][0], 2
+    paths[1][1] = [-s, -m, -m, s, m]     # the second-link rectangle on the wrong side (still a closed loop)
+    return paths
+
+
+SYMANZIK_MUTATIONS = {
+    "rectangles long in the first direction only": lambda mp: mp.setattr(
+        S, "rectangle_sum", lambda U, dims: sum(
+            S.loop_trace_sum(U, dims, [m + 1, m + 1, n + 1, -(m + 1), -(m + 1), -(n + 1)])
+            for m in range(4) for n in range(m + 1, 4)) * 2),
+    "rectangles as 1x1 loops": lambda mp: mp.setattr(
+        S, "rectangle_sum", lambda U, dims: 2 * S.plaquette_sum(U, dims)),
+    "c1 sign flipped in the action": lambda mp: mp.setattr(
+        S, "action", (lambda f: (lambda U, dims, beta, c1: f(U, dims, beta, -c1)))(S.action)),
+    "c0 = 1 + 8 c1": lambda mp: mp.setattr(
+        S, "action", lambda U, dims, beta, c1: float(beta / 3.0 * (
+            (1 + 8 * c1) * (18.0 * int(np.prod(dims)) - S.plaquette_sum(U, dims))
+            + c1 * (36.0 * int(np.prod(dims)) - S.rectangle_sum(U, dims))))),
+    "rectangle staple on the wrong side": lambda mp: mp.setattr(S, "RECTANGLE_STAPLE_PATHS",
+                                                                _rect_paths_swapped_side()),
+}
+
+
+@pytest.mark.parametrize("name", list(SYMANZIK_MUTATIONS))
+def test_planted_symanzik_mistake_fails_a_pin(monkeypatch, name):
+    SYMANZIK_MUTATIONS[name](monkeypatch)
+    pins = [lambda: PS.test_abelian_plane_wave_closed_form(0.3), PS.test_tree_level_improvement_fixes_the_sign_of_c1,
+            PS.test_unit_field, lambda: PS.test_force_vs_finite_differences(0.2)]
+    assert _caught(pins), f"no pin caught the planted mistake: {name}"
