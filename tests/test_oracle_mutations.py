@@ -180,3 +180,53 @@ def test_planted_symanzik_mistake_fails_a_pin(monkeypatch, name):
     pins = [lambda: PS.test_abelian_plane_wave_closed_form(0.3), PS.test_tree_level_improvement_fixes_the_sign_of_c1,
             PS.test_unit_field, lambda: PS.test_force_vs_finite_differences(0.2)]
     assert _caught(pins), f"no pin caught the planted mistake: {name}"
+
+
+import test_oracle_bicgstab as PB
+from oracle import bicgstab as BI
+
+
+def _bicgstab_with(beta_ratio=True, omega_conj=False):
+    """BiCGStab with one planted change: beta without the alpha/omega factor, or omega from (s, t)."""
+    def solve(apply_A, b, tol=1e-10, maxiter=400, x0=None):
+        x = np.zeros_like(b) if x0 is None else x0.astype(np.complex128, copy=True)
+        r = b - apply_A(x) if x0 is not None else b.copy()
+        rt = r.copy()
+        bb = np.vdot(b, b).real
+        if bb == 0.0:
+            return np.zeros_like(b), 0, True
+        rho_prev = alpha = omega = 1.0 + 0.0j
+        v = np.zeros_like(b)
+        p = np.zeros_like(b)
+        k = 0
+        while np.vdot(r, r).real > tol * tol * bb:
+            if k >= maxiter:
+                return x, k, False
+            rho = np.vdot(rt, r)
+            beta = (rho / rho_prev) * ((alpha / omega) if beta_ratio else 1.0)
+            p = r + beta * (p - omega * v)
+            v = apply_A(p)
+            alpha = rho / np.vdot(rt, v)
+            s = r - alpha * v
+            t = apply_A(s)
+            omega = (np.vdot(s, t) if omega_conj else np.vdot(t, s)) / np.vdot(t, t).real
+            x = x + alpha * p + omega * s
+            r = s - omega * t
+            rho_prev = rho
+            k += 1
+        return x, k, True
+    return solve
+
+
+@pytest.mark.parametrize("kw", [dict(beta_ratio=False), dict(omega_conj=True)])
+def test_planted_bicgstab_mistake_fails_a_pin(monkeypatch, kw):
+    monkeypatch.setattr(BI, "bicgstab", _bicgstab_with(**kw))
+    pins = [PB.test_small_nonsymmetric_matrix_against_lu,
+            lambda: PB.test_M_against_dense_lu((4, 2, 2, 4), 0.16, 0.3)]
+    assert _caught(pins), f"no pin caught the planted mistake: {kw}"
+
+
+def test_unplanted_bicgstab_copy_passes(monkeypatch):
+    monkeypatch.setattr(BI, "bicgstab", _bicgstab_with())
+    PB.test_small_nonsymmetric_matrix_against_lu()
+    PB.test_M_against_dense_lu((4, 2, 2, 4), 0.16, 0.3)
