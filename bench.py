@@ -649,8 +649,14 @@ def bench_hmc(T, synth, dev):
     Xe = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(prob.volume // 2, 83)).to(dev), T.F64, T.EVEN)
     ws_eo = T._bytes(T.force_eo_workspace_bytes(prob), dev)
     t_force_eo = _events_time(lambda: T.force_eo(prob, h.U, Xe, out=G, ws=ws_eo), 20)
+    # gauge forces: Wilson plaquettes and the tree-level Symanzik action (c1 = -1/12); flops counted as
+    # 198 per 3x3 complex product (27 complex multiply-adds) over the products one link's staples take
+    t_gauge_w = _events_time(lambda: T.gauge_force(prob, h.U, 3.9, out=G), 20)
+    t_gauge_s = _events_time(lambda: T.gauge_force_tlsym(prob, h.U, 3.9, -1.0 / 12.0, out=G), 20)
+    flops_w = 4 * prob.volume * 198 * (6 * 2 + 1)
+    flops_s = 4 * prob.volume * 198 * (6 * 2 + 18 * 4 + 1)
 
-    def run(hmc, n_steps, integrator="leapfrog"):
+    def run(hmc, n_steps, integrator="leapfrog", n_inner=1):
         dh, acc = [], 0
         n_eta = prob.volume // 2 if hmc.eo else prob.volume
         t0 = time.perf_counter()
@@ -659,7 +665,7 @@ def bench_hmc(T, synth, dev):
             eta = torch.from_numpy(synth.gaussian_spinor(n_eta, 2000 + k)).to(dev)
             u = float(np.random.default_rng(3000 + k).random())
             hmc.U.copy_(U_start)   # every trajectory from the same start: dH of one field, two step sizes
-            out = hmc.trajectory(p, eta, u, n_steps, 1.0 / n_steps, integrator=integrator)
+            out = hmc.trajectory(p, eta, u, n_steps, 1.0 / n_steps, integrator=integrator, n_inner=n_inner)
             dh.append(out["dH"])
             acc += int(out["accepted"])
         torch.cuda.synchronize()
@@ -683,6 +689,10 @@ def bench_hmc(T, synth, dev):
     dh_eo20, _, _ = run(heo, 20, "2mn")
     heo32g = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10, eo=True, inner_prec=T.F32, guess=True)
     dh_eo32g, acc_eo32g, t_eo32g = run(heo32g, 10, "2mn")
+    # the paper's production setting: even-odd action, tree-level Symanzik gauge action (beta 3.9,
+    # c1 = -1/12) on the inner scale with 2 inner steps, FP32-inner solves from the previous solution
+    hprod = HMC(prob, U, beta=3.9, tol=1e-12, md_tol=1e-10, eo=True, inner_prec=T.F32, guess=True, c1=-1.0 / 12.0)
+    dh_prod, acc_prod, t_prod = run(hprod, 10, "2mn", n_inner=2)
     creutz = creutz_4x4x4x4(T, synth, dev)
     e = np.exp(-np.clip(np.array(dh20), -700, 700))
     ratio = float(np.mean(np.abs(dh20)) / np.mean(np.abs(dh40)))
@@ -701,6 +711,17 @@ def bench_hmc(T, synth, dev):
             "cg_iters_per_solve": round(h.cg_iters / max(1, h.solves), 1),
             "creutz_4x4x4x4": creutz,
             "force_eo_us": round(t_force_eo * 1e6, 1),
+            "gauge_force_wilson_us": round(t_gauge_w * 1e6, 1),
+            "gauge_force_wilson_TFLOP_s": round(flops_w / t_gauge_w / 1e12, 2),
+            "gauge_force_tlsym_us": round(t_gauge_s * 1e6, 1),
+            "gauge_force_tlsym_TFLOP_s": round(flops_s / t_gauge_s / 1e12, 2),
+            "gauge_force_tlsym_frac_of_fp64_peak": round(flops_s / t_gauge_s / 78.6e12, 4),
+            "eo_2mn_tlsym_beta3.9": {"trajectory_s": round(t_prod, 3), "acceptance": acc_prod,
+                                     "mean_abs_dH": round(float(np.mean(np.abs(dh_prod))), 4),
+                                     "cg_iters_per_solve": round(hprod.cg_iters / max(1, hprod.solves), 1),
+                                     "setup": "even-odd action, tree-level Symanzik gauge action beta 3.9, "
+                                              "c1 = -1/12, 10 outer 2MN steps of 2 inner steps, FP32-inner "
+                                              "solves from the previous solution, tau 1"},
             "eo_2mn": {"trajectory_s": round(t_eo, 3), "dH": [round(x, 6) for x in dh_eo], "acceptance": acc_eo,
                        "mean_abs_dH": round(float(np.mean(np.abs(dh_eo))), 6),
                        "mean_abs_dH_ratio_10_to_20_outer_steps":

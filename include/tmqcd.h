@@ -180,6 +180,23 @@ int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const voi
              const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes,
              void* stream);
 
+/* BiCGStab (the paper's other Krylov solver for D phi = psi, its §2.1; van der
+ * Vorst's algorithm) on the non-hermitian operator itself: opts->op = TMQCD_M
+ * (b, x full fields) or TMQCD_MHAT (the even-odd Schur complement; b, x even
+ * fields), FP64 only (opts->inner_prec must be TMQCD_F64), links U_packed FP64
+ * with opts->recon.  Stops when the true residual ||b - A x|| / ||b|| <= tol
+ * (recomputed in FP64 when the recursive one got there; the recursion restarts
+ * from the true residual otherwise, counted in stats->reliable_updates).
+ * opts->reliable_delta is ignored; check_every and x_is_zero act as for CG.
+ * stats->iters counts BiCGStab iterations (two operator applications each).
+ * ws: tmqcd_bicgstab_workspace_bytes(prob, op) bytes, device, 256-byte
+ * aligned, caller-owned; x may not overlap b; ws overlaps none of b, x, U_packed.
+ * Returns TMQCD_ENOCONV at max_iter, TMQCD_EBREAKDOWN on (rt, v) = 0, omega = 0
+ * or a non-finite residual, else the errors of tmqcd_cg. */
+size_t tmqcd_bicgstab_workspace_bytes(const tmqcd_problem* prob, int op);
+int tmqcd_bicgstab(const tmqcd_problem* prob, const void* U_packed, const void* b, void* x,
+                   const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- several lattices at once ------------------------------------------------ */
 /* FP64 CG on Mhat^+ Mhat for n (1..8) lattices of any volumes in one solve:
  * every stage of an iteration is a single grid-stride launch over the tiles of

@@ -190,6 +190,31 @@ int tmqcd_dslash(const tmqcd_problem* prob, const void* U_packed, const void* in
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
+size_t tmqcd_bicgstab_workspace_bytes(const tmqcd_problem* prob, int op) {
+    if (!valid_problem(prob) || (op != TMQCD_M && op != TMQCD_MHAT)) return 0;
+    return (size_t)bicgstab_workspace(make_geom(*prob), op);
+}
+
+int tmqcd_bicgstab(const tmqcd_problem* prob, const void* U_packed, const void* b, void* x,
+                   const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_problem(prob) || !U_packed || !b || !x || !opts || !stats) return TMQCD_EINVAL;
+    const tmqcd_cg_opts& o = *opts;
+    if (o.op != TMQCD_M && o.op != TMQCD_MHAT) return TMQCD_EINVAL;
+    if (o.inner_prec != TMQCD_F64 || !valid_recon(o.recon) || o.max_iter < 1) return TMQCD_EINVAL;
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol) || o.check_every < 0) return TMQCD_EINVAL;
+    if (!aligned(b, kAlignBytes) || !aligned(x, kAlignBytes) || !aligned(U_packed, kAlignBytes)) return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int64_t fb = field_bytes(g, TMQCD_F64, o.op == TMQCD_M ? TMQCD_FULL : TMQCD_EVEN);
+    if (overlap(b, fb, x, fb)) return TMQCD_EALIAS;
+    const int64_t need = bicgstab_workspace(g, o.op);
+    if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
+    if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+    if (overlap(ws, need, b, fb) || overlap(ws, need, x, fb) ||
+        overlap(ws, need, U_packed, gauge_bytes(g, TMQCD_F64, o.recon)))
+        return TMQCD_EALIAS;
+    return run_bicgstab(*prob, U_packed, b, x, o, *stats, ws, (hipStream_t)stream);
+}
+
 int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const void* b, void* x,
              const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
     if (!valid_problem(prob) || !U_packed || !b || !x || !opts || !stats) return TMQCD_EINVAL;

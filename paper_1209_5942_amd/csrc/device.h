@@ -385,6 +385,13 @@ struct CgState {
 };
 enum { kDoneRunning = 0, kDoneStop = 1, kDoneBreakdown = 2, kDoneMaxIter = 3 };
 
+// BiCGStab scalars (complex values as (re, im)); done uses the codes above.
+struct BiState {
+    double rho[2], alpha[2], omega[2], beta[2];
+    double rr, stop_rr;
+    int iter, max_iter, done, pad;
+};
+
 // Deterministic two-pass reductions.  Pass 1: every block stores the sums of
 // its threads' values (in a fixed order) to partials[bid * N + i].  Pass 2
 // (a later launch, so the partials are visible without device-wide fences):

@@ -73,6 +73,12 @@ int64_t tune_mrhs_workspace_bytes(const Geom& g, int prec, int nrhs);
 int run_tune_mrhs(const tmqcd_problem& prob, const void* gauge, int prec, int recon, int nrhs, void* ws,
                   hipStream_t s, tmqcd_tune_result* res);
 
+// BiCGStab on M (full field) or Mhat (even field) in FP64 (bicgstab.hip); o.op selects
+// the operator, o.recon the links; workspace bicgstab_workspace(g, op) bytes.
+int run_bicgstab(const tmqcd_problem& prob, const void* gauge, const void* b, void* x, const tmqcd_cg_opts& o,
+                 tmqcd_cg_stats& stats, void* ws, hipStream_t s);
+int64_t bicgstab_workspace(const Geom& g, int op);
+
 int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b, void* x, const tmqcd_cg_opts& o,
            tmqcd_cg_stats& stats, void* ws, hipStream_t s);
 

@@ -28,7 +28,7 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
 
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg",
-                "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_force", "tmqcd_force_eo_workspace_bytes",
+                "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_bicgstab_workspace_bytes", "tmqcd_bicgstab", "tmqcd_force", "tmqcd_force_eo_workspace_bytes",
                 "tmqcd_force_eo", "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle",
                 "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune", "tmqcd_tune_save",
                 "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set", "tmqcd_tune_mrhs_workspace_bytes",
@@ -98,6 +98,8 @@ def lib():
             "tmqcd_cg": (I, [P, ctypes.POINTER(V * 3), V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats),
                              V, S, V]),
             "tmqcd_cg_batch_workspace_bytes": (S, [I, P]),
+            "tmqcd_bicgstab_workspace_bytes": (S, [P, I]),
+            "tmqcd_bicgstab": (I, [P, V, V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats), V, S, V]),
             "tmqcd_cg_batch": (I, [I, P, V, V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats), I, V, S, V]),
             "tmqcd_force": (I, [P, V, I, V, V, V, D, I, V]),
             "tmqcd_force_eo_workspace_bytes": (S, [P]),
@@ -267,6 +269,28 @@ def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, m
                         ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream))
     if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
         raise TmqcdError(rc, "tmqcd_cg")
+    return x, st.as_dict(), rc
+
+
+def bicgstab(prob: Problem, U_packed, b, x=None, *, x_is_zero=None, tol=1e-10, max_iter=10000, op=MHAT,
+             recon=RECON18, check_every=0, ws=None, stream=None, raise_on_noconv=True):
+    """Solve op x = b with BiCGStab, op = M (full fields) or MHAT (even fields); U_packed: FP64 links.
+
+    x, x_is_zero as for cg.  Returns (x, stats dict, return code)."""
+    subset = FULL if op == M else EVEN
+    if x_is_zero is None:
+        x_is_zero = x is None
+    if x is None:
+        x = _bytes(spinor_bytes(prob, F64, subset))
+    if ws is None:
+        ws = _bytes(lib().tmqcd_bicgstab_workspace_bytes(ctypes.byref(prob.c()), op))
+    o = CCgOpts(tol=tol, max_iter=max_iter, op=op, inner_prec=F64, recon=recon, reliable_delta=0.0,
+                check_every=check_every, x_is_zero=int(x_is_zero))
+    st = CCgStats()
+    rc = lib().tmqcd_bicgstab(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(b), _ptr(x), ctypes.byref(o),
+                              ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream))
+    if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
+        raise TmqcdError(rc, "tmqcd_bicgstab")
     return x, st.as_dict(), rc
 
 

@@ -173,6 +173,34 @@ def test_tlsym_and_rectangle_argument_errors(L):
     assert L.tmqcd_rectangle(p, U, 1 << 36, 1 << 36, ws, None) == T.EALIAS
 
 
+def test_bicgstab_argument_errors(L):
+    prob = T.Problem((4, 4, 4, 4), 0.15, 0.01)
+    p = ctypes.byref(prob.c())
+    need = L.tmqcd_bicgstab_workspace_bytes(p, T.MHAT)
+    assert need > 7 * T.spinor_bytes(prob, T.F64, T.EVEN)
+    assert L.tmqcd_bicgstab_workspace_bytes(p, T.MDAGM) == 0
+    assert L.tmqcd_bicgstab_workspace_bytes(p, T.M) > need
+    st = T.CCgStats()
+
+    def call(U=1 << 30, b=1 << 32, x=1 << 33, ws=1 << 36, wsb=need, **kw):
+        o = dict(tol=1e-10, max_iter=100, op=T.MHAT, inner_prec=T.F64, recon=0, reliable_delta=0.0, check_every=0,
+                 x_is_zero=1)
+        o.update(kw)
+        return L.tmqcd_bicgstab(p, U, b, x, ctypes.byref(T.CCgOpts(**o)), ctypes.byref(st), ws, wsb, None)
+    assert call(op=T.MHATDAGMHAT) == T.EINVAL
+    assert call(inner_prec=T.F32) == T.EINVAL
+    assert call(tol=0.0) == T.EINVAL
+    assert call(max_iter=0) == T.EINVAL
+    assert call(recon=7) == T.EINVAL
+    assert call(U=None) == T.EINVAL
+    assert call(b=(1 << 32) + 8) == T.EALIGN
+    assert call(x=1 << 32) == T.EALIAS
+    assert call(ws=None) == T.EWORKSPACE
+    assert call(wsb=need - 1) == T.EWORKSPACE
+    assert call(ws=1 << 32) == T.EALIAS
+    assert call(ws=1 << 30) == T.EALIAS
+
+
 def test_error_strings(L):
     for code in (T.OK, T.EINVAL, T.EALIAS, T.EALIGN, T.ENOCONV, T.EBREAKDOWN, T.EHIP, T.EWORKSPACE):
         assert T.error_string(code) and "unknown" not in T.error_string(code)
