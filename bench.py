@@ -226,6 +226,37 @@ def main():
         "context": {"paper_hd5870_dslash_dp_gflops": 60, "paper_hmc_speedup_vs_server_cpu": 4},
     }
 
+    # ------------------------------- BiCGStab on Mhat vs CG on the normal equations ---
+    # the same system Mhat x = b: BiCGStab on Mhat itself, CG on Mhat^dag Mhat x = Mhat^dag b
+    log("BiCGStab vs CGNE on Mhat x = b")
+    ws_bi = T._bytes(T.bicgstab_workspace_bytes(prob, T.MHAT), dev)
+    xb_dev = torch.empty_like(x_dev)
+    bd_dev = T.dslash(prob, gauges[(0, 0)], b_dev, T.MHATDAG, ws=ws)
+    xc_dev = torch.empty_like(x_dev)
+
+    def best_of(fn, n=3):
+        best = None
+        for _ in range(n):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, st)
+        return best
+    t_bi, st_bi = best_of(lambda: T.bicgstab(prob, gauges[(0, 0)], b_dev, xb_dev, x_is_zero=True, tol=1e-10,
+                                             op=T.MHAT, ws=ws_bi, check_every=8)[1])
+    t_cgne, st_cgne = best_of(lambda: T.cg(prob, {T.F64: gauges[(0, 0)]}, bd_dev, xc_dev, x_is_zero=True, tol=1e-10,
+                                           max_iter=5000, op=T.MHATDAGMHAT, ws=ws, check_every=16)[1])
+    result["bicgstab_24x24x24x48"] = {
+        "workload": "Mhat x = b, 24^3x48 (the step's lattice and source), tol 1e-10 on the solver's own system",
+        "bicgstab_ms": round(1e3 * t_bi, 3), "bicgstab_iters": st_bi["iters"],
+        "bicgstab_hop_launches": st_bi["hop_launches"], "bicgstab_true_rel_residual": st_bi["true_rel_residual"],
+        "cgne_ms": round(1e3 * t_cgne, 3), "cgne_iters": st_cgne["iters"], "cgne_hop_launches": st_cgne["hop_launches"],
+        "speedup_bicgstab_vs_cgne": round(t_cgne / t_bi, 3)}
+    log(f"BiCGStab {1e3 * t_bi:.1f} ms ({st_bi['iters']} it), CGNE {1e3 * t_cgne:.1f} ms ({st_cgne['iters']} it)")
+
     # ---------------------------------------------- FP64 vs mixed CG -------
     if not args.no_mixed:
         m = MIXED
@@ -312,6 +343,10 @@ def main():
         x = T.unpack_spinor(prob, x_dev, T.F64, T.EVEN).cpu().numpy()
         A = lambda v: D.apply_MhatdagMhat(U, v, dims, w["kappa"], w["mu"], (1, 1, 1, -1))
         result["cg_fp64_24x24x24x48"]["oracle_rel_residual"] = D.true_rel_residual(A, b, x)
+        Ahat = lambda v: D.apply_Mhat(U, v, dims, w["kappa"], w["mu"], (1, 1, 1, -1))
+        for name, xd in (("bicgstab", xb_dev), ("cgne", xc_dev)):
+            xh = T.unpack_spinor(prob, xd, T.F64, T.EVEN).cpu().numpy()
+            result["bicgstab_24x24x24x48"][f"{name}_oracle_rel_residual_of_Mhat_x_eq_b"] = D.true_rel_residual(Ahat, b, xh)
         log("CPU baseline: oracle hop")
         psi = synth.gaussian_spinor(prob.volume, 27)
         with threadpool_limits(1):

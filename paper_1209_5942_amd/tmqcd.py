@@ -28,12 +28,13 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
 
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg",
-                "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_bicgstab_workspace_bytes", "tmqcd_bicgstab", "tmqcd_force", "tmqcd_force_eo_workspace_bytes",
-                "tmqcd_force_eo", "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle",
-                "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune", "tmqcd_tune_save",
-                "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set", "tmqcd_tune_mrhs_workspace_bytes",
-                "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot", "tmqcd_hbm_probe",
-                "tmqcd_error_string", "tmqcd_last_hip_error")
+                "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_bicgstab_workspace_bytes",
+                "tmqcd_bicgstab", "tmqcd_force", "tmqcd_force_eo_workspace_bytes", "tmqcd_force_eo",
+                "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle", "tmqcd_update_links",
+                "tmqcd_tune_workspace_bytes", "tmqcd_tune", "tmqcd_tune_save", "tmqcd_tune_load",
+                "tmqcd_tune_clear", "tmqcd_tune_set", "tmqcd_tune_mrhs_workspace_bytes", "tmqcd_tune_mrhs",
+                "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot", "tmqcd_hbm_probe", "tmqcd_error_string",
+                "tmqcd_last_hip_error")
 
 
 class TmqcdLibraryMissing(RuntimeError):
@@ -272,6 +273,10 @@ def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, m
     return x, st.as_dict(), rc
 
 
+def bicgstab_workspace_bytes(prob: Problem, op=MHAT) -> int:
+    return lib().tmqcd_bicgstab_workspace_bytes(ctypes.byref(prob.c()), op)
+
+
 def bicgstab(prob: Problem, U_packed, b, x=None, *, x_is_zero=None, tol=1e-10, max_iter=10000, op=MHAT,
              recon=RECON18, check_every=0, ws=None, stream=None, raise_on_noconv=True):
     """Solve op x = b with BiCGStab, op = M (full fields) or MHAT (even fields); U_packed: FP64 links.
@@ -283,7 +288,7 @@ def bicgstab(prob: Problem, U_packed, b, x=None, *, x_is_zero=None, tol=1e-10, m
     if x is None:
         x = _bytes(spinor_bytes(prob, F64, subset))
     if ws is None:
-        ws = _bytes(lib().tmqcd_bicgstab_workspace_bytes(ctypes.byref(prob.c()), op))
+        ws = _bytes(bicgstab_workspace_bytes(prob, op))
     o = CCgOpts(tol=tol, max_iter=max_iter, op=op, inner_prec=F64, recon=recon, reliable_delta=0.0,
                 check_every=check_every, x_is_zero=int(x_is_zero))
     st = CCgStats()

@@ -230,3 +230,26 @@ def test_unplanted_bicgstab_copy_passes(monkeypatch):
     monkeypatch.setattr(BI, "bicgstab", _bicgstab_with())
     PB.test_small_nonsymmetric_matrix_against_lu()
     PB.test_M_against_dense_lu((4, 2, 2, 4), 0.16, 0.3)
+
+
+import test_oracle_heatbath as PH
+from oracle import heatbath as HBO
+
+
+HEATBATH_MUTATIONS = {
+    # alpha = beta k (the 2/3 of the normalisation lost)
+    "alpha factor": lambda mp: mp.setattr(HBO, "sample_x0", (lambda f: (lambda alpha, *a, **k: f(
+        1.5 * np.asarray(alpha), *a, **k)))(HBO.sample_x0)),
+    # sign of a2 in the quaternion projection
+    "projection sign": lambda mp: mp.setattr(HBO, "su2_project", (lambda f: (lambda w: (lambda q: (
+        q[0], q[1], -q[2], q[3]))(f(w))))(HBO.su2_project)),
+    # the accepted x0 reflected: weight exp(-alpha x0)
+    "x0 sign": lambda mp: mp.setattr(HBO, "sample_x0", (lambda f: (lambda *a, **k: -f(*a, **k)))(HBO.sample_x0)),
+}
+
+
+@pytest.mark.parametrize("name", list(HEATBATH_MUTATIONS))
+def test_planted_heatbath_mistake_fails_a_pin(monkeypatch, name):
+    HEATBATH_MUTATIONS[name](monkeypatch)
+    pins = [lambda: PH.test_single_link_chain_matches_weyl_integral(6.0, 1.0), PH.test_overrelaxation_is_microcanonical]
+    assert _caught(pins), f"no pin caught the planted mistake: {name}"
