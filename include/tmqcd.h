@@ -270,6 +270,26 @@ int tmqcd_gauge_force_tlsym(const tmqcd_problem* prob, const void* U_packed, dou
  * FP64 rounding (Taylor polynomial after scaling, then squaring). */
 int tmqcd_update_links(const tmqcd_problem* prob, void* U_packed, const double* p, double dt,
                        void* stream);
+/* ---- pure-gauge updates (the paper's heatbath section) ---------------------- */
+/* One sweep over all links of the Wilson plaquette action
+ * S = (beta/3) sum (3 - Re Tr P), in place on the packed FP64 RECON18 links:
+ * direction by direction and parity by parity (8 launches; the links of one
+ * direction and parity do not appear in each other's staples), each link
+ * updated through the SU(2) subgroups (0,1), (0,2), (1,2) (Cabibbo-Marinari).
+ *   tmqcd_heatbath:  the exact SU(2) heatbath in each subgroup (Creutz's
+ *                    inversion below alpha = 2, Kennedy-Pendleton above);
+ *                    random numbers from the counter-based Philox4x32-10 with
+ *                    key `seed` and counter (4 s + mu, sweep, subgroup * 2^16 +
+ *                    trial, 0), s the canonical site index, so a sweep is a
+ *                    pure function of (links, beta, seed, sweep).
+ *   tmqcd_overrelax: the microcanonical reflection r = (s^+)^2 in each
+ *                    subgroup (no random numbers; keeps the action).
+ * Errors: TMQCD_EINVAL (bad problem, null links, beta negative or not finite,
+ * more than 2^32 links), TMQCD_EALIGN; TMQCD_EHIP if a launch fails. */
+int tmqcd_heatbath(const tmqcd_problem* prob, void* U_packed, double beta, uint64_t seed, uint32_t sweep,
+                   void* stream);
+int tmqcd_overrelax(const tmqcd_problem* prob, void* U_packed, void* stream);
+
 /* Deterministic FP64 reductions into device memory.  ws: tmqcd_workspace_bytes(prob, -1, 1, 1) bytes.
  *   tmqcd_plaquette:      result[0] = sum_{x, mu<nu} Re Tr P_mu_nu(x)       (U_packed FP64 RECON18)
  *   tmqcd_rectangle:      result[0] = sum_{x, mu!=nu} Re Tr R_mu_nu(x)      (the 12 V rectangles of

@@ -27,6 +27,9 @@ sqrt(1 - x0^2); Creutz 1980), else by Kennedy and Pendleton's method
 r4^2 <= 1 - lambda^2, x0 = 1 - 2 lambda^2; Kennedy and Pendleton 1985).  The
 direction of (x1, x2, x3) is uniform on the sphere: cos(theta) = 2 u1 - 1,
 phi = 2 pi u2.  alpha = 0 gives x0 = 2u - 1 accepted with sqrt(1 - x0^2).
+1 - x^2 is evaluated as (1 - x)(1 + x), which stays accurate to a few units
+in the last place near x = +-1, where the square root magnifies the error of
+1 - x x by 1/sqrt(1 - x^2).
 
 A sweep updates every link, direction by direction and parity by parity: the
 staples of U_mu(x) hold no other U_mu(y) of the parity of x, so those links are
@@ -103,7 +106,7 @@ def sample_x0(alpha, seed, link, sweep, sub, max_trials: int = 0xFFFE):
             # alpha < 2: invert the exponential, accept with sqrt(1 - x0^2)
             xc = np.where(alpha > 0, -1.0 + np.log1p(u[0] * np.expm1(2.0 * alpha)) / np.where(alpha > 0, alpha, 1.0),
                           2.0 * u[0] - 1.0)
-            acc_c = u[1] <= np.sqrt(np.maximum(0.0, 1.0 - xc * xc))
+            acc_c = u[1] <= np.sqrt(np.maximum(0.0, (1.0 - xc) * (1.0 + xc)))
             # Kennedy-Pendleton
             lam2 = -(np.log(u[0]) + np.cos(2.0 * np.pi * u[1]) ** 2 * np.log(u[2])) / (2.0 * alpha)
             acc_k = u[3] * u[3] <= 1.0 - lam2
@@ -158,8 +161,8 @@ def update_su3(u, V, beta, seed: int, link, sweep: int, heatbath: bool):
             wd = _words(seed, link, sweep, sub, DIR_TRIAL)
             cth = 2.0 * uniform(wd[0]) - 1.0
             phi = 2.0 * np.pi * uniform(wd[1])
-            rad = np.sqrt(np.maximum(0.0, 1.0 - x0 * x0))
-            sth = np.sqrt(np.maximum(0.0, 1.0 - cth * cth))
+            rad = np.sqrt(np.maximum(0.0, (1.0 - x0) * (1.0 + x0)))
+            sth = np.sqrt(np.maximum(0.0, (1.0 - cth) * (1.0 + cth)))
             x = _su2(x0, rad * sth * np.cos(phi), rad * sth * np.sin(phi), rad * cth)
             r = x @ _dag(s)
         else:

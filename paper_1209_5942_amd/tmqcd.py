@@ -30,11 +30,11 @@ ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_byte
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg",
                 "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_bicgstab_workspace_bytes",
                 "tmqcd_bicgstab", "tmqcd_force", "tmqcd_force_eo_workspace_bytes", "tmqcd_force_eo",
-                "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle", "tmqcd_update_links",
-                "tmqcd_tune_workspace_bytes", "tmqcd_tune", "tmqcd_tune_save", "tmqcd_tune_load",
-                "tmqcd_tune_clear", "tmqcd_tune_set", "tmqcd_tune_mrhs_workspace_bytes", "tmqcd_tune_mrhs",
-                "tmqcd_plaquette", "tmqcd_momentum_norm2", "tmqcd_dot", "tmqcd_hbm_probe", "tmqcd_error_string",
-                "tmqcd_last_hip_error")
+                "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle", "tmqcd_heatbath",
+                "tmqcd_overrelax", "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune",
+                "tmqcd_tune_save", "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set",
+                "tmqcd_tune_mrhs_workspace_bytes", "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2",
+                "tmqcd_dot", "tmqcd_hbm_probe", "tmqcd_error_string", "tmqcd_last_hip_error")
 
 
 class TmqcdLibraryMissing(RuntimeError):
@@ -108,6 +108,8 @@ def lib():
             "tmqcd_gauge_force": (I, [P, V, D, V, D, I, V]),
             "tmqcd_gauge_force_tlsym": (I, [P, V, D, D, V, D, I, V]),
             "tmqcd_rectangle": (I, [P, V, V, V, S, V]),
+            "tmqcd_heatbath": (I, [P, V, D, ctypes.c_uint64, ctypes.c_uint32, V]),
+            "tmqcd_overrelax": (I, [P, V, V]),
             "tmqcd_update_links": (I, [P, V, V, D, V]),
             "tmqcd_plaquette": (I, [P, V, V, V, S, V]),
             "tmqcd_momentum_norm2": (I, [P, V, V, V, S, V]),
@@ -412,6 +414,17 @@ def gauge_force_tlsym(prob: Problem, U_packed, beta, c1, out=None, scale=1.0, ac
     _check(lib().tmqcd_gauge_force_tlsym(ctypes.byref(prob.c()), _ptr(U_packed), float(beta), float(c1), _ptr(out),
                                          float(scale), int(accumulate), _stream(stream)), "tmqcd_gauge_force_tlsym")
     return out
+
+
+def heatbath(prob: Problem, U_packed, beta, seed, sweep, stream=None):
+    """One heatbath sweep of the Wilson action, in place on packed FP64 RECON18 links."""
+    _check(lib().tmqcd_heatbath(ctypes.byref(prob.c()), _ptr(U_packed), float(beta), int(seed) & (2 ** 64 - 1),
+                                int(sweep) & 0xFFFFFFFF, _stream(stream)), "tmqcd_heatbath")
+
+
+def overrelax(prob: Problem, U_packed, stream=None):
+    """One overrelaxation sweep, in place on packed FP64 RECON18 links."""
+    _check(lib().tmqcd_overrelax(ctypes.byref(prob.c()), _ptr(U_packed), _stream(stream)), "tmqcd_overrelax")
 
 
 def update_links(prob: Problem, U_packed, p, dt, stream=None):

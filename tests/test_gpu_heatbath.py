@@ -1,0 +1,80 @@
+"""The heatbath and overrelaxation sweeps on the GPU against the FP64 oracle (same generator streams):
+links after heatbath and overrelaxation sweeps on several extents and couplings (both x0 methods),
+reproducibility, action conservation by overrelaxation, and the strong-coupling plaquette on 8^4."""
+import numpy as np
+import pytest
+
+from gpu_util import BC_AP, Fields, dev, host
+from oracle import force as F
+from oracle import heatbath as OHB
+from paper_1209_5942_amd import synth
+from paper_1209_5942_amd import tmqcd as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 2, 6, 4), (2, 2, 2, 2), (6, 4, 2, 8)])
+@pytest.mark.parametrize("beta", [0.0, 1.0, 5.7, 12.0])
+def test_sweeps_match_oracle(dims, beta):
+    """Sweep by sweep: the oracle gets the GPU's links before each sweep.  The chain itself magnifies
+    rounding (a new link depends on the direction s = q/k of its neighbourhood, and links updated
+    earlier in a sweep enter later staples), so two FP64 orderings of the same arithmetic drift apart
+    over several sweeps (to 1e-8 after three sweeps at beta = 0 between two CPU orderings).  From the
+    same links, two CPU orderings agree after one heatbath sweep to 2.8e-13 and after one
+    overrelaxation sweep to 2.6e-14 at beta >= 5.7 but only to 8.6e-12 at beta <= 1 (there k falls to
+    0.04 and the reflection (s^+)^2 follows s with no random draw to damp it).  Bounds: 1e-11, and
+    1e-9 for overrelaxation at beta <= 1."""
+    print(f"\nheatbath dims={dims} beta={beta}", flush=True)
+    f = Fields(dims, 0.5, 601, 0.15, 0.0, BC_AP)
+    seed = 0x1234_5678_9ABC_DEF0
+    g = f.gauge(T.F64, 0).clone()
+    before = f.U
+    for kind, sweep in (("hb", 7), ("hb", 8), ("or", 0)):
+        if kind == "hb":
+            T.heatbath(f.prob, g, beta, seed, sweep)
+            want = OHB.heatbath_sweep(before, dims, beta, seed, sweep)
+        else:
+            T.overrelax(f.prob, g)
+            want = OHB.overrelax_sweep(before, dims)
+        got = host(T.unpack_gauge(f.prob, g))
+        bound = 1e-9 if (kind == "or" and beta <= 1.0) else 1e-11
+        assert np.abs(got - want).max() < bound, (kind, sweep, np.abs(got - want).max())
+        assert np.abs(got - before).max() > 0.01
+        before = got
+
+
+def test_reproducible_and_stream_dependent():
+    dims = (4, 4, 4, 4)
+    f = Fields(dims, 0.5, 611, 0.15, 0.0, BC_AP)
+    outs = []
+    for seed, sweep in ((5, 0), (5, 0), (5, 1), (6, 0)):
+        g = f.gauge(T.F64, 0).clone()
+        T.heatbath(f.prob, g, 5.7, seed, sweep)
+        outs.append(g)
+    assert bool((outs[0] == outs[1]).all())
+    assert not bool((outs[0] == outs[2]).all()) and not bool((outs[0] == outs[3]).all())
+
+
+def test_overrelaxation_keeps_the_action():
+    dims = (8, 4, 4, 8)
+    f = Fields(dims, 0.5, 621, 0.15, 0.0, BC_AP)
+    g = f.gauge(T.F64, 0).clone()
+    p0 = float(T.plaquette(f.prob, g)[0])
+    for _ in range(3):
+        T.overrelax(f.prob, g)
+    p1 = float(T.plaquette(f.prob, g)[0])
+    assert abs(p1 - p0) < 1e-11 * abs(p0)
+    u = host(T.unpack_gauge(f.prob, g))
+    np.testing.assert_allclose(np.linalg.det(u), 1.0, atol=1e-13)
+
+
+def test_strong_coupling_plaquette_8x8x8x8():
+    dims, beta = (8, 8, 8, 8), 0.3
+    prob = T.Problem(dims, 0.15, 0.0, BC_AP)
+    g = T.pack_gauge(prob, dev(synth.random_links(dims, 0.3, 631).reshape(-1, 4, 3, 3)))
+    vals = []
+    for sw in range(30):
+        T.heatbath(prob, g, beta, 77, sw)
+        if sw >= 5:
+            vals.append(float(T.plaquette(prob, g)[0]) / (6 * prob.volume) / 3.0)
+    assert abs(np.mean(vals) - beta / 18.0) < 0.002, np.mean(vals)
