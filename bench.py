@@ -333,6 +333,7 @@ def main():
         result["multi_rhs_24x24x24x48"] = bench_multi_rhs(T, prob, U, dev)
         result["batch_cg"] = bench_batch(T, synth, dev)
         result["hmc_16x16x16x32"] = bench_hmc(T, synth, dev)
+        result["heatbath"] = bench_heatbath(T, synth, dev)
 
     # ------------------------------------- oracle check and CPU baseline ---
     if not args.no_oracle:
@@ -444,6 +445,44 @@ def traffic_from_counters(fetch_csv, write_csv, kernel_log):
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     print(json.dumps(rec))
+
+
+def bench_heatbath(T, synth, dev):
+    """Pure-gauge sweeps (Wilson action, beta 5.7) on 24^3x48 and 32^3x64: time per heatbath and per
+    overrelaxation sweep from HIP events, link updates per second, the FP64 flop rate in the paper's
+    count (3912 / 3846 flops per link update, its Table 2), and the HBM roofline of a sweep: each of its
+    8 launches (one direction and parity) reads the whole link field (the staples of the updated links
+    touch every direction of both parities) and writes the links it updates, 8 x 576 + 8 x 72 = 5184
+    algorithmic bytes per site and sweep."""
+    import numpy as np
+    import torch
+    log("heatbath / overrelaxation sweeps")
+    out = {}
+    for dims in ((24, 24, 24, 48), (32, 32, 32, 64)):
+        prob = T.Problem(dims, 0.15, 0.0, (1, 1, 1, -1))
+        g = T.pack_gauge(prob, torch.from_numpy(synth.random_links(dims, 0.4, 91)).to(dev))
+        for i in range(3):      # away from the start
+            T.heatbath(prob, g, 5.7, 92, 1000 + i)
+        counter = iter(range(10 ** 6))
+        t_hb = _events_time(lambda: T.heatbath(prob, g, 5.7, 92, next(counter)), 10)
+        t_or = _events_time(lambda: T.overrelax(prob, g), 10)
+        links = 4 * prob.volume
+        sweep_bytes = 5184 * prob.volume
+        plaq = float(T.plaquette(prob, g)[0]) / (18 * prob.volume)
+        out["x".join(map(str, dims))] = {
+            "heatbath_ms": round(t_hb * 1e3, 3), "overrelax_ms": round(t_or * 1e3, 3),
+            "heatbath_Glinks_s": round(links / t_hb / 1e9, 3), "overrelax_Glinks_s": round(links / t_or / 1e9, 3),
+            "heatbath_TFLOP_s_paper_count": round(links * 3912 / t_hb / 1e12, 2),
+            "overrelax_TFLOP_s_paper_count": round(links * 3846 / t_or / 1e12, 2),
+            "roofline_heatbath": {"bound": "hbm", "achieved": round(sweep_bytes / t_hb / 1e9, 1), "peak": PEAK_HBM_GBPS,
+                                  "unit": "GB/s", "frac": round(sweep_bytes / t_hb / 1e9 / PEAK_HBM_GBPS, 4)},
+            "roofline_overrelax": {"bound": "hbm", "achieved": round(sweep_bytes / t_or / 1e9, 1),
+                                   "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                                   "frac": round(sweep_bytes / t_or / 1e9 / PEAK_HBM_GBPS, 4)},
+            "plaquette_after": round(plaq, 5)}
+        del g
+    out["setup"] = "FP64 RECON18 links, Wilson action beta 5.7 from the eps 0.4 start; 3 sweeps before timing"
+    return out
 
 
 def creutz_4x4x4x4(T, synth, dev, eo=False):
