@@ -87,10 +87,17 @@ typedef struct {
 #define TMQCD_F32 1
 #define TMQCD_F16 2   /* IEEE half: links unscaled (|U_ab| <= 1), spinors with one FP32 scale per site */
 
-/* link storage: all 18 reals, or the first two rows (12 reals) with the third
- * rebuilt as conj(row1 x row2), exact for det U = 1 (the paper's REC12) */
+/* link storage (the paper's §4.1, Table 3): all 18 reals; the first two rows
+ * (12 reals) with the third rebuilt as conj(row1 x row2), exact for det U = 1
+ * (REC12); the first row and first column (10 reals), the other four entries
+ * rebuilt from unitarity and det U = 1 (REC10); as REC10 with |a1| and |c1|
+ * rebuilt from the unit norms of the first row and column and only their
+ * phases stored (8 reals, REC8).  REC10 and REC8 divide by |a2|^2 + |a3|^2 and
+ * lose accuracy as the first row approaches a pure phase times (1, 0, 0). */
 #define TMQCD_RECON18 0
 #define TMQCD_RECON12 1
+#define TMQCD_RECON10 2
+#define TMQCD_RECON8  3
 
 /* spinor subsets */
 #define TMQCD_FULL 0

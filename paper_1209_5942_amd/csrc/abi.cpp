@@ -31,7 +31,7 @@ bool valid_problem(const tmqcd_problem* p) {
     return true;
 }
 bool valid_prec(int p) { return p == TMQCD_F64 || p == TMQCD_F32 || p == TMQCD_F16; }
-bool valid_recon(int r) { return r == TMQCD_RECON18 || r == TMQCD_RECON12; }
+bool valid_recon(int r) { return r == TMQCD_RECON18 || r == TMQCD_RECON12 || r == TMQCD_RECON10 || r == TMQCD_RECON8; }
 bool valid_subset(int s) { return s == TMQCD_FULL || s == TMQCD_EVEN || s == TMQCD_ODD; }
 bool valid_op(int op) { return op >= TMQCD_DSLASH_EO && op <= TMQCD_MHATDAGMHAT; }
 bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }

@@ -209,7 +209,8 @@ template <int P, int R>
 struct LinkIO;
 
 template <int R>
-struct LinkIO<TMQCD_F64, R> {
+struct LinkIO64 {
+    static_assert(R == TMQCD_RECON18 || R == TMQCD_RECON12, "18- or 12-real FP64 links");
     using T = double;
     using Unit = double2;
     static constexpr int kUnits = R == TMQCD_RECON18 ? 9 : 6;
@@ -232,6 +233,10 @@ struct LinkIO<TMQCD_F64, R> {
         for (int k = 0; k < kUnits; ++k) p[k * gstride] = make_double2(u.m[k / 3][k % 3].re, u.m[k / 3][k % 3].im);
     }
 };
+template <>
+struct LinkIO<TMQCD_F64, TMQCD_RECON18> : LinkIO64<TMQCD_RECON18> {};
+template <>
+struct LinkIO<TMQCD_F64, TMQCD_RECON12> : LinkIO64<TMQCD_RECON12> {};
 
 template <>
 struct LinkIO<TMQCD_F32, TMQCD_RECON18> {
@@ -344,6 +349,195 @@ struct LinkIO<TMQCD_F16, TMQCD_RECON12> {
             w.h[3] = __float2half_rn((float)b.im);
             p[k * gstride] = w.u;
         }
+    }
+};
+
+// ------------------------------------------------- REC10 and REC8 links ---
+// REC10 keeps the first row a and the first column (a1, b1, c1); b2, b3 solve
+// conj(a2) b2 + conj(a3) b3 = -conj(a1) b1 (b orthogonal to a) and
+// -a3 b2 + a2 b3 = conj(c1) (the first entry of c = conj(a x b)), and
+// c2, c3 follow from c = conj(a x b); written out with n = 1/(|a2|^2 + |a3|^2):
+template <typename T>
+__device__ __forceinline__ void complete_from_row_col(Su3<T>& u) {
+    const C<T> a1 = u.m[0][0], a2 = u.m[0][1], a3 = u.m[0][2], b1 = u.m[1][0], c1 = u.m[2][0];
+    const T n = T(1) / (norm2(a2) + norm2(a3));
+    const C<T> a1c = conj(a1), c1c = conj(c1), b1c = conj(b1);
+    u.m[1][1] = scale(-n, b1 * a1c * a2 + c1c * conj(a3));
+    u.m[1][2] = scale(-n, b1 * a1c * a3 - c1c * conj(a2));
+    u.m[2][1] = scale(n, b1c * conj(a3) - c1 * a1c * a2);
+    u.m[2][2] = scale(-n, b1c * conj(a2) + c1 * a1c * a3);
+}
+
+__device__ __forceinline__ void sincos_pi(double x, double* s, double* c) { sincospi(x, s, c); }
+__device__ __forceinline__ void sincos_pi(float x, float* s, float* c) { sincospif(x, s, c); }
+
+// REC8: a1 and c1 from their phases (stored as angle / pi) and the unit norms of
+// the first row and the first column, then as REC10
+template <typename T>
+__device__ __forceinline__ void complete_rec8(Su3<T>& u, T tha, T thc) {
+    const T ra = sqrt(fmax(T(0), T(1) - norm2(u.m[0][1]) - norm2(u.m[0][2])));
+    T s, c;
+    sincos_pi(tha, &s, &c);
+    u.m[0][0] = {ra * c, ra * s};
+    const T rc = sqrt(fmax(T(0), T(1) - ra * ra - norm2(u.m[1][0])));
+    sincos_pi(thc, &s, &c);
+    u.m[2][0] = {rc * c, rc * s};
+    complete_from_row_col(u);
+}
+__host__ __device__ inline double phase_over_pi(const C<double>& z) { return atan2(z.im, z.re) / M_PI; }
+
+// one complex entry per unit: FP64 double2, FP32 float2, FP16 half2
+template <int P>
+struct Entry;
+template <>
+struct Entry<TMQCD_F64> {
+    using T = double;
+    using Unit = double2;
+    __device__ __forceinline__ static C<T> get(Unit w) { return {w.x, w.y}; }
+    __device__ __forceinline__ static Unit put(const C<double>& z) { return make_double2(z.re, z.im); }
+};
+template <>
+struct Entry<TMQCD_F32> {
+    using T = float;
+    using Unit = float2;
+    __device__ __forceinline__ static C<T> get(Unit w) { return {w.x, w.y}; }
+    __device__ __forceinline__ static Unit put(const C<double>& z) { return make_float2((float)z.re, (float)z.im); }
+};
+template <>
+struct Entry<TMQCD_F16> {
+    using T = float;
+    using Unit = __half2;
+    __device__ __forceinline__ static C<T> get(Unit w) {
+        const float2 f = __half22float2(w);
+        return {f.x, f.y};
+    }
+    __device__ __forceinline__ static Unit put(const C<double>& z) {
+        return __halves2half2(__float2half_rn((float)z.re), __float2half_rn((float)z.im));
+    }
+};
+
+// REC10: units a1, a2, a3, b1, c1
+template <int P>
+struct LinkIO10 {
+    using E = Entry<P>;
+    using T = typename E::T;
+    using Unit = typename E::Unit;
+    static constexpr int kUnits = 5;
+    template <bool STREAM = true>
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const Unit* p = reinterpret_cast<const Unit*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+        C<T> e[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) e[k] = E::get(STREAM ? ld_stream(p + k * gstride) : p[k * gstride]);
+        u.m[0][0] = e[0];
+        u.m[0][1] = e[1];
+        u.m[0][2] = e[2];
+        u.m[1][0] = e[3];
+        u.m[2][0] = e[4];
+        complete_from_row_col(u);
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        Unit* p = reinterpret_cast<Unit*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+        p[0] = E::put(u.m[0][0]);
+        p[gstride] = E::put(u.m[0][1]);
+        p[2 * gstride] = E::put(u.m[0][2]);
+        p[3 * gstride] = E::put(u.m[1][0]);
+        p[4 * gstride] = E::put(u.m[2][0]);
+    }
+};
+template <>
+struct LinkIO<TMQCD_F64, TMQCD_RECON10> : LinkIO10<TMQCD_F64> {};
+template <>
+struct LinkIO<TMQCD_F32, TMQCD_RECON10> : LinkIO10<TMQCD_F32> {};
+template <>
+struct LinkIO<TMQCD_F16, TMQCD_RECON10> : LinkIO10<TMQCD_F16> {};
+
+// REC8, FP64: units (theta_a / pi, theta_c / pi), a2, a3, b1
+template <>
+struct LinkIO<TMQCD_F64, TMQCD_RECON8> {
+    using T = double;
+    using Unit = double2;
+    static constexpr int kUnits = 4;
+    template <bool STREAM = true>
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const double2* p = reinterpret_cast<const double2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+        double2 w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = STREAM ? ld_stream(p + k * gstride) : p[k * gstride];
+        u.m[0][1] = {w[1].x, w[1].y};
+        u.m[0][2] = {w[2].x, w[2].y};
+        u.m[1][0] = {w[3].x, w[3].y};
+        complete_rec8(u, w[0].x, w[0].y);
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        double2* p = reinterpret_cast<double2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+        p[0] = make_double2(phase_over_pi(u.m[0][0]), phase_over_pi(u.m[2][0]));
+        p[gstride] = make_double2(u.m[0][1].re, u.m[0][1].im);
+        p[2 * gstride] = make_double2(u.m[0][2].re, u.m[0][2].im);
+        p[3 * gstride] = make_double2(u.m[1][0].re, u.m[1][0].im);
+    }
+};
+
+// REC8, FP32: units (theta_a / pi, theta_c / pi, a2), (a3, b1)
+template <>
+struct LinkIO<TMQCD_F32, TMQCD_RECON8> {
+    using T = float;
+    using Unit = float4;
+    static constexpr int kUnits = 2;
+    template <bool STREAM = true>
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const float4* p = reinterpret_cast<const float4*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+        const float4 w0 = STREAM ? ld_stream(p) : p[0];
+        const float4 w1 = STREAM ? ld_stream(p + gstride) : p[gstride];
+        u.m[0][1] = {w0.z, w0.w};
+        u.m[0][2] = {w1.x, w1.y};
+        u.m[1][0] = {w1.z, w1.w};
+        complete_rec8(u, w0.x, w0.y);
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        float4* p = reinterpret_cast<float4*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+        p[0] = make_float4((float)phase_over_pi(u.m[0][0]), (float)phase_over_pi(u.m[2][0]), (float)u.m[0][1].re,
+                           (float)u.m[0][1].im);
+        p[gstride] = make_float4((float)u.m[0][2].re, (float)u.m[0][2].im, (float)u.m[1][0].re, (float)u.m[1][0].im);
+    }
+};
+
+// REC8, FP16: one unit of eight halves (theta_a / pi, theta_c / pi, a2, a3, b1)
+template <>
+struct LinkIO<TMQCD_F16, TMQCD_RECON8> {
+    using T = float;
+    using Unit = uint4;
+    static constexpr int kUnits = 1;
+    union U16 {
+        uint4 u;
+        __half h[8];
+    };
+    template <bool STREAM = true>
+    __device__ __forceinline__ static void load(Su3<T>& u, const char* base, int64_t gstride, int par, int mu,
+                                                int64_t h) {
+        const uint4* p = reinterpret_cast<const uint4*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+        U16 w;
+        w.u = STREAM ? ld_stream(p) : p[0];
+        u.m[0][1] = {__half2float(w.h[2]), __half2float(w.h[3])};
+        u.m[0][2] = {__half2float(w.h[4]), __half2float(w.h[5])};
+        u.m[1][0] = {__half2float(w.h[6]), __half2float(w.h[7])};
+        complete_rec8(u, __half2float(w.h[0]), __half2float(w.h[1]));
+    }
+    __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
+                                                 const Su3<double>& u) {
+        uint4* p = reinterpret_cast<uint4*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
+        U16 w;
+        const double v[8] = {phase_over_pi(u.m[0][0]), phase_over_pi(u.m[2][0]), u.m[0][1].re, u.m[0][1].im,
+                             u.m[0][2].re, u.m[0][2].im, u.m[1][0].re, u.m[1][0].im};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w.h[k] = __float2half_rn((float)v[k]);
+        p[0] = w.u;
     }
 };
 

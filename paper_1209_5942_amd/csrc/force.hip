@@ -211,8 +211,13 @@ hipError_t launch_force(const Geom& g, const void* gauge, int recon, const void*
     k.scale = scale;
     k.accumulate = accumulate;
     const dim3 grid(2 * k.nb_half);
-    if (recon == TMQCD_RECON12) hipLaunchKernelGGL((force_dir_kernel<TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k);
-    else hipLaunchKernelGGL((force_dir_kernel<TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k);
+    switch (recon) {
+        case TMQCD_RECON18: hipLaunchKernelGGL((force_dir_kernel<TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k); break;
+        case TMQCD_RECON12: hipLaunchKernelGGL((force_dir_kernel<TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k); break;
+        case TMQCD_RECON10: hipLaunchKernelGGL((force_dir_kernel<TMQCD_RECON10>), grid, dim3(kBlock), 0, s, k); break;
+        case TMQCD_RECON8: hipLaunchKernelGGL((force_dir_kernel<TMQCD_RECON8>), grid, dim3(kBlock), 0, s, k); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

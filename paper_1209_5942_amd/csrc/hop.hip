@@ -94,19 +94,9 @@ hipError_t launch_hop(const HopParams& a_in, hipStream_t s, int* nblocks) {
     if (nblocks) *nblocks = a.nrhs > 1 ? 0 : k.nblocks;
     const int want_vprec = a.prec == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
     if (a.epi == kEpiCgUpdate && a.vprec != want_vprec) return hipErrorInvalidValue;
-    const bool r12 = a.recon == TMQCD_RECON12;
-    switch (a.prec) {
-        case TMQCD_F64:
-            return r12 ? dispatch_variant<TMQCD_F64, TMQCD_RECON12>(a, k, s)
-                       : dispatch_variant<TMQCD_F64, TMQCD_RECON18>(a, k, s);
-        case TMQCD_F32:
-            return r12 ? dispatch_variant<TMQCD_F32, TMQCD_RECON12>(a, k, s)
-                       : dispatch_variant<TMQCD_F32, TMQCD_RECON18>(a, k, s);
-        case TMQCD_F16:
-            return r12 ? dispatch_variant<TMQCD_F16, TMQCD_RECON12>(a, k, s)
-                       : dispatch_variant<TMQCD_F16, TMQCD_RECON18>(a, k, s);
-    }
-    return hipErrorInvalidValue;
+    return with_link_format(a.prec, a.recon, [&](auto p, auto r) {
+        return dispatch_variant<decltype(p)::value, decltype(r)::value>(a, k, s);
+    });
 }
 
 }  // namespace tmqcd

@@ -36,17 +36,20 @@ __global__ __launch_bounds__(kBlock) void hop_batch_kernel(const HopBatch b) {
     }
 }
 
-template <bool DAG, bool OWN, int EPI>
+template <int R, bool DAG, bool OWN, int EPI>
 hipError_t launch_batch_inst(const HopBatch& b, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((hop_batch_kernel<TMQCD_F64, TMQCD_RECON18, DAG, OWN, EPI, TMQCD_F64>), dim3(grid),
-                       dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL((hop_batch_kernel<TMQCD_F64, R, DAG, OWN, EPI, TMQCD_F64>), dim3(grid), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 template <bool DAG, bool OWN, int EPI>
-hipError_t launch_batch_inst12(const HopBatch& b, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((hop_batch_kernel<TMQCD_F64, TMQCD_RECON12, DAG, OWN, EPI, TMQCD_F64>), dim3(grid),
-                       dim3(kBlock), 0, s, b);
-    return hipGetLastError();
+hipError_t launch_batch_recon(int recon, const HopBatch& b, int grid, hipStream_t s) {
+    switch (recon) {
+        case TMQCD_RECON18: return launch_batch_inst<TMQCD_RECON18, DAG, OWN, EPI>(b, grid, s);
+        case TMQCD_RECON12: return launch_batch_inst<TMQCD_RECON12, DAG, OWN, EPI>(b, grid, s);
+        case TMQCD_RECON10: return launch_batch_inst<TMQCD_RECON10, DAG, OWN, EPI>(b, grid, s);
+        case TMQCD_RECON8: return launch_batch_inst<TMQCD_RECON8, DAG, OWN, EPI>(b, grid, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -71,8 +74,8 @@ hipError_t launch_hop_batch(const HopParams* ps, int n, int max_grid, hipStream_
     const int total = b.tile_start[n];
     const int grid = total < max_grid ? total : max_grid;
     const HopParams& a = ps[0];
-    const bool own = a.own != nullptr, r12 = a.recon == TMQCD_RECON12;
-#define TMQCD_BATCH(D, O, E) return r12 ? launch_batch_inst12<D, O, E>(b, grid, s) : launch_batch_inst<D, O, E>(b, grid, s)
+    const bool own = a.own != nullptr;
+#define TMQCD_BATCH(D, O, E) return launch_batch_recon<D, O, E>(a.recon, b, grid, s)
     switch (a.epi) {
         case kEpiStore:
             if (!a.dag && !own) TMQCD_BATCH(false, false, kEpiStore);

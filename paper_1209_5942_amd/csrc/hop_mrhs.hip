@@ -119,13 +119,9 @@ hipError_t launch_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_hop_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
-    const bool r12 = a.recon == TMQCD_RECON12;
-    switch (a.prec) {
-        case TMQCD_F64: return r12 ? launch_mrhs<TMQCD_F64, TMQCD_RECON12>(a, k, s) : launch_mrhs<TMQCD_F64, TMQCD_RECON18>(a, k, s);
-        case TMQCD_F32: return r12 ? launch_mrhs<TMQCD_F32, TMQCD_RECON12>(a, k, s) : launch_mrhs<TMQCD_F32, TMQCD_RECON18>(a, k, s);
-        case TMQCD_F16: return r12 ? launch_mrhs<TMQCD_F16, TMQCD_RECON12>(a, k, s) : launch_mrhs<TMQCD_F16, TMQCD_RECON18>(a, k, s);
-    }
-    return hipErrorInvalidValue;
+    return with_link_format(a.prec, a.recon, [&](auto p, auto r) {
+        return launch_mrhs<decltype(p)::value, decltype(r)::value>(a, k, s);
+    });
 }
 
 }  // namespace stencil

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "layout.h"
 
@@ -85,6 +86,22 @@ hipError_t launch_hop_batch(const HopParams* ps, int n, int max_grid, hipStream_
 int hop_blocks(const Geom& g, int nparity);   // grid size (and partial count) of a hop launch
 
 // ---- BLAS-1 over packed fields of nhalf half fields -------------------------
+// Calls f(integral_constant<P>, integral_constant<R>) for the run-time storage precision and
+// link encoding (every combination is compiled); hipErrorInvalidValue for an unknown pair.
+template <typename F>
+hipError_t with_link_format(int prec, int recon, F&& f) {
+    using std::integral_constant;
+#define TMQCD_LF(P, R) \
+    if (prec == P && recon == R) return f(integral_constant<int, P>{}, integral_constant<int, R>{});
+#define TMQCD_LF_R(P) TMQCD_LF(P, TMQCD_RECON18) TMQCD_LF(P, TMQCD_RECON12) TMQCD_LF(P, TMQCD_RECON10) TMQCD_LF(P, TMQCD_RECON8)
+    TMQCD_LF_R(TMQCD_F64)
+    TMQCD_LF_R(TMQCD_F32)
+    TMQCD_LF_R(TMQCD_F16)
+#undef TMQCD_LF_R
+#undef TMQCD_LF
+    return hipErrorInvalidValue;
+}
+
 struct VecSpec {
     const Geom* g;
     int nhalf;       // 1 = half field, 2 = full field

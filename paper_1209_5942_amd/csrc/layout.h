@@ -68,14 +68,19 @@ inline int64_t field_bytes(const Geom& g, int prec, int subset) {
 
 // gauge: number of storage units per link and bytes per unit
 inline int gauge_units(int prec, int recon) {
-    if (recon == TMQCD_RECON18) return 9;
-    return prec == TMQCD_F64 ? 6 : 3;
+    switch (recon) {
+        case TMQCD_RECON18: return 9;
+        case TMQCD_RECON12: return prec == TMQCD_F64 ? 6 : 3;
+        case TMQCD_RECON10: return 5;
+        case TMQCD_RECON8: return prec == TMQCD_F64 ? 4 : (prec == TMQCD_F32 ? 2 : 1);
+    }
+    return 0;
 }
 inline int gauge_unit_bytes(int prec, int recon) {
     switch (prec) {
         case TMQCD_F64: return 16;
-        case TMQCD_F32: return recon == TMQCD_RECON18 ? 8 : 16;
-        case TMQCD_F16: return recon == TMQCD_RECON18 ? 4 : 8;
+        case TMQCD_F32: return (recon == TMQCD_RECON18 || recon == TMQCD_RECON10) ? 8 : 16;
+        case TMQCD_F16: return (recon == TMQCD_RECON18 || recon == TMQCD_RECON10) ? 4 : (recon == TMQCD_RECON12 ? 8 : 16);
     }
     return 0;
 }

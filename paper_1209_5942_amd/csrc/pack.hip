@@ -110,24 +110,11 @@ hipError_t launch_pack_gauge(const Geom& g, const void* canon, void* packed, int
     const dim3 grid((unsigned)((k.vol + kBlock - 1) / kBlock));
     const double2* c = static_cast<const double2*>(canon);
     char* p = static_cast<char*>(packed);
-    const bool r12 = recon == TMQCD_RECON12;
-    switch (prec) {
-        case TMQCD_F64:
-            if (r12) hipLaunchKernelGGL((pack_gauge_kernel<TMQCD_F64, TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k, c, p);
-            else hipLaunchKernelGGL((pack_gauge_kernel<TMQCD_F64, TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k, c, p);
-            break;
-        case TMQCD_F32:
-            if (r12) hipLaunchKernelGGL((pack_gauge_kernel<TMQCD_F32, TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k, c, p);
-            else hipLaunchKernelGGL((pack_gauge_kernel<TMQCD_F32, TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k, c, p);
-            break;
-        case TMQCD_F16:
-            if (r12) hipLaunchKernelGGL((pack_gauge_kernel<TMQCD_F16, TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k, c, p);
-            else hipLaunchKernelGGL((pack_gauge_kernel<TMQCD_F16, TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k, c, p);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return with_link_format(prec, recon, [&](auto pp, auto rr) {
+        hipLaunchKernelGGL((pack_gauge_kernel<decltype(pp)::value, decltype(rr)::value>), grid, dim3(kBlock), 0, s, k,
+                           c, p);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_unpack_gauge(const Geom& g, const void* packed, void* canon, int prec, int recon, hipStream_t s) {
@@ -135,18 +122,11 @@ hipError_t launch_unpack_gauge(const Geom& g, const void* packed, void* canon, i
     const dim3 grid((unsigned)((k.vol + kBlock - 1) / kBlock));
     double2* c = static_cast<double2*>(canon);
     const char* p = static_cast<const char*>(packed);
-    const bool r12 = recon == TMQCD_RECON12;
-#define TMQCD_UNPACK(PR)                                                                                      \
-    if (prec == PR) {                                                                                         \
-        if (r12) hipLaunchKernelGGL((unpack_gauge_kernel<PR, TMQCD_RECON12>), grid, dim3(kBlock), 0, s, k, c, p); \
-        else hipLaunchKernelGGL((unpack_gauge_kernel<PR, TMQCD_RECON18>), grid, dim3(kBlock), 0, s, k, c, p);     \
-        return hipGetLastError();                                                                             \
-    }
-    TMQCD_UNPACK(TMQCD_F64)
-    TMQCD_UNPACK(TMQCD_F32)
-    TMQCD_UNPACK(TMQCD_F16)
-#undef TMQCD_UNPACK
-    return hipErrorInvalidValue;
+    return with_link_format(prec, recon, [&](auto pp, auto rr) {
+        hipLaunchKernelGGL((unpack_gauge_kernel<decltype(pp)::value, decltype(rr)::value>), grid, dim3(kBlock), 0, s,
+                           k, c, p);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_pack_spinor(const Geom& g, const void* canon, void* packed, int prec, int subset, int nrhs,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libtmqcd.so")
 # constants of include/tmqcd.h
 OK, EINVAL, EALIAS, EALIGN, ENOCONV, EBREAKDOWN, EHIP, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F16 = 0, 1, 2
-RECON18, RECON12 = 0, 1
+RECON18, RECON12, RECON10, RECON8 = 0, 1, 2, 3
 FULL, EVEN, ODD = 0, 1, 2
 DSLASH_EO, DSLASH_OE, M, MDAG, MDAGM, MHAT, MHATDAG, MHATDAGMHAT = range(8)
 OPS = {"DSLASH_EO": DSLASH_EO, "DSLASH_OE": DSLASH_OE, "M": M, "MDAG": MDAG, "MDAGM": MDAGM,

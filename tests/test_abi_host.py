@@ -34,6 +34,11 @@ def test_sizes_match_paper_memory_table(L):
     assert T.spinor_bytes(prob, T.F64, T.EVEN) == gold["phi_eo"] * v
     assert T.gauge_bytes(prob, T.F64, T.RECON18) == gold["U"] * v
     assert T.gauge_bytes(prob, T.F64, T.RECON12) == gold["U_REC12"] * v
+    assert T.gauge_bytes(prob, T.F64, T.RECON10) == gold["U_REC10"] * v
+    assert T.gauge_bytes(prob, T.F64, T.RECON8) == gold["U_REC8"] * v
+    for rec, key in ((T.RECON10, "U_REC10"), (T.RECON8, "U_REC8")):
+        assert T.gauge_bytes(prob, T.F32, rec) == gold[key] * v // 2
+        assert T.gauge_bytes(prob, T.F16, rec) == gold[key] * v // 4
     # lower precisions halve and quarter the storage (FP16 spinors carry one FP32 scale per site)
     assert T.spinor_bytes(prob, T.F32, T.FULL) == gold["phi"] * v // 2
     assert T.spinor_bytes(prob, T.F16, T.FULL) == gold["phi"] * v // 4 + 4 * v
@@ -66,7 +71,8 @@ def test_dslash_argument_errors(L):
     assert _dslash(L, prob, None, a, b) == T.EINVAL
     assert _dslash(L, prob, U, a, b, op=99) == T.EINVAL
     assert _dslash(L, prob, U, a, b, prec=3) == T.EINVAL
-    assert _dslash(L, prob, U, a, b, recon=2) == T.EINVAL
+    assert _dslash(L, prob, U, a, b, recon=4) == T.EINVAL
+    assert _dslash(L, prob, U, a, b, recon=-1) == T.EINVAL
     assert _dslash(L, prob, U, a, b, nrhs=0) == T.EINVAL
     assert _dslash(L, prob, U, a, b, nrhs=17) == T.EINVAL
     assert _dslash(L, prob, U, a + 8, b) == T.EALIGN
