@@ -28,7 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0          # MI355X published HBM3E bandwidth
-BYTES_PER_SITE = {(0, 0): 1536, (0, 1): 1152, (1, 0): 768, (1, 1): 576, (2, 0): 392, (2, 1): 296}
+# per output site of a hop: 8 links + one input spinor + one output spinor (perfect neighbour reuse);
+# links by (precision, encoding) 144/96/80/64 B in FP64 (REC18/12/10/8), half and a quarter of that in
+# FP32 and FP16; spinors 192 / 96 / 52 B (FP16 with its FP32 scale)
+_LINK = {0: (144, 96, 80, 64), 1: (72, 48, 40, 32), 2: (36, 24, 20, 16)}
+_SPINOR = {0: 192, 1: 96, 2: 52}
+BYTES_PER_SITE = {(p, r): 8 * _LINK[p][r] + 2 * _SPINOR[p] for p in range(3) for r in range(4)}
 FLOPS_PER_SITE = 1320           # Wilson hop, per output site
 WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.5, kappa=0.16, mu=0.005, seed=24, src_seed=26)
 MIXED = dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.162, mu=0.003, seed=32, src_seed=34)
@@ -112,7 +117,7 @@ def main():
     U = synth.random_links(dims, w["eps"], w["seed"])
     b = synth.gaussian_spinor(vh, w["src_seed"])
     U_dev = torch.from_numpy(U).to(dev)
-    gauges = {(p, r): T.pack_gauge(prob, U_dev, p, r) for p in (T.F64, T.F32, T.F16) for r in (0, 1)}
+    gauges = {(p, r): T.pack_gauge(prob, U_dev, p, r) for p in (T.F64, T.F32, T.F16) for r in (0, 1, 2, 3)}
     del U_dev
     b_dev = T.pack_spinor(prob, torch.from_numpy(b).to(dev), T.F64, T.EVEN)
     x_dev = torch.empty(T.spinor_bytes(prob, T.F64, T.EVEN), dtype=torch.uint8, device=dev)
@@ -169,12 +174,12 @@ def main():
 
     t_hop, gbs_hop, gflops_hop = time_hop(T.F64, T.RECON18, 200)
     for p in (T.F64, T.F32, T.F16):            # the sweep in tuned shapes too
-        for r in (0, 1):
+        for r in (0, 1, 2, 3):
             if (p, r) != (T.F64, T.RECON18):
                 T.tune(prob, gauges[(p, r)], p, r)
     sweep = {}
     for p, pn in ((T.F64, "f64"), (T.F32, "f32"), (T.F16, "f16")):
-        for r, rn in ((0, "rec18"), (1, "rec12")):
+        for r, rn in ((0, "rec18"), (1, "rec12"), (2, "rec10"), (3, "rec8")):
             t, gbs, gf = time_hop(p, r)
             sweep[f"{pn}_{rn}"] = {"us": round(t * 1e6, 2), "GB_s": round(gbs, 1), "GFLOPS": round(gf, 1),
                                    "bytes_per_site": BYTES_PER_SITE[(p, r)]}
