@@ -729,9 +729,12 @@ def bench_hmc(T, synth, dev):
     ws_eo = T._bytes(T.force_eo_workspace_bytes(prob), dev)
     t_force_eo = _events_time(lambda: T.force_eo(prob, h.U, Xe, out=G, ws=ws_eo), 20)
     # gauge forces: Wilson plaquettes and the tree-level Symanzik action (c1 = -1/12); flops counted as
-    # 198 per 3x3 complex product (27 complex multiply-adds) over the products one link's staples take
+    # 198 per 3x3 complex product (27 complex multiply-adds) over the products that walking one link's
+    # loops takes (the kernel needs fewer: it builds rectangle staples from stored plaquette staples)
     t_gauge_w = _events_time(lambda: T.gauge_force(prob, h.U, 3.9, out=G), 20)
-    t_gauge_s = _events_time(lambda: T.gauge_force_tlsym(prob, h.U, 3.9, -1.0 / 12.0, out=G), 20)
+    ws_sym = T._bytes(T.gauge_force_tlsym_workspace_bytes(prob), dev)
+    t_gauge_s = _events_time(lambda: T.gauge_force_tlsym(prob, h.U, 3.9, -1.0 / 12.0, out=G, ws=ws_sym), 20)
+    del ws_sym
     flops_w = 4 * prob.volume * 198 * (6 * 2 + 1)
     flops_s = 4 * prob.volume * 198 * (6 * 2 + 18 * 4 + 1)
 

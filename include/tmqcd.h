@@ -268,10 +268,17 @@ int tmqcd_gauge_force(const tmqcd_problem* prob, const void* U_packed, double be
  * c1 = -1/12; c1 = 0 gives tmqcd_gauge_force's Wilson action.
  *   G^a = (beta/3) Im Tr[T^a U_mu(x) V_mu(x)],  V_mu = c0 (6 plaquette staples) + c1 (18 rectangle staples),
  * written or accumulated into dSdw[V][4][8] like tmqcd_force.  U_packed: FP64, RECON18.
+ * For c1 != 0 a first kernel stores the 24 single plaquette staples of every
+ * site in ws (tmqcd_gauge_force_tlsym_workspace_bytes(prob) bytes, 3456 per
+ * site: device, 256-byte aligned, caller-owned, overwritten) and each rectangle
+ * staple is then a product of two stored staples and a link (U^+ U = 1); for
+ * c1 = 0 ws is not used and may be NULL.
  * Errors: TMQCD_EINVAL (bad problem, null pointer, non-finite beta, c1 or scale,
- * accumulate not 0/1), TMQCD_EALIGN, TMQCD_EALIAS (dSdw overlaps U_packed). */
+ * accumulate not 0/1), TMQCD_EALIGN, TMQCD_EWORKSPACE (c1 != 0 and ws missing
+ * or short), TMQCD_EALIAS (dSdw overlaps U_packed; ws overlaps U_packed or dSdw). */
+size_t tmqcd_gauge_force_tlsym_workspace_bytes(const tmqcd_problem* prob);
 int tmqcd_gauge_force_tlsym(const tmqcd_problem* prob, const void* U_packed, double beta, double c1, double* dSdw,
-                            double scale, int accumulate, void* stream);
+                            double scale, int accumulate, void* ws, size_t ws_bytes, void* stream);
 /* U_mu(x) <- exp(i dt p^a T^a) U_mu(x) for every link, in place on the packed
  * FP64 RECON18 field; p[V][4][8] (device, float64).  The exponential is exact to
  * FP64 rounding (Taylor polynomial after scaling, then squaring). */

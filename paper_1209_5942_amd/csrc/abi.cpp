@@ -334,15 +334,28 @@ int tmqcd_gauge_force(const tmqcd_problem* prob, const void* U_packed, double be
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
+size_t tmqcd_gauge_force_tlsym_workspace_bytes(const tmqcd_problem* prob) {
+    if (!valid_problem(prob)) return 0;
+    return (size_t)round_up(staple_field_bytes(make_geom(*prob)), kAlignBytes);
+}
+
 int tmqcd_gauge_force_tlsym(const tmqcd_problem* prob, const void* U_packed, double beta, double c1, double* dSdw,
-                            double scale, int accumulate, void* stream) {
+                            double scale, int accumulate, void* ws, size_t ws_bytes, void* stream) {
     if (!valid_problem(prob) || !U_packed || !dSdw || !std::isfinite(beta) || !std::isfinite(c1) ||
         !std::isfinite(scale) || (accumulate != 0 && accumulate != 1))
         return TMQCD_EINVAL;
     if (!aligned(U_packed, kAlignBytes) || !aligned(dSdw, 16)) return TMQCD_EALIGN;
     const Geom g = make_geom(*prob);
-    if (overlap(dSdw, mom_bytes(g), U_packed, gauge_bytes(g, TMQCD_F64, TMQCD_RECON18))) return TMQCD_EALIAS;
-    const hipError_t e = launch_gauge_force_sym(g, U_packed, beta, c1, dSdw, scale, accumulate, (hipStream_t)stream);
+    const int64_t ub = gauge_bytes(g, TMQCD_F64, TMQCD_RECON18), ob = mom_bytes(g);
+    if (overlap(dSdw, ob, U_packed, ub)) return TMQCD_EALIAS;
+    if (c1 != 0.0) {
+        const int64_t need = staple_field_bytes(g);
+        if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
+        if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+        if (overlap(ws, need, U_packed, ub) || overlap(ws, need, dSdw, ob)) return TMQCD_EALIAS;
+    }
+    const hipError_t e =
+        launch_gauge_force_sym(g, U_packed, beta, c1, dSdw, scale, accumulate, ws, (hipStream_t)stream);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 

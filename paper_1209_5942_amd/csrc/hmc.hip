@@ -5,7 +5,8 @@
 //     G^a = (beta/3) Im Tr[T^a U_mu(x) V_mu(x)] with V_mu the six staples,
 //     written or accumulated with a scale factor (momentum updates fuse here);
 //   * the tree-level Symanzik force, V_mu = c0 (6 plaquette staples) + c1 (18
-//     rectangle staples), c0 = 1 - 8 c1, and the rectangle sum of its action;
+//     rectangle staples), c0 = 1 - 8 c1, from a stored field of plaquette
+//     staples, and the rectangle sum of its action;
 //   * link update U_mu(x) <- exp(i dt p^a T^a) U_mu(x): the exponential of the
 //     anti-hermitian generator by a degree-16 Taylor polynomial after scaling
 //     by 2^-n (||dt P|| / 2^n <= 1/4) and n squarings;
@@ -57,14 +58,9 @@ __global__ __launch_bounds__(kBlock) void gauge_force_kernel(LatK k, const char*
 // ------------------------------------------- tree-level Symanzik action ---
 // Loops are walked as lists of signed 1-based directions: +(d+1) moves forwards
 // over U_d(y), -(d+1) backwards over U_d(y - d)^+.  The rectangle R_mu_nu(x) is
-// two links long in mu and one in nu; the loops through U_mu(x), walked forwards
-// over it, leave from x + mu as (m = mu+1, s = +-(nu+1)):
-//   plaquette           s, -m, -s
-//   rectangle, link 1   m, s, -m, -m, -s      (long in mu, U_mu(x) its first mu link)
-//   rectangle, link 2   s, -m, -m, -s, m      (long in mu, U_mu(x) its second mu link)
-//   rectangle, long nu  s, s, -m, -s, -s
-// and V_mu(x) = c0 sum(plaquette staples) + c1 sum(rectangle staples), so that
-// the loops' traces are Tr[U_mu(x) V_mu(x)].
+// two links long in mu and one in nu: m, m, n, -m, -m, -n from x (m = mu+1,
+// n = nu+1); the action's rectangle sum walks it, the force (below) builds the
+// rectangle staples from stored plaquette staples.
 
 // moves pos one step along the signed direction (selects, so pos stays in registers)
 __device__ __forceinline__ void move(int pos[4], int st) {
@@ -109,11 +105,27 @@ __device__ __forceinline__ void add_scaled(Su3<double>& v, double c, const Su3<d
         for (int j = 0; j < 3; ++j) v.m[i][j] = v.m[i][j] + scale(c, a.m[i][j]);
 }
 
+// The Symanzik force from a stored staple field.  With the single plaquette
+// staples of U_mu(x),
+//   Sigma+_{mu nu}(x) = U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+,
+//   Sigma-_{mu nu}(x) = U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu),
+// and U^+ U = 1, the three rectangle staples of side s (s = +nu or -nu) are
+//   U_mu(x+mu) Sigma_s(x+mu) Sigma_s(x)          (long in mu, U_mu(x) the first link)
+//   Sigma_s(x) Sigma_s(x-mu) U_mu(x-mu)          (long in mu, U_mu(x) the second link)
+//   U_nu(x+mu) Sigma+(x+nu) U_nu(x)^+   or   U_nu(x+mu-nu)^+ Sigma-(x-nu) U_nu(x-nu)   (long in nu)
+// so a link takes 36 products and 38 matrix loads instead of 84 products and 108
+// link loads when every loop is walked.  The field holds 24 matrices per site,
+// component (mu * 3 + j) * 2 + side, j the rank of nu among the directions other
+// than mu, side 0 for +nu.
+constexpr int kStapleComps = 24;
+__device__ __forceinline__ int staple_comp(int mu, int nu, int side) {
+    return (mu * 3 + (nu < mu ? nu : nu - 1)) * 2 + side;
+}
+
 // One thread per link: block b covers kBlock sites of parity par = b / (4 nb_half)
 // in the direction mu = (b / nb_half) % 4, so every load of a block's wave goes to
-// neighbouring sites of one direction.
-__global__ __launch_bounds__(kBlock) void gauge_force_sym_kernel(LatK k, const char* gauge, double* out, double coef,
-                                                                 double c0, double c1, int accumulate) {
+// neighbouring sites of one direction.  This kernel stores the six staples of U_mu(x).
+__global__ __launch_bounds__(kBlock) void staple_field_kernel(LatK k, const char* gauge, char* sig) {
     const int tile = blockIdx.x % k.nb_half;
     const int mu = (blockIdx.x / k.nb_half) & 3;
     const int par = blockIdx.x / (4 * k.nb_half);
@@ -121,47 +133,100 @@ __global__ __launch_bounds__(kBlock) void gauge_force_sym_kernel(LatK k, const c
     if (h >= k.vh) return;
     int c[4];
     coords_of(k, par, h, c);
-    const int m = mu + 1;
-    Su3<double> v, t;
+    const int zero[4] = {0, 0, 0, 0};
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        int dm[4] = {0, 0, 0, 0}, dn[4] = {0, 0, 0, 0}, dmn[4] = {0, 0, 0, 0}, dbn[4] = {0, 0, 0, 0};
+        dm[mu] = 1;
+        dn[nu] = 1;
+        dmn[mu] = 1;
+        dmn[nu] = -1;
+        dbn[nu] = -1;
+        Su3<double> a, b, t;
+        // + side: U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+        link_at(a, k, gauge, c, dm, nu);
+        link_at(b, k, gauge, c, dn, mu);
+        mat_mul_nd(t, a, b);
+        link_at(a, k, gauge, c, zero, nu);
+        mat_mul_nd(b, t, a);
+        mat_store(sig, k.gstride, kStapleComps, par, staple_comp(mu, nu, 0), h, b);
+        // - side: U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
+        link_at(a, k, gauge, c, dmn, nu);
+        link_at(b, k, gauge, c, dbn, mu);
+        mat_mul(t, b, a);                                // U_mu(x-nu) U_nu(x+mu-nu)
+        link_at(a, k, gauge, c, dbn, nu);
+        mat_mul_dn(b, t, a);
+        mat_store(sig, k.gstride, kStapleComps, par, staple_comp(mu, nu, 1), h, b);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void gauge_force_rect_kernel(LatK k, const char* gauge, const char* sig,
+                                                                  double* out, double coef, double c0, double c1,
+                                                                  int accumulate) {
+    const int tile = blockIdx.x % k.nb_half;
+    const int mu = (blockIdx.x / k.nb_half) & 3;
+    const int par = blockIdx.x / (4 * k.nb_half);
+    const int h = tile * kBlock + threadIdx.x;
+    if (h >= k.vh) return;
+    int c[4];
+    coords_of(k, par, h, c);
+    const int zero[4] = {0, 0, 0, 0};
+    int dm[4] = {0, 0, 0, 0}, dmb[4] = {0, 0, 0, 0};
+    dm[mu] = 1;
+    dmb[mu] = -1;
+    Su3<double> v;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) v.m[i][j] = {0.0, 0.0};
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu) continue;
-#pragma unroll
+        // not unrolled: unrolling lets the compiler hoist both sides' loads (256 VGPRs and
+        // AGPR spills, one wave per SIMD), which measured 20 % slower
+#pragma unroll 1
         for (int side = 0; side < 2; ++side) {
-            const int sn = side ? -(nu + 1) : nu + 1;
-            {
-                int pos[4] = {mu == 0, mu == 1, mu == 2, mu == 3};
-                const int st[3] = {sn, -m, -sn};
-                walk(t, k, gauge, c, pos, st);
-                add_scaled(v, c0, t);
+            const int comp = staple_comp(mu, nu, side);
+            Su3<double> sx, a, b, t;
+            int pp, hh;
+            mat_load(sx, sig, k.gstride, kStapleComps, par, comp, h);
+            add_scaled(v, c0, sx);
+            // U_mu(x+mu) Sigma(x+mu) Sigma(x)
+            link_at(a, k, gauge, c, dm, mu);
+            site_at(k, c, dm, pp, hh);
+            mat_load(b, sig, k.gstride, kStapleComps, pp, comp, hh);
+            mat_mul(t, a, b);
+            mat_mul(a, t, sx);
+            add_scaled(v, c1, a);
+            // Sigma(x) Sigma(x-mu) U_mu(x-mu)
+            site_at(k, c, dmb, pp, hh);
+            mat_load(b, sig, k.gstride, kStapleComps, pp, comp, hh);
+            mat_mul(t, sx, b);
+            link_at(a, k, gauge, c, dmb, mu);
+            mat_mul(b, t, a);
+            add_scaled(v, c1, b);
+            // long in nu
+            int dn[4] = {0, 0, 0, 0};
+            dn[nu] = side ? -1 : 1;
+            site_at(k, c, dn, pp, hh);
+            mat_load(b, sig, k.gstride, kStapleComps, pp, comp, hh);
+            if (side == 0) {
+                link_at(a, k, gauge, c, dm, nu);
+                mat_mul(t, a, b);
+                link_at(a, k, gauge, c, zero, nu);
+                mat_mul_nd(b, t, a);
+            } else {
+                int dmn[4] = {0, 0, 0, 0};
+                dmn[mu] = 1;
+                dmn[nu] = -1;
+                link_at(a, k, gauge, c, dmn, nu);
+                mat_mul_dn(t, a, b);
+                link_at(a, k, gauge, c, dn, nu);
+                mat_mul(b, t, a);
             }
-            if (c1 != 0.0) {
-                {
-                    int pos[4] = {mu == 0, mu == 1, mu == 2, mu == 3};
-                    const int st[5] = {m, sn, -m, -m, -sn};
-                    walk(t, k, gauge, c, pos, st);
-                    add_scaled(v, c1, t);
-                }
-                {
-                    int pos[4] = {mu == 0, mu == 1, mu == 2, mu == 3};
-                    const int st[5] = {sn, -m, -m, -sn, m};
-                    walk(t, k, gauge, c, pos, st);
-                    add_scaled(v, c1, t);
-                }
-                {
-                    int pos[4] = {mu == 0, mu == 1, mu == 2, mu == 3};
-                    const int st[5] = {sn, sn, -m, -sn, -sn};
-                    walk(t, k, gauge, c, pos, st);
-                    add_scaled(v, c1, t);
-                }
-            }
+            add_scaled(v, c1, b);
         }
     }
-    Su3<double> u;
-    const int zero[4] = {0, 0, 0, 0};
+    Su3<double> u, t;
     link_at(u, k, gauge, c, zero, mu);
     mat_mul(t, u, v);
     double g[8];
@@ -356,11 +421,24 @@ hipError_t launch_gauge_force(const Geom& g, const void* gauge, double beta, dou
     return hipGetLastError();
 }
 
+int64_t staple_field_bytes(const Geom& g) { return (int64_t)2 * kStapleComps * 9 * 16 * g.gstride; }
+
 hipError_t launch_gauge_force_sym(const Geom& g, const void* gauge, double beta, double c1, double* out, double scale,
-                                  int accumulate, hipStream_t s) {
+                                  int accumulate, void* ws, hipStream_t s) {
     const LatK k = make_latk(g);
-    hipLaunchKernelGGL(gauge_force_sym_kernel, dim3(8 * k.nb_half), dim3(kBlock), 0, s, k,
-                       static_cast<const char*>(gauge), out, scale * beta / 6.0, 1.0 - 8.0 * c1, c1, accumulate);
+    const double coef = scale * beta / 6.0;
+    if (c1 == 0.0) {   // the Wilson action: plaquette staples only
+        hipLaunchKernelGGL(gauge_force_kernel, dim3(2 * k.nb_half), dim3(kBlock), 0, s, k,
+                           static_cast<const char*>(gauge), out, coef, accumulate);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(staple_field_kernel, dim3(8 * k.nb_half), dim3(kBlock), 0, s, k, static_cast<const char*>(gauge),
+                       static_cast<char*>(ws));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gauge_force_rect_kernel, dim3(8 * k.nb_half), dim3(kBlock), 0, s, k,
+                       static_cast<const char*>(gauge), static_cast<const char*>(ws), out, coef, 1.0 - 8.0 * c1, c1,
+                       accumulate);
     return hipGetLastError();
 }
 

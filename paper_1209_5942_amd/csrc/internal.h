@@ -167,8 +167,10 @@ hipError_t launch_gauge_force(const Geom& g, const void* gauge, double beta, dou
 hipError_t launch_update_links(const Geom& g, void* gauge, const double* mom, double dt, hipStream_t s);
 hipError_t launch_plaquette(const Geom& g, const void* gauge, double* result, double* partials, hipStream_t s);
 // tree-level Symanzik gauge force (plaquettes with c0 = 1 - 8 c1, rectangles with c1) and the rectangle sum
+// (c1 != 0: ws holds staple_field_bytes(g) bytes for the single plaquette staples)
 hipError_t launch_gauge_force_sym(const Geom& g, const void* gauge, double beta, double c1, double* out, double scale,
-                                  int accumulate, hipStream_t s);
+                                  int accumulate, void* ws, hipStream_t s);
+int64_t staple_field_bytes(const Geom& g);
 hipError_t launch_rectangle(const Geom& g, const void* gauge, double* result, double* partials, hipStream_t s);
 // one heatbath (heatbath = true) or overrelaxation sweep of the Wilson plaquette action, in place on the
 // packed FP64 RECON18 links (heatbath.hip)

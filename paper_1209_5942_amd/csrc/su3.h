@@ -36,9 +36,8 @@ __device__ __forceinline__ void coords_of(const LatK& k, int par, int h, int c[4
     c[0] = 2 * xh + ((par + c[1] + c[2] + c[3]) & 1);
 }
 
-// link U_mu at the site c + d (periodic), FP64 18-real packed layout
-__device__ __forceinline__ void link_at(Su3<double>& u, const LatK& k, const char* gauge, const int c[4],
-                                        const int d[4], int mu) {
+// parity and half index of the site c + d (periodic)
+__device__ __forceinline__ void site_at(const LatK& k, const int c[4], const int d[4], int& par, int& h) {
     int q[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -46,9 +45,34 @@ __device__ __forceinline__ void link_at(Su3<double>& u, const LatK& k, const cha
         v = v < 0 ? v + k.L[i] : (v >= k.L[i] ? v - k.L[i] : v);
         q[i] = v;
     }
-    const int par = (q[0] + q[1] + q[2] + q[3]) & 1;
-    const int s = q[0] + k.L[0] * (q[1] + k.L[1] * (q[2] + k.L[2] * q[3]));
-    LinkIO<TMQCD_F64, TMQCD_RECON18>::load<false>(u, gauge, k.gstride, par, mu, s >> 1);
+    par = (q[0] + q[1] + q[2] + q[3]) & 1;
+    h = (q[0] + k.L[0] * (q[1] + k.L[1] * (q[2] + k.L[2] * q[3]))) >> 1;
+}
+
+// link U_mu at the site c + d (periodic), FP64 18-real packed layout
+__device__ __forceinline__ void link_at(Su3<double>& u, const LatK& k, const char* gauge, const int c[4],
+                                        const int d[4], int mu) {
+    int par, h;
+    site_at(k, c, d, par, h);
+    LinkIO<TMQCD_F64, TMQCD_RECON18>::load<false>(u, gauge, k.gstride, par, mu, h);
+}
+
+// a field of ncomp SU(3)-shaped matrices per site in the 18-real link layout
+// (component comp of the site (par, h) at ((par * ncomp + comp) * 9 + k) * gstride + h)
+__device__ __forceinline__ void mat_load(Su3<double>& u, const char* base, int64_t gstride, int ncomp, int par,
+                                         int comp, int h) {
+    const double2* p = reinterpret_cast<const double2*>(base) + (int64_t)((par * ncomp + comp) * 9) * gstride + h;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double2 w = p[k * gstride];
+        u.m[k / 3][k % 3] = {w.x, w.y};
+    }
+}
+__device__ __forceinline__ void mat_store(char* base, int64_t gstride, int ncomp, int par, int comp, int h,
+                                          const Su3<double>& u) {
+    double2* p = reinterpret_cast<double2*>(base) + (int64_t)((par * ncomp + comp) * 9) * gstride + h;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) p[k * gstride] = make_double2(u.m[k / 3][k % 3].re, u.m[k / 3][k % 3].im);
 }
 
 __device__ __forceinline__ void mat_mul(Su3<double>& r, const Su3<double>& a, const Su3<double>& b) {

@@ -113,6 +113,7 @@ class HMC:
         self.ws_dslash = T.workspace(prob, self.op, 1)
         self.ws_aux = T.aux_workspace(prob)
         self.ws_force = T._bytes(T.force_eo_workspace_bytes(prob), dev) if eo else None
+        self.ws_gauge = T._bytes(T.gauge_force_tlsym_workspace_bytes(prob), dev) if c1 != 0.0 else None
         self.X = torch.empty(fb, dtype=torch.uint8, device=dev)
         self.Y = torch.empty(fb, dtype=torch.uint8, device=dev)
         self.phi = torch.empty(fb, dtype=torch.uint8, device=dev)
@@ -166,7 +167,8 @@ class HMC:
         if self.beta == 0.0:
             return
         if self.c1 != 0.0:
-            T.gauge_force_tlsym(self.prob, self.U, self.beta, self.c1, out=p, scale=scale, accumulate=True)
+            T.gauge_force_tlsym(self.prob, self.U, self.beta, self.c1, out=p, scale=scale, accumulate=True,
+                                ws=self.ws_gauge)
         else:
             T.gauge_force(self.prob, self.U, self.beta, out=p, scale=scale, accumulate=True)
 

@@ -30,7 +30,7 @@ ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_byte
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg",
                 "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_bicgstab_workspace_bytes",
                 "tmqcd_bicgstab", "tmqcd_force", "tmqcd_force_eo_workspace_bytes", "tmqcd_force_eo",
-                "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle", "tmqcd_heatbath",
+                "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym_workspace_bytes", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle", "tmqcd_heatbath",
                 "tmqcd_overrelax", "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune",
                 "tmqcd_tune_save", "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set",
                 "tmqcd_tune_mrhs_workspace_bytes", "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2",
@@ -106,7 +106,8 @@ def lib():
             "tmqcd_force_eo_workspace_bytes": (S, [P]),
             "tmqcd_force_eo": (I, [P, V, I, V, V, D, I, V, S, V]),
             "tmqcd_gauge_force": (I, [P, V, D, V, D, I, V]),
-            "tmqcd_gauge_force_tlsym": (I, [P, V, D, D, V, D, I, V]),
+            "tmqcd_gauge_force_tlsym_workspace_bytes": (S, [P]),
+            "tmqcd_gauge_force_tlsym": (I, [P, V, D, D, V, D, I, V, S, V]),
             "tmqcd_rectangle": (I, [P, V, V, V, S, V]),
             "tmqcd_heatbath": (I, [P, V, D, ctypes.c_uint64, ctypes.c_uint32, V]),
             "tmqcd_overrelax": (I, [P, V, V]),
@@ -407,12 +408,20 @@ def gauge_force(prob: Problem, U_packed, beta, out=None, scale=1.0, accumulate=F
     return out
 
 
-def gauge_force_tlsym(prob: Problem, U_packed, beta, c1, out=None, scale=1.0, accumulate=False, stream=None):
+def gauge_force_tlsym_workspace_bytes(prob: Problem) -> int:
+    return lib().tmqcd_gauge_force_tlsym_workspace_bytes(ctypes.byref(prob.c()))
+
+
+def gauge_force_tlsym(prob: Problem, U_packed, beta, c1, out=None, scale=1.0, accumulate=False, ws=None, stream=None):
     """scale * dS_g/dw^a of the tree-level Symanzik action with rectangle coefficient c1, c0 = 1 - 8 c1
-    (FP64 RECON18 links)."""
+    (FP64 RECON18 links); ws: the staple-field workspace (allocated when None and c1 != 0)."""
     out = _mom(prob, out, U_packed)
+    if ws is None and c1 != 0:
+        ws = _bytes(gauge_force_tlsym_workspace_bytes(prob), U_packed.device)
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().tmqcd_gauge_force_tlsym(ctypes.byref(prob.c()), _ptr(U_packed), float(beta), float(c1), _ptr(out),
-                                         float(scale), int(accumulate), _stream(stream)), "tmqcd_gauge_force_tlsym")
+                                         float(scale), int(accumulate), _ptr(ws), nbytes, _stream(stream)),
+           "tmqcd_gauge_force_tlsym")
     return out
 
 

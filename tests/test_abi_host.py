@@ -165,13 +165,23 @@ def test_force_eo_argument_errors(L):
 def test_tlsym_and_rectangle_argument_errors(L):
     prob = T.Problem((4, 4, 4, 4), 0.15, 0.01)
     p = ctypes.byref(prob.c())
-    U, out = 1 << 30, 1 << 34
-    assert L.tmqcd_gauge_force_tlsym(p, None, 5.0, -1 / 12, out, 1.0, 0, None) == T.EINVAL
-    assert L.tmqcd_gauge_force_tlsym(p, U, 5.0, float("nan"), out, 1.0, 0, None) == T.EINVAL
-    assert L.tmqcd_gauge_force_tlsym(p, U, float("inf"), -1 / 12, out, 1.0, 0, None) == T.EINVAL
-    assert L.tmqcd_gauge_force_tlsym(p, U, 5.0, -1 / 12, out, 1.0, 3, None) == T.EINVAL
-    assert L.tmqcd_gauge_force_tlsym(p, U + 16, 5.0, -1 / 12, out, 1.0, 0, None) == T.EALIGN
-    assert L.tmqcd_gauge_force_tlsym(p, U, 5.0, -1 / 12, U, 1.0, 0, None) == T.EALIAS
+    U, out, w = 1 << 30, 1 << 34, 1 << 36
+    need = L.tmqcd_gauge_force_tlsym_workspace_bytes(p)
+    assert need == 3456 * prob.volume
+
+    def call(U=U, beta=5.0, c1=-1 / 12, out=out, acc=0, ws=w, wsb=need):
+        return L.tmqcd_gauge_force_tlsym(p, U, beta, c1, out, 1.0, acc, ws, wsb, None)
+    assert call(U=None) == T.EINVAL
+    assert call(c1=float("nan")) == T.EINVAL
+    assert call(beta=float("inf")) == T.EINVAL
+    assert call(acc=3) == T.EINVAL
+    assert call(U=U + 16) == T.EALIGN
+    assert call(out=U) == T.EALIAS
+    assert call(ws=None) == T.EWORKSPACE
+    assert call(wsb=need - 1) == T.EWORKSPACE
+    assert call(ws=w + 16) == T.EALIGN
+    assert call(ws=U) == T.EALIAS
+    assert call(ws=out) == T.EALIAS
     ws = T.workspace_bytes(prob, -1, 1, 1)
     assert L.tmqcd_rectangle(p, None, out, 1 << 36, ws, None) == T.EINVAL
     assert L.tmqcd_rectangle(p, U, out, 1 << 36, 8, None) == T.EWORKSPACE
