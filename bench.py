@@ -296,30 +296,35 @@ def main():
         for k in ("mixed_f32", "mixed_f16"):
             mixed[k]["speedup_vs_fp64"] = round(mixed["fp64"]["ms"] / mixed[k]["ms"], 3)
         mixed["workload"] = "Mhat^dag Mhat, 32^3x64, kappa 0.162, mu 0.003, eps 0.5, tol 1e-10 (FP64 true residual)"
-        # the same solves with 12-real links (the paper's compression) in every precision
-        Um = torch.from_numpy(Um_host).to(dev)
-        g12 = {p: T.pack_gauge(pm, Um, p, 1) for p in (T.F64, T.F32, T.F16)}
-        del Um
-        rec12 = {}
-        for p, name in ((T.F64, "fp64"), (T.F32, "mixed_f32"), (T.F16, "mixed_f16")):
-            T.tune(pm, g12[p], p, 1)
-        for p, name in ((T.F64, "fp64"), (T.F32, "mixed_f32"), (T.F16, "mixed_f16")):
-            best = None
-            for _ in range(3):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, st, _ = T.cg(pm, g12, bm, xm, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT,
-                                inner_prec=p, recon=1, ws=wsm, check_every=16)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                if best is None or dt < best[0]:
-                    best = (dt, st)
-            dt, st = best
-            rec12[name] = {"ms": round(1e3 * dt, 2), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
-                           "true_rel_residual": st["true_rel_residual"], "converged": st["converged"],
-                           "speedup_vs_fp64_rec18": round(mixed["fp64"]["ms"] / (1e3 * dt), 3)}
-        mixed["rec12"] = rec12
-        del g12
+        # the same solves with compressed links (REC12, REC10, REC8) in every precision; the FP16-inner
+        # REC8 solution is kept for an oracle check
+        xr8 = torch.empty_like(xm)
+        for rec, rname in ((1, "rec12"), (2, "rec10"), (3, "rec8")):
+            Um = torch.from_numpy(Um_host).to(dev)
+            gr = {p: T.pack_gauge(pm, Um, p, rec) for p in (T.F64, T.F32, T.F16)}
+            del Um
+            for p in (T.F64, T.F32, T.F16):
+                T.tune(pm, gr[p], p, rec)
+            res = {}
+            for p, name in ((T.F64, "fp64"), (T.F32, "mixed_f32"), (T.F16, "mixed_f16")):
+                out_x = xr8 if (rec == 3 and p == T.F16) else xm
+                best = None
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, st, _ = T.cg(pm, gr, bm, out_x, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT,
+                                    inner_prec=p, recon=rec, ws=wsm, check_every=16)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    if best is None or dt < best[0]:
+                        best = (dt, st)
+                dt, st = best
+                res[name] = {"ms": round(1e3 * dt, 2), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
+                             "true_rel_residual": st["true_rel_residual"], "converged": st["converged"],
+                             "speedup_vs_fp64_rec18": round(mixed["fp64"]["ms"] / (1e3 * dt), 3)}
+                log(f"32^3x64 {rname} {name}: {1e3 * dt:.1f} ms, {st['iters']} iters")
+            mixed[rname] = res
+            del gr
         # the REC18 FP16-inner solution again, for the oracle check below
         T.cg(pm, gm, bm, xm, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT, inner_prec=T.F16, ws=wsm,
              check_every=16)
@@ -330,7 +335,9 @@ def main():
             xs = T.unpack_spinor(pm, xm, T.F64, T.EVEN).cpu().numpy()
             Am = lambda v: D.apply_MhatdagMhat(Um_host, v, m["dims"], m["kappa"], m["mu"], (1, 1, 1, -1))
             mixed["mixed_f16"]["oracle_rel_residual"] = D.true_rel_residual(Am, bm_host, xs)
-        del gm, bm, xm, wsm, Um_host
+            xs8 = T.unpack_spinor(pm, xr8, T.F64, T.EVEN).cpu().numpy()
+            mixed["rec8"]["mixed_f16"]["oracle_rel_residual"] = D.true_rel_residual(Am, bm_host, xs8)
+        del gm, bm, xm, xr8, wsm, Um_host
 
     if not args.no_extras:
         result["small_4x4x4x4"] = bench_small(T, synth, dev, not args.no_oracle)
