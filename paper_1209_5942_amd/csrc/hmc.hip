@@ -17,6 +17,7 @@
 #include "device.h"
 #include "internal.h"
 #include "su3.h"
+#include "stencil.h"
 
 namespace tmqcd {
 namespace {
@@ -33,11 +34,12 @@ __device__ __forceinline__ void im_tr_lambda(const Su3<double>& q, double g[8]) 
     g[7] = (q.m[0][0].im + q.m[1][1].im - 2.0 * q.m[2][2].im) * 0.57735026918962576451;
 }
 
-__global__ __launch_bounds__(kBlock) void gauge_force_kernel(LatK k, const char* gauge, double* out, double coef,
-                                                             int accumulate) {
-    const int par = blockIdx.x >= (unsigned)k.nb_half ? 1 : 0;
-    const int h = (blockIdx.x - par * k.nb_half) * kBlock + threadIdx.x;
-    if (h >= k.vh) return;
+// one thread per site (four directions); map: the t-slab block order (20 % faster than consecutive
+// blocks at 24^3 x 48)
+__global__ __launch_bounds__(kBlock) void gauge_force_kernel(LatK k, stencil::HopK map, const char* gauge,
+                                                             double* out, double coef, int accumulate) {
+    int par, h;
+    if (!stencil::block_site(map, blockIdx.x, threadIdx.x, par, h)) return;
     int c[4];
     coords_of(k, par, h, c);
     const int64_t s = 2 * (int64_t)h + (c[0] & 1);
@@ -122,15 +124,14 @@ __device__ __forceinline__ int staple_comp(int mu, int nu, int side) {
     return (mu * 3 + (nu < mu ? nu : nu - 1)) * 2 + side;
 }
 
-// One thread per link: block b covers kBlock sites of parity par = b / (4 nb_half)
-// in the direction mu = (b / nb_half) % 4, so every load of a block's wave goes to
+// One thread per link: blockIdx.y is the direction mu and blockIdx.x covers kBlock sites in
+// the hop's t-slab order (each XCD walks its eighth of every t-slice through all t, so the
+// links around the next slice are in its L2 already), so every load of a block's wave goes to
 // neighbouring sites of one direction.  This kernel stores the six staples of U_mu(x).
-__global__ __launch_bounds__(kBlock) void staple_field_kernel(LatK k, const char* gauge, char* sig) {
-    const int tile = blockIdx.x % k.nb_half;
-    const int mu = (blockIdx.x / k.nb_half) & 3;
-    const int par = blockIdx.x / (4 * k.nb_half);
-    const int h = tile * kBlock + threadIdx.x;
-    if (h >= k.vh) return;
+__global__ __launch_bounds__(kBlock) void staple_field_kernel(LatK k, stencil::HopK map, const char* gauge, char* sig) {
+    const int mu = blockIdx.y;
+    int par, h;
+    if (!stencil::block_site(map, blockIdx.x, threadIdx.x, par, h)) return;
     int c[4];
     coords_of(k, par, h, c);
     const int zero[4] = {0, 0, 0, 0};
@@ -160,14 +161,12 @@ __global__ __launch_bounds__(kBlock) void staple_field_kernel(LatK k, const char
     }
 }
 
-__global__ __launch_bounds__(kBlock) void gauge_force_rect_kernel(LatK k, const char* gauge, const char* sig,
+__global__ __launch_bounds__(kBlock) void gauge_force_rect_kernel(LatK k, stencil::HopK map, const char* gauge, const char* sig,
                                                                   double* out, double coef, double c0, double c1,
                                                                   int accumulate) {
-    const int tile = blockIdx.x % k.nb_half;
-    const int mu = (blockIdx.x / k.nb_half) & 3;
-    const int par = blockIdx.x / (4 * k.nb_half);
-    const int h = tile * kBlock + threadIdx.x;
-    if (h >= k.vh) return;
+    const int mu = blockIdx.y;
+    int par, h;
+    if (!stencil::block_site(map, blockIdx.x, threadIdx.x, par, h)) return;
     int c[4];
     coords_of(k, par, h, c);
     const int zero[4] = {0, 0, 0, 0};
@@ -415,8 +414,15 @@ int64_t aux_partials_doubles(const Geom& g) {
 hipError_t launch_gauge_force(const Geom& g, const void* gauge, double beta, double* out, double scale, int accumulate,
                               hipStream_t s) {
     const LatK k = make_latk(g);
+    HopParams hp{};
+    hp.g = g;
+    hp.prec = hp.vprec = TMQCD_F64;
+    hp.nparity = 2;
+    hp.nrhs = 1;
+    hp.order = kOrderSlab;
+    const stencil::HopK map = stencil::make_hopk(hp, kBlock);
     // G^a = (beta/3) Im Tr[T^a U V] = (beta/6) Im Tr[lambda^a U V]
-    hipLaunchKernelGGL(gauge_force_kernel, dim3(2 * k.nb_half), dim3(kBlock), 0, s, k,
+    hipLaunchKernelGGL(gauge_force_kernel, dim3(map.nblocks), dim3(kBlock), 0, s, k, map,
                        static_cast<const char*>(gauge), out, scale * beta / 6.0, accumulate);
     return hipGetLastError();
 }
@@ -427,16 +433,23 @@ hipError_t launch_gauge_force_sym(const Geom& g, const void* gauge, double beta,
                                   int accumulate, void* ws, hipStream_t s) {
     const LatK k = make_latk(g);
     const double coef = scale * beta / 6.0;
+    HopParams hp{};
+    hp.g = g;
+    hp.prec = hp.vprec = TMQCD_F64;
+    hp.nparity = 2;
+    hp.nrhs = 1;
+    hp.order = kOrderSlab;
+    const stencil::HopK map = stencil::make_hopk(hp, kBlock);
     if (c1 == 0.0) {   // the Wilson action: plaquette staples only
-        hipLaunchKernelGGL(gauge_force_kernel, dim3(2 * k.nb_half), dim3(kBlock), 0, s, k,
+        hipLaunchKernelGGL(gauge_force_kernel, dim3(map.nblocks), dim3(kBlock), 0, s, k, map,
                            static_cast<const char*>(gauge), out, coef, accumulate);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(staple_field_kernel, dim3(8 * k.nb_half), dim3(kBlock), 0, s, k, static_cast<const char*>(gauge),
-                       static_cast<char*>(ws));
+    hipLaunchKernelGGL(staple_field_kernel, dim3(map.nblocks, 4), dim3(kBlock), 0, s, k, map,
+                       static_cast<const char*>(gauge), static_cast<char*>(ws));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gauge_force_rect_kernel, dim3(8 * k.nb_half), dim3(kBlock), 0, s, k,
+    hipLaunchKernelGGL(gauge_force_rect_kernel, dim3(map.nblocks, 4), dim3(kBlock), 0, s, k, map,
                        static_cast<const char*>(gauge), static_cast<const char*>(ws), out, coef, 1.0 - 8.0 * c1, c1,
                        accumulate);
     return hipGetLastError();
