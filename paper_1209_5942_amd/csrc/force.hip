@@ -9,7 +9,8 @@
 //   Q1 = sum_spin [(1 - gamma_mu) U X(x+mu)] (x) Y(x)^+
 //   Q2 = sum_spin X(x) (x) [U (1 + gamma_mu) Y(x+mu)]^+
 // One thread per (site, direction); each output is written once, so no
-// atomics are needed.  The spin projectors are applied as in the hop.
+// atomics are needed.  The spin projectors are applied as in the hop, and the
+// rank-2 projectors halve the spin sums of Q1 and Q2 (see project below).
 #include "device.h"
 #include "internal.h"
 
@@ -20,10 +21,12 @@ constexpr int kPerm[4][2] = {{1, 0}, {1, 0}, {0, 1}, {0, 1}};
 constexpr int kB[4][2] = {{3, 3}, {2, 0}, {3, 1}, {2, 2}};
 constexpr int kBd[4][2] = {{1, 1}, {0, 2}, {1, 3}, {2, 2}};
 
-// (1 + eps gamma_mu) U v = [g ; eps B^+ g] with g = U (v_up + eps B v_dn)
+// The rows of (1 + eps gamma_mu) v: h = v_up + eps B v_dn (the lower two rows are
+// eps B^+ h).  In the chiral basis (1 + eps gamma_mu) = R P with P = [1, eps B] and
+// R^+ = P, so for any a, b:  sum_spin [(1 + eps gamma_mu) a] (x) b^+ = sum_{r=0,1} (P a)_r (x) (P b)_r^+,
+// which halves the outer products of Q1 and Q2.
 template <int MU, int EPS>
-__device__ __forceinline__ void proj_mul(Spinor<double>& out, const Su3<double>& u, const Spinor<double>& v) {
-    Half<double> h;
+__device__ __forceinline__ void project(Half<double>& h, const Spinor<double>& v) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int src = 2 + kPerm[MU][r];
@@ -41,28 +44,15 @@ __device__ __forceinline__ void proj_mul(Spinor<double>& out, const Su3<double>&
             h.s[r][c] = v.s[r][c] + bz;
         }
     }
+}
+
+// g = U h on both rows
+__device__ __forceinline__ void umul(Half<double>& g, const Su3<double>& u, const Half<double>& h) {
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            out.s[r][a] = u.m[a][0] * h.s[r][0] + u.m[a][1] * h.s[r][1] + u.m[a][2] * h.s[r][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int src = kPerm[MU][r];
-        const int code = (kBd[MU][r] + (EPS > 0 ? 0 : 2)) & 3;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const C<double> z = out.s[src][c];
-            C<double> bz;
-            switch (code) {
-                case 0: bz = z; break;
-                case 1: bz = {-z.im, z.re}; break;
-                case 2: bz = {-z.re, -z.im}; break;
-                default: bz = {z.im, -z.re}; break;
-            }
-            out.s[2 + r][c] = bz;
-        }
-    }
+            g.s[r][a] = u.m[a][0] * h.s[r][0] + u.m[a][1] * h.s[r][1] + u.m[a][2] * h.s[r][2];
 }
 
 struct ForceK {
@@ -86,11 +76,17 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
     const char* Yn = a.Y[1 - par];
     Su3<double> u;
     LinkIO<TMQCD_F64, R>::template load<true>(u, a.gauge, a.gstride, par, MU, h);
-    Spinor<double> xn, yn, v1, v2;
+    Spinor<double> xn, yn;
     SpinorIO<TMQCD_F64>::load(xn, Xn, a.stride, nh);
     SpinorIO<TMQCD_F64>::load(yn, Yn, a.stride, nh);
-    proj_mul<MU, -1>(v1, u, xn);   // (1 - gamma_mu) U X(x+mu)
-    proj_mul<MU, +1>(v2, u, yn);   // U (1 + gamma_mu) Y(x+mu)
+    // Q1 = sum_r [U P- X(x+mu)]_r (x) [P- Y(x)]_r^+,  Q2 = sum_r [P+ X(x)]_r (x) [U P+ Y(x+mu)]_r^+
+    Half<double> hh, g1, g2, z1, z2;
+    project<MU, -1>(hh, xn);
+    umul(g1, u, hh);
+    project<MU, +1>(hh, yn);
+    umul(g2, u, hh);
+    project<MU, -1>(z1, yo);
+    project<MU, +1>(z2, xo);
     C<double> b = cross ? a.bc[MU] : C<double>{1.0, 0.0};
     C<double> q[3][3];
 #pragma unroll
@@ -99,9 +95,9 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
         for (int j = 0; j < 3; ++j) {
             C<double> q1 = {0, 0}, q2 = {0, 0};
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                q1 = q1 + cmul_cj(yo.s[s][j], v1.s[s][i]);   // v1_i conj(Y_j)
-                q2 = q2 + cmul_cj(v2.s[s][j], xo.s[s][i]);   // X_i conj(v2_j)
+            for (int r = 0; r < 2; ++r) {
+                q1 = q1 + cmul_cj(z1.s[r][j], g1.s[r][i]);   // g1_i conj(z1_j)
+                q2 = q2 + cmul_cj(g2.s[r][j], z2.s[r][i]);   // z2_i conj(g2_j)
             }
             q[i][j] = b * q1 - conj(b) * q2;
         }
@@ -119,7 +115,8 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
 
 // A block covers 64 sites and its wave w computes direction w (a wave-uniform
 // branch), so each thread holds one direction's operands; the four waves read
-// the same X(x), Y(x) (cache hits after the first).  Launch bounds ask for two
+// the same X(x), Y(x) (cache hits after the first; staging them in LDS once per
+// block measured 3 % slower).  Launch bounds ask for two
 // waves per SIMD (at most 256 registers; the kernel does not spill).  Holding
 // all four directions per thread needed 260 registers, one wave per SIMD, and
 // ran 14 % slower.
