@@ -481,7 +481,22 @@ def bench_heatbath(T, synth, dev):
         links = 4 * prob.volume
         sweep_bytes = 5184 * prob.volume
         plaq = float(T.plaquette(prob, g)[0]) / (18 * prob.volume)
+        # the same sweeps on FP32 links with FP32 arithmetic (the precision of the paper's measurement):
+        # 2592 algorithmic bytes per site and sweep
+        g32 = T.pack_gauge(prob, T.unpack_gauge(prob, g), T.F32)
+        counter32 = iter(range(10 ** 6))
+        t_hb32 = _events_time(lambda: T.heatbath(prob, g32, 5.7, 93, next(counter32), prec=T.F32), 10)
+        t_or32 = _events_time(lambda: T.overrelax(prob, g32, prec=T.F32), 10)
+        del g32
+        fp32 = {"heatbath_ms": round(t_hb32 * 1e3, 3), "overrelax_ms": round(t_or32 * 1e3, 3),
+                "heatbath_Glinks_s": round(links / t_hb32 / 1e9, 3), "overrelax_Glinks_s": round(links / t_or32 / 1e9, 3),
+                "heatbath_TFLOP_s_paper_count": round(links * 3912 / t_hb32 / 1e12, 2),
+                "overrelax_TFLOP_s_paper_count": round(links * 3846 / t_or32 / 1e12, 2),
+                "roofline_heatbath": {"bound": "hbm", "achieved": round(2592 * prob.volume / t_hb32 / 1e9, 1),
+                                      "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                                      "frac": round(2592 * prob.volume / t_hb32 / 1e9 / PEAK_HBM_GBPS, 4)}}
         out["x".join(map(str, dims))] = {
+            "fp32": fp32,
             "heatbath_ms": round(t_hb * 1e3, 3), "overrelax_ms": round(t_or * 1e3, 3),
             "heatbath_Glinks_s": round(links / t_hb / 1e9, 3), "overrelax_Glinks_s": round(links / t_or / 1e9, 3),
             "heatbath_TFLOP_s_paper_count": round(links * 3912 / t_hb / 1e12, 2),
@@ -493,7 +508,8 @@ def bench_heatbath(T, synth, dev):
                                    "frac": round(sweep_bytes / t_or / 1e9 / PEAK_HBM_GBPS, 4)},
             "plaquette_after": round(plaq, 5)}
         del g
-    out["setup"] = "FP64 RECON18 links, Wilson action beta 5.7 from the eps 0.4 start; 3 sweeps before timing"
+    out["setup"] = ("FP64 RECON18 links (and FP32 links with FP32 arithmetic under fp32), Wilson action beta 5.7 "
+                    "from the eps 0.4 start; 3 sweeps before timing")
     return out
 
 

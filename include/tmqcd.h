@@ -286,7 +286,9 @@ int tmqcd_update_links(const tmqcd_problem* prob, void* U_packed, const double* 
                        void* stream);
 /* ---- pure-gauge updates (the paper's heatbath section) ---------------------- */
 /* One sweep over all links of the Wilson plaquette action
- * S = (beta/3) sum (3 - Re Tr P), in place on the packed FP64 RECON18 links:
+ * S = (beta/3) sum (3 - Re Tr P), in place on the packed RECON18 links of
+ * precision prec (TMQCD_F64, or TMQCD_F32 with FP32 arithmetic, the precision
+ * in which the paper measures its heatbath):
  * direction by direction and parity by parity (8 launches; the links of one
  * direction and parity do not appear in each other's staples), each link
  * updated through the SU(2) subgroups (0,1), (0,2), (1,2) (Cabibbo-Marinari).
@@ -298,11 +300,12 @@ int tmqcd_update_links(const tmqcd_problem* prob, void* U_packed, const double* 
  *                    pure function of (links, beta, seed, sweep).
  *   tmqcd_overrelax: the microcanonical reflection r = (s^+)^2 in each
  *                    subgroup (no random numbers; keeps the action).
- * Errors: TMQCD_EINVAL (bad problem, null links, beta negative or not finite,
- * more than 2^32 links), TMQCD_EALIGN; TMQCD_EHIP if a launch fails. */
-int tmqcd_heatbath(const tmqcd_problem* prob, void* U_packed, double beta, uint64_t seed, uint32_t sweep,
+ * Errors: TMQCD_EINVAL (bad problem, null links, prec not FP64/FP32, beta
+ * negative or not finite, more than 2^32 links), TMQCD_EALIGN; TMQCD_EHIP if a
+ * launch fails. */
+int tmqcd_heatbath(const tmqcd_problem* prob, void* U_packed, int prec, double beta, uint64_t seed, uint32_t sweep,
                    void* stream);
-int tmqcd_overrelax(const tmqcd_problem* prob, void* U_packed, void* stream);
+int tmqcd_overrelax(const tmqcd_problem* prob, void* U_packed, int prec, void* stream);
 
 /* Deterministic FP64 reductions into device memory.  ws: tmqcd_workspace_bytes(prob, -1, 1, 1) bytes.
  *   tmqcd_plaquette:      result[0] = sum_{x, mu<nu} Re Tr P_mu_nu(x)       (U_packed FP64 RECON18)

@@ -359,20 +359,22 @@ int tmqcd_gauge_force_tlsym(const tmqcd_problem* prob, const void* U_packed, dou
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
-int tmqcd_heatbath(const tmqcd_problem* prob, void* U_packed, double beta, uint64_t seed, uint32_t sweep,
+int tmqcd_heatbath(const tmqcd_problem* prob, void* U_packed, int prec, double beta, uint64_t seed, uint32_t sweep,
                    void* stream) {
-    if (!valid_problem(prob) || !U_packed || !std::isfinite(beta) || beta < 0.0) return TMQCD_EINVAL;
+    if (!valid_problem(prob) || !U_packed || (prec != TMQCD_F64 && prec != TMQCD_F32) || !std::isfinite(beta) ||
+        beta < 0.0)
+        return TMQCD_EINVAL;
     if (!aligned(U_packed, kAlignBytes)) return TMQCD_EALIGN;
     const Geom g = make_geom(*prob);
     if (4 * 2 * g.vh > 0xFFFFFFFFll) return TMQCD_EINVAL;   // generator counters are 32-bit link ids
-    const hipError_t e = launch_su3_sweep(g, U_packed, beta, seed, sweep, true, (hipStream_t)stream);
+    const hipError_t e = launch_su3_sweep(g, U_packed, prec, beta, seed, sweep, true, (hipStream_t)stream);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
-int tmqcd_overrelax(const tmqcd_problem* prob, void* U_packed, void* stream) {
-    if (!valid_problem(prob) || !U_packed) return TMQCD_EINVAL;
+int tmqcd_overrelax(const tmqcd_problem* prob, void* U_packed, int prec, void* stream) {
+    if (!valid_problem(prob) || !U_packed || (prec != TMQCD_F64 && prec != TMQCD_F32)) return TMQCD_EINVAL;
     if (!aligned(U_packed, kAlignBytes)) return TMQCD_EALIGN;
-    const hipError_t e = launch_su3_sweep(make_geom(*prob), U_packed, 0.0, 0, 0, false, (hipStream_t)stream);
+    const hipError_t e = launch_su3_sweep(make_geom(*prob), U_packed, prec, 0.0, 0, 0, false, (hipStream_t)stream);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 

@@ -173,9 +173,9 @@ hipError_t launch_gauge_force_sym(const Geom& g, const void* gauge, double beta,
 int64_t staple_field_bytes(const Geom& g);
 hipError_t launch_rectangle(const Geom& g, const void* gauge, double* result, double* partials, hipStream_t s);
 // one heatbath (heatbath = true) or overrelaxation sweep of the Wilson plaquette action, in place on the
-// packed FP64 RECON18 links (heatbath.hip)
-hipError_t launch_su3_sweep(const Geom& g, void* gauge, double beta, uint64_t seed, uint32_t sweep, bool heatbath,
-                            hipStream_t s);
+// packed RECON18 links of precision prec (FP64 or FP32; heatbath.hip)
+hipError_t launch_su3_sweep(const Geom& g, void* gauge, int prec, double beta, uint64_t seed, uint32_t sweep,
+                            bool heatbath, hipStream_t s);
 hipError_t launch_mom_norm2(const Geom& g, const double* mom, double* result, double* partials, hipStream_t s);
 hipError_t launch_spinor_dot(const Geom& g, const void* x, const void* y, int nhalf, double* result, double* partials,
                              hipStream_t s);

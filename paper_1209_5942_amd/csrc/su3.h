@@ -49,12 +49,14 @@ __device__ __forceinline__ void site_at(const LatK& k, const int c[4], const int
     h = (q[0] + k.L[0] * (q[1] + k.L[1] * (q[2] + k.L[2] * q[3]))) >> 1;
 }
 
-// link U_mu at the site c + d (periodic), FP64 18-real packed layout
-__device__ __forceinline__ void link_at(Su3<double>& u, const LatK& k, const char* gauge, const int c[4],
+// link U_mu at the site c + d (periodic), 18-real packed layout of storage precision P
+// (FP64 by default; FP32 links load into Su3<float>)
+template <int P = TMQCD_F64>
+__device__ __forceinline__ void link_at(Su3<typename Prec<P>::T>& u, const LatK& k, const char* gauge, const int c[4],
                                         const int d[4], int mu) {
     int par, h;
     site_at(k, c, d, par, h);
-    LinkIO<TMQCD_F64, TMQCD_RECON18>::load<false>(u, gauge, k.gstride, par, mu, h);
+    LinkIO<P, TMQCD_RECON18>::template load<false>(u, gauge, k.gstride, par, mu, h);
 }
 
 // a field of ncomp SU(3)-shaped matrices per site in the 18-real link layout
@@ -75,14 +77,16 @@ __device__ __forceinline__ void mat_store(char* base, int64_t gstride, int ncomp
     for (int k = 0; k < 9; ++k) p[k * gstride] = make_double2(u.m[k / 3][k % 3].re, u.m[k / 3][k % 3].im);
 }
 
-__device__ __forceinline__ void mat_mul(Su3<double>& r, const Su3<double>& a, const Su3<double>& b) {
+template <typename T>
+__device__ __forceinline__ void mat_mul(Su3<T>& r, const Su3<T>& a, const Su3<T>& b) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) r.m[i][j] = a.m[i][0] * b.m[0][j] + a.m[i][1] * b.m[1][j] + a.m[i][2] * b.m[2][j];
 }
 // a * b^+
-__device__ __forceinline__ void mat_mul_nd(Su3<double>& r, const Su3<double>& a, const Su3<double>& b) {
+template <typename T>
+__device__ __forceinline__ void mat_mul_nd(Su3<T>& r, const Su3<T>& a, const Su3<T>& b) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -90,7 +94,8 @@ __device__ __forceinline__ void mat_mul_nd(Su3<double>& r, const Su3<double>& a,
             r.m[i][j] = cmul_cj(b.m[j][0], a.m[i][0]) + cmul_cj(b.m[j][1], a.m[i][1]) + cmul_cj(b.m[j][2], a.m[i][2]);
 }
 // a^+ * b
-__device__ __forceinline__ void mat_mul_dn(Su3<double>& r, const Su3<double>& a, const Su3<double>& b) {
+template <typename T>
+__device__ __forceinline__ void mat_mul_dn(Su3<T>& r, const Su3<T>& a, const Su3<T>& b) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -100,14 +105,16 @@ __device__ __forceinline__ void mat_mul_dn(Su3<double>& r, const Su3<double>& a,
 
 // V_mu(x): the six Wilson staples of U_mu(x), so that the plaquettes through the
 // link sum to Re Tr[U_mu(x) V_mu(x)]
-__device__ __forceinline__ void staple_sum_at(Su3<double>& v, const LatK& k, const char* gauge, const int c[4],
-                                              int mu) {
+template <int P = TMQCD_F64>
+__device__ __forceinline__ void staple_sum_at(Su3<typename Prec<P>::T>& v, const LatK& k, const char* gauge,
+                                              const int c[4], int mu) {
+    using T = typename Prec<P>::T;
     const int zero[4] = {0, 0, 0, 0};
-    Su3<double> a, b, t;
+    Su3<T> a, b, t;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) v.m[i][j] = {0.0, 0.0};
+        for (int j = 0; j < 3; ++j) v.m[i][j] = {T(0), T(0)};
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu) continue;
         int dm[4] = {0, 0, 0, 0}, dn[4] = {0, 0, 0, 0}, dmn[4] = {0, 0, 0, 0}, dmn2[4] = {0, 0, 0, 0};
@@ -117,20 +124,20 @@ __device__ __forceinline__ void staple_sum_at(Su3<double>& v, const LatK& k, con
         dmn[nu] = -1;
         dmn2[nu] = -1;
         // U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
-        link_at(a, k, gauge, c, dm, nu);
-        link_at(b, k, gauge, c, dn, mu);
+        link_at<P>(a, k, gauge, c, dm, nu);
+        link_at<P>(b, k, gauge, c, dn, mu);
         mat_mul_nd(t, a, b);
-        link_at(a, k, gauge, c, zero, nu);
+        link_at<P>(a, k, gauge, c, zero, nu);
         mat_mul_nd(b, t, a);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) v.m[i][j] = v.m[i][j] + b.m[i][j];
         // U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
-        link_at(a, k, gauge, c, dmn, nu);
-        link_at(b, k, gauge, c, dmn2, mu);
+        link_at<P>(a, k, gauge, c, dmn, nu);
+        link_at<P>(b, k, gauge, c, dmn2, mu);
         mat_mul(t, b, a);                          // U_mu(x-nu) U_nu(x+mu-nu)
-        link_at(a, k, gauge, c, dmn2, nu);
+        link_at<P>(a, k, gauge, c, dmn2, nu);
         mat_mul_dn(b, t, a);                       // (U_mu U_nu)^+ U_nu(x-nu)
 #pragma unroll
         for (int i = 0; i < 3; ++i)

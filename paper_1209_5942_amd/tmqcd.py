@@ -109,8 +109,8 @@ def lib():
             "tmqcd_gauge_force_tlsym_workspace_bytes": (S, [P]),
             "tmqcd_gauge_force_tlsym": (I, [P, V, D, D, V, D, I, V, S, V]),
             "tmqcd_rectangle": (I, [P, V, V, V, S, V]),
-            "tmqcd_heatbath": (I, [P, V, D, ctypes.c_uint64, ctypes.c_uint32, V]),
-            "tmqcd_overrelax": (I, [P, V, V]),
+            "tmqcd_heatbath": (I, [P, V, I, D, ctypes.c_uint64, ctypes.c_uint32, V]),
+            "tmqcd_overrelax": (I, [P, V, I, V]),
             "tmqcd_update_links": (I, [P, V, V, D, V]),
             "tmqcd_plaquette": (I, [P, V, V, V, S, V]),
             "tmqcd_momentum_norm2": (I, [P, V, V, V, S, V]),
@@ -425,15 +425,15 @@ def gauge_force_tlsym(prob: Problem, U_packed, beta, c1, out=None, scale=1.0, ac
     return out
 
 
-def heatbath(prob: Problem, U_packed, beta, seed, sweep, stream=None):
-    """One heatbath sweep of the Wilson action, in place on packed FP64 RECON18 links."""
-    _check(lib().tmqcd_heatbath(ctypes.byref(prob.c()), _ptr(U_packed), float(beta), int(seed) & (2 ** 64 - 1),
-                                int(sweep) & 0xFFFFFFFF, _stream(stream)), "tmqcd_heatbath")
+def heatbath(prob: Problem, U_packed, beta, seed, sweep, prec=F64, stream=None):
+    """One heatbath sweep of the Wilson action, in place on packed RECON18 links of precision prec (F64/F32)."""
+    _check(lib().tmqcd_heatbath(ctypes.byref(prob.c()), _ptr(U_packed), prec, float(beta),
+                                int(seed) & (2 ** 64 - 1), int(sweep) & 0xFFFFFFFF, _stream(stream)), "tmqcd_heatbath")
 
 
-def overrelax(prob: Problem, U_packed, stream=None):
-    """One overrelaxation sweep, in place on packed FP64 RECON18 links."""
-    _check(lib().tmqcd_overrelax(ctypes.byref(prob.c()), _ptr(U_packed), _stream(stream)), "tmqcd_overrelax")
+def overrelax(prob: Problem, U_packed, prec=F64, stream=None):
+    """One overrelaxation sweep, in place on packed RECON18 links of precision prec (F64/F32)."""
+    _check(lib().tmqcd_overrelax(ctypes.byref(prob.c()), _ptr(U_packed), prec, _stream(stream)), "tmqcd_overrelax")
 
 
 def update_links(prob: Problem, U_packed, p, dt, stream=None):

@@ -220,14 +220,16 @@ def test_bicgstab_argument_errors(L):
 def test_heatbath_argument_errors(L):
     prob = T.Problem((4, 4, 4, 4), 0.15, 0.01)
     p = ctypes.byref(prob.c())
-    assert L.tmqcd_heatbath(p, None, 5.7, 1, 0, None) == T.EINVAL
-    assert L.tmqcd_heatbath(p, 1 << 30, -1.0, 1, 0, None) == T.EINVAL
-    assert L.tmqcd_heatbath(p, 1 << 30, float("nan"), 1, 0, None) == T.EINVAL
-    assert L.tmqcd_heatbath(p, (1 << 30) + 8, 5.7, 1, 0, None) == T.EALIGN
-    assert L.tmqcd_overrelax(p, None, None) == T.EINVAL
-    assert L.tmqcd_overrelax(p, (1 << 30) + 8, None) == T.EALIGN
+    assert L.tmqcd_heatbath(p, None, T.F64, 5.7, 1, 0, None) == T.EINVAL
+    assert L.tmqcd_heatbath(p, 1 << 30, T.F16, 5.7, 1, 0, None) == T.EINVAL
+    assert L.tmqcd_heatbath(p, 1 << 30, T.F64, -1.0, 1, 0, None) == T.EINVAL
+    assert L.tmqcd_heatbath(p, 1 << 30, T.F32, float("nan"), 1, 0, None) == T.EINVAL
+    assert L.tmqcd_heatbath(p, (1 << 30) + 8, T.F64, 5.7, 1, 0, None) == T.EALIGN
+    assert L.tmqcd_overrelax(p, None, T.F64, None) == T.EINVAL
+    assert L.tmqcd_overrelax(p, 1 << 30, 7, None) == T.EINVAL
+    assert L.tmqcd_overrelax(p, (1 << 30) + 8, T.F32, None) == T.EALIGN
     bad = T.Problem((3, 4, 4, 4), 0.15, 0.01)
-    assert L.tmqcd_heatbath(ctypes.byref(bad.c()), 1 << 30, 5.7, 1, 0, None) == T.EINVAL
+    assert L.tmqcd_heatbath(ctypes.byref(bad.c()), 1 << 30, T.F64, 5.7, 1, 0, None) == T.EINVAL
 
 
 def test_error_strings(L):

@@ -78,3 +78,55 @@ def test_strong_coupling_plaquette_8x8x8x8():
         if sw >= 5:
             vals.append(float(T.plaquette(prob, g)[0]) / (6 * prob.volume) / 3.0)
     assert abs(np.mean(vals) - beta / 18.0) < 0.002, np.mean(vals)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8)])
+@pytest.mark.parametrize("beta", [1.0, 5.7])
+def test_fp32_sweeps_match_oracle(dims, beta):
+    """FP32 links and arithmetic against the FP64 oracle, sweep by sweep from the same (FP32-rounded)
+    links.  One FP64 sweep magnifies input rounding by up to ~3000 at beta <= 1 and ~100 at 5.7 (the
+    spreads of test_sweeps_match_oracle over 1e-16), so FP32 (6e-8) allows 1e-3 and 1e-4; a decision of
+    the x0 sampler that FP32 rounding flips changes one link at O(1), so up to 0.5 % of the links may
+    differ by more (their count is printed)."""
+    print(f"\nFP32 heatbath dims={dims} beta={beta}", flush=True)
+    f = Fields(dims, 0.5, 641, 0.15, 0.0, BC_AP)
+    seed = 0x5151_7272
+    g = T.pack_gauge(f.prob, f.U_dev, T.F32)
+    before = host(T.unpack_gauge(f.prob, g, T.F32))
+    bound = 1e-3 if beta <= 1.0 else 1e-4
+    for kind, sweep in (("hb", 3), ("hb", 4), ("or", 0)):
+        if kind == "hb":
+            T.heatbath(f.prob, g, beta, seed, sweep, prec=T.F32)
+            want = OHB.heatbath_sweep(before, dims, beta, seed, sweep)
+        else:
+            T.overrelax(f.prob, g, prec=T.F32)
+            want = OHB.overrelax_sweep(before, dims)
+        got = host(T.unpack_gauge(f.prob, g, T.F32))
+        d = np.abs(got - want).reshape(got.shape[0], 4, -1).max(axis=-1)
+        n_out = int((d > bound).sum())
+        print(f"{kind}{sweep}: median {np.median(d):.1e}, links beyond {bound:g}: {n_out} of {d.size}", flush=True)
+        assert n_out <= 0.005 * d.size
+        assert np.median(d) < bound / 10
+        np.testing.assert_allclose(np.linalg.det(got), 1.0, atol=1e-5)
+        before = got
+
+
+def test_fp32_overrelaxation_keeps_the_action_and_strong_coupling():
+    dims = (8, 4, 4, 8)
+    f = Fields(dims, 0.5, 651, 0.15, 0.0, BC_AP)
+    g = T.pack_gauge(f.prob, f.U_dev, T.F32)
+    g64 = T.pack_gauge(f.prob, T.unpack_gauge(f.prob, g, T.F32))
+    p0 = float(T.plaquette(f.prob, g64)[0])
+    T.overrelax(f.prob, g, prec=T.F32)
+    g64 = T.pack_gauge(f.prob, T.unpack_gauge(f.prob, g, T.F32))
+    assert abs(float(T.plaquette(f.prob, g64)[0]) - p0) < 1e-5 * abs(p0)
+    dims, beta = (8, 8, 8, 8), 0.3
+    prob = T.Problem(dims, 0.15, 0.0, BC_AP)
+    g = T.pack_gauge(prob, dev(synth.random_links(dims, 0.3, 652).reshape(-1, 4, 3, 3)), T.F32)
+    vals = []
+    for sw in range(30):
+        T.heatbath(prob, g, beta, 78, sw, prec=T.F32)
+        if sw >= 5:
+            g64 = T.pack_gauge(prob, T.unpack_gauge(prob, g, T.F32))
+            vals.append(float(T.plaquette(prob, g64)[0]) / (6 * prob.volume) / 3.0)
+    assert abs(np.mean(vals) - beta / 18.0) < 0.002, np.mean(vals)
