@@ -43,9 +43,20 @@
  *     them before it returns).  Problem, option and stats structs are host
  *     memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *     tmqcd_pack_*, tmqcd_unpack_spinor, tmqcd_dslash and tmqcd_force are
- *     stream-ordered and return without waiting.  tmqcd_cg synchronises the
- *     stream (it reads residuals back) and returns when the solve has ended.
+ *     tmqcd_pack_*, tmqcd_unpack_*, tmqcd_dslash, the forces, the link update,
+ *     the reductions, tmqcd_heatbath and tmqcd_overrelax are stream-ordered
+ *     and return without waiting.  tmqcd_cg, tmqcd_cg_batch and tmqcd_bicgstab
+ *     synchronise the stream (they read residuals back) and return when the
+ *     solve has ended.
+ *
+ * Entry points: sizes and workspaces (*_bytes); packing; tmqcd_dslash (the
+ * operators, 1..16 right-hand sides); solvers tmqcd_cg (CG on M^+M or
+ * Mhat^+Mhat, FP64 or mixed precision), tmqcd_cg_batch (several lattices),
+ * tmqcd_bicgstab (M or Mhat); HMC pieces tmqcd_force, tmqcd_force_eo,
+ * tmqcd_gauge_force, tmqcd_gauge_force_tlsym, tmqcd_update_links,
+ * tmqcd_plaquette, tmqcd_rectangle, tmqcd_momentum_norm2, tmqcd_dot; pure-gauge
+ * updates tmqcd_heatbath and tmqcd_overrelax; the autotuner (tmqcd_tune*);
+ * tmqcd_hbm_probe; errors (tmqcd_error_string, tmqcd_last_hip_error).
  *   - No exceptions cross the interface; functions return TMQCD_OK (0) or a
  *     negative error code.  Arguments are validated on the host before any HIP
  *     call, so every argument error is reported without touching the device.
