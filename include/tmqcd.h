@@ -174,6 +174,11 @@ typedef struct {
     int32_t check_every;     /* most iterations queued between host residual checks (0 -> 32); batches
                                 are sized from the observed convergence rate */
     int32_t x_is_zero;       /* 1: ignore the contents of x and start from x0 = 0 */
+    int32_t use_graph;       /* tmqcd_cg: replay the iterations from a hipGraph of 8 iterations captured
+                                once per solve (saves the host's launch overhead, which bounds small
+                                lattices): 0 -> for lattices of at most 2^17 sites per parity, 1 always,
+                                -1 never.  Results are bitwise those of the eager launches.  On the
+                                null stream the solve then runs on a blocking stream of its own. */
 } tmqcd_cg_opts;
 
 typedef struct {

@@ -222,7 +222,7 @@ int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const voi
     if (o.op != TMQCD_MDAGM && o.op != TMQCD_MHATDAGMHAT) return TMQCD_EINVAL;
     if (!valid_prec(o.inner_prec) || !valid_recon(o.recon) || o.max_iter < 1) return TMQCD_EINVAL;
     if (!(o.tol > 0.0) || !std::isfinite(o.tol) || o.reliable_delta < 0 || o.reliable_delta >= 1 ||
-        o.check_every < 0)
+        o.check_every < 0 || o.use_graph < -1 || o.use_graph > 1)
         return TMQCD_EINVAL;
     if (!U_packed[TMQCD_F64] || !U_packed[o.inner_prec]) return TMQCD_EINVAL;
     if (!aligned(b, kAlignBytes) || !aligned(x, kAlignBytes) || !aligned(U_packed[TMQCD_F64], kAlignBytes) ||

@@ -380,10 +380,35 @@ StateInit no_change() {
         }                                             \
     } while (0)
 
+// The graph of a batch of iterations and, on the null stream, the stream it runs on; released
+// on every return path.
+struct IterGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t own = nullptr;
+    ~IterGraph() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (own) {
+            hipStreamSynchronize(own);
+            hipStreamDestroy(own);
+        }
+    }
+};
+constexpr int kGraphIters = 8;             // iterations per captured graph
+constexpr int64_t kGraphAutoMaxVh = 1 << 17;   // use_graph = 0: lattices up to this many sites per parity
+
 int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b, void* x, const tmqcd_cg_opts& o,
-           tmqcd_cg_stats& stats, void* ws, hipStream_t s) {
+           tmqcd_cg_stats& stats, void* ws, hipStream_t s_user) {
     const auto t0 = std::chrono::steady_clock::now();
     std::memset(&stats, 0, sizeof(stats));
+    const bool graph = o.use_graph == 1 || (o.use_graph == 0 && make_geom(prob).vh <= kGraphAutoMaxVh);
+    IterGraph ig;
+    hipStream_t s = s_user;
+    if (graph && s == nullptr) {   // the null stream cannot be captured; a blocking stream orders with it
+        TRY(hipStreamCreate(&ig.own));
+        s = ig.own;
+    }
     const bool full = o.op == TMQCD_MDAGM;
     const int nh = full ? 2 : 1;
     const int q = o.inner_prec;
@@ -470,6 +495,15 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
         return launch_set_state(w.st, v, s);
     };
     TRY(start_cycle(rr));
+    if (graph) {   // every stage of an iteration queued after the stop returns at once, so replays are safe
+        TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t ec = hipSuccess;
+        for (int k = 0; k < kGraphIters && ec == hipSuccess; ++k) ec = queue_iteration(cq, full, f, w.st, w.partials, pv);
+        const hipError_t ee = hipStreamEndCapture(s, &ig.graph);
+        TRY(ec);
+        TRY(ee);
+        TRY(hipGraphInstantiate(&ig.exec, ig.graph, nullptr, nullptr, 0));
+    }
 
     int status = TMQCD_OK;
     for (;;) {
@@ -481,7 +515,11 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
             double rr_poll = rr;
             int it_poll = iters_done;
             for (;;) {
-                for (int k = 0; k < batch; ++k) TRY(queue_iteration(cq, full, f, w.st, w.partials, pv));
+                if (graph) {
+                    for (int k = 0; k < batch; k += kGraphIters) TRY(hipGraphLaunch(ig.exec, s));
+                } else {
+                    for (int k = 0; k < batch; ++k) TRY(queue_iteration(cq, full, f, w.st, w.partials, pv));
+                }
                 TRY(read_state(w.st, hs, s));
                 if (hs.s.done != kDoneRunning) break;
                 int next = check;

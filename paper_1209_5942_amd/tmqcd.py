@@ -55,7 +55,7 @@ class CProblem(ctypes.Structure):
 class CCgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("op", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("recon", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
-                ("check_every", ctypes.c_int32), ("x_is_zero", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("x_is_zero", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class CCgStats(ctypes.Structure):
@@ -253,7 +253,7 @@ def dslash(prob: Problem, U_packed, inp, op, prec=F64, recon=RECON18, nrhs=1, ws
 
 def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, max_iter=10000, op=MHATDAGMHAT,
        inner_prec=F64, recon=RECON18, reliable_delta=0.0, check_every=0, ws=None, stream=None,
-       raise_on_noconv=True):
+       raise_on_noconv=True, use_graph=0):
     """Solve op x = b (packed FP64 fields).  U_packed maps precision -> packed gauge field.
 
     x: output buffer (allocated when None).  x_is_zero: start from x0 = 0 (default: when x is None);
@@ -267,7 +267,8 @@ def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, m
         ws = _bytes(workspace_bytes(prob, op, 1 | (1 << inner_prec)))
     gp = (ctypes.c_void_p * 3)(*[_ptr(U_packed.get(p)) for p in (F64, F32, F16)])
     o = CCgOpts(tol=tol, max_iter=max_iter, op=op, inner_prec=inner_prec, recon=recon,
-                reliable_delta=reliable_delta, check_every=check_every, x_is_zero=int(x_is_zero))
+                reliable_delta=reliable_delta, check_every=check_every, x_is_zero=int(x_is_zero),
+                use_graph=int(use_graph))
     st = CCgStats()
     rc = lib().tmqcd_cg(ctypes.byref(prob.c()), ctypes.byref(gp), _ptr(b), _ptr(x), ctypes.byref(o),
                         ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream))
@@ -284,7 +285,7 @@ def bicgstab(prob: Problem, U_packed, b, x=None, *, x_is_zero=None, tol=1e-10, m
              recon=RECON18, check_every=0, ws=None, stream=None, raise_on_noconv=True):
     """Solve op x = b with BiCGStab, op = M (full fields) or MHAT (even fields); U_packed: FP64 links.
 
-    x, x_is_zero as for cg.  Returns (x, stats dict, return code)."""
+    x, x_is_zero as for cg (use_graph does not apply).  Returns (x, stats dict, return code)."""
     subset = FULL if op == M else EVEN
     if x_is_zero is None:
         x_is_zero = x is None

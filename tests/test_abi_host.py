@@ -102,6 +102,8 @@ def test_cg_argument_errors(L):
     assert call(op=T.M) == T.EINVAL
     assert call(tol=0.0) == T.EINVAL
     assert call(max_iter=0) == T.EINVAL
+    assert call(use_graph=2) == T.EINVAL
+    assert call(use_graph=-2) == T.EINVAL
     assert call(inner_prec=T.F32) == T.EINVAL          # no FP32 gauge field given
     assert call(reliable_delta=1.5) == T.EINVAL
     assert call(x=(1 << 32) + 256) == T.EALIAS

@@ -168,3 +168,34 @@ def test_cg_mixed_production_shape_32x32x32x64():
         print(f"oracle residual checked for inner precision {inner}", flush=True)
     for inner in (T.F32, T.F16):
         assert rel(xs[inner], xs[T.F64]) < 1e-6, inner
+
+
+@pytest.mark.parametrize("dims,inner,op", [((4, 4, 4, 4), T.F64, T.MHATDAGMHAT), ((8, 8, 8, 8), T.F32, T.MHATDAGMHAT),
+                                           ((4, 4, 4, 4), T.F64, T.MDAGM), ((16, 16, 16, 32), T.F64, T.MHATDAGMHAT)])
+def test_cg_graph_replay_equals_eager(dims, inner, op):
+    """Iterations replayed from a captured hipGraph give the eager launches' solution bit for bit, on the
+    null stream (the solve moves to a stream of its own) and on a caller stream."""
+    import torch
+    print(f"\ngraph CG {dims} inner={inner} op={op}", flush=True)
+    f = Fields(dims, 0.4, 701, 0.155, 0.01, BC_TWIST)
+    sub = T.FULL if op == T.MDAGM else T.EVEN
+    b = T.pack_spinor(f.prob, dev(f.spinor(sub, 702)), T.F64, sub)
+    gauges = {T.F64: f.gauge(T.F64, 0), inner: f.gauge(inner, 0)}
+    outs, its = [], []
+    for use_graph, stream in ((-1, None), (1, None), (1, torch.cuda.Stream())):
+        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            x, st, rc = T.cg(f.prob, gauges, b, tol=1e-10, op=op, inner_prec=inner, use_graph=use_graph)
+        torch.cuda.synchronize()
+        assert rc == T.OK
+        outs.append(x.clone())
+        its.append(st["iters"])
+    assert its[0] == its[1] == its[2]
+    assert bool((outs[0] == outs[1]).all()) and bool((outs[0] == outs[2]).all())
+
+
+class _nullctx:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *a):
+        return False
