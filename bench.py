@@ -741,6 +741,9 @@ def bench_hmc(T, synth, dev):
     prob = T.Problem(dims, 0.155, 0.01, (1, 1, 1, -1))
     U = torch.from_numpy(synth.random_links(dims, 0.4, 80)).to(dev)
     h = HMC(prob, U, beta=0.0, tol=1e-12, md_tol=1e-10)
+    # the hop kernels in their tuned launch shapes on this lattice (FP64, and FP32 for the FP32-inner solves)
+    T.tune(prob, h.U, T.F64, T.RECON18)
+    T.tune(prob, T.pack_gauge(prob, U, T.F32), T.F32, T.RECON18)
     X = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(prob.volume, 81)).to(dev))
     Y = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(prob.volume, 82)).to(dev))
     G = torch.empty((prob.volume, 4, 8), dtype=torch.float64, device=dev)
