@@ -174,11 +174,13 @@ typedef struct {
     int32_t check_every;     /* most iterations queued between host residual checks (0 -> 32); batches
                                 are sized from the observed convergence rate */
     int32_t x_is_zero;       /* 1: ignore the contents of x and start from x0 = 0 */
-    int32_t use_graph;       /* tmqcd_cg: replay the iterations from a hipGraph of 8 iterations captured
-                                once per solve (saves the host's launch overhead, which bounds small
-                                lattices): 0 -> for lattices of at most 2^17 sites per parity, 1 always,
-                                -1 never.  Results are bitwise those of the eager launches.  On the
-                                null stream the solve then runs on a blocking stream of its own. */
+    int32_t use_graph;       /* tmqcd_cg: 1 replays the iterations from a hipGraph of 8 iterations
+                                captured once per solve (saves host launch time, a few us per
+                                iteration on lattices up to 8^3 x 16, for the cost of one capture per
+                                solve: worth it for long solves on small lattices); 0 or -1 launch
+                                every iteration.  Results are bitwise those of the eager launches.
+                                With 1 on the null stream the solve runs on a blocking stream of its
+                                own. */
 } tmqcd_cg_opts;
 
 typedef struct {

@@ -396,13 +396,12 @@ struct IterGraph {
     }
 };
 constexpr int kGraphIters = 8;             // iterations per captured graph
-constexpr int64_t kGraphAutoMaxVh = 1 << 17;   // use_graph = 0: lattices up to this many sites per parity
 
 int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b, void* x, const tmqcd_cg_opts& o,
            tmqcd_cg_stats& stats, void* ws, hipStream_t s_user) {
     const auto t0 = std::chrono::steady_clock::now();
     std::memset(&stats, 0, sizeof(stats));
-    const bool graph = o.use_graph == 1 || (o.use_graph == 0 && make_geom(prob).vh <= kGraphAutoMaxVh);
+    const bool graph = o.use_graph == 1;
     IterGraph ig;
     hipStream_t s = s_user;
     if (graph && s == nullptr) {   // the null stream cannot be captured; a blocking stream orders with it

@@ -257,7 +257,8 @@ def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, m
     """Solve op x = b (packed FP64 fields).  U_packed maps precision -> packed gauge field.
 
     x: output buffer (allocated when None).  x_is_zero: start from x0 = 0 (default: when x is None);
-    otherwise the contents of x are the start vector.  Returns (x, stats dict, return code)."""
+    otherwise the contents of x are the start vector.  use_graph: 1 replays the iterations from a
+    captured hipGraph, 0 or -1 launches them one by one.  Returns (x, stats dict, return code)."""
     subset = FULL if op == MDAGM else EVEN
     if x_is_zero is None:
         x_is_zero = x is None
