@@ -35,6 +35,11 @@ _LINK = {0: (144, 96, 80, 64), 1: (72, 48, 40, 32), 2: (36, 24, 20, 16)}
 _SPINOR = {0: 192, 1: 96, 2: 52}
 BYTES_PER_SITE = {(p, r): 8 * _LINK[p][r] + 2 * _SPINOR[p] for p in range(3) for r in range(4)}
 FLOPS_PER_SITE = 1320           # Wilson hop, per output site
+# one FP64 iteration of CG on Mhat^dag Mhat per even site (algorithmic, REC18 links): the operator's four
+# hops -- two plain stores (1536 B each), the one that adds A p and sums |Mhat p|^2 (also reads p: 1728 B),
+# the one that adds A^dag t, updates x and r and sums |r|^2 (reads t and p, reads and writes x and r:
+# 2496 B) -- and p = r + beta p (576 B)
+CG_ITER_BYTES_PER_SITE = 1536 + 1728 + 1536 + 2496 + 576
 WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.5, kappa=0.16, mu=0.005, seed=24, src_seed=26)
 MIXED = dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.162, mu=0.003, seed=32, src_seed=34)
 HOP_SOURCES = ("hop.hip", "stencil.h", "device.h", "layout.h")
@@ -198,6 +203,7 @@ def main():
     del a, c
 
     traffic = traffic_from_profile(vh)
+    cg_gbs = st0["iters"] * vh * CG_ITER_BYTES_PER_SITE / (elapsed / args.steps) / 1e9
     result = {
         "metric": "Dslash GB/s (% HBM peak); CG time to 1e-10 residual, FP64 vs mixed",
         "value": round(value, 1),
@@ -216,7 +222,12 @@ def main():
                    "bc": "periodic space, antiperiodic time", "recon": 18, "parallelism": "1 GPU"},
         "cg_fp64_24x24x24x48": {"iters": st0["iters"], "ms": round(1e3 * elapsed / args.steps, 3),
                                 "true_rel_residual": st0["true_rel_residual"],
-                                "hop_launches_per_solve": st0["hop_launches"]},
+                                "hop_launches_per_solve": st0["hop_launches"],
+                                "algorithmic_bytes_per_iteration": vh * CG_ITER_BYTES_PER_SITE,
+                                # the iterations' bytes over the whole solve's time (set-up and the final
+                                # true residual included)
+                                "iteration_GB_s": round(cg_gbs, 1),
+                                "iteration_frac_of_measured_read": round(cg_gbs / read_gbs, 4)},
         "roofline": {"bound": "hbm", "achieved": round(gbs_hop, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(gbs_hop / PEAK_HBM_GBPS, 4), "traffic": traffic,
                      "kernel": f"hop_kernel<F64,RECON18,dag=0,own=0,store> block {tuning['class0']['block']} "
