@@ -120,12 +120,16 @@ def test_tune_mrhs_admits_equal_orders_and_keeps_results():
     g = f.gauge(T.F64, 0)
     try:
         T.tune_clear()
-        before = host(T.dslash(f.prob, g, inp, T.MHATDAGMHAT, nrhs=12))
+        # compare the sites only: the packed fields' padding (this lattice's half volume is not a
+        # multiple of 64) is never written
+        before = host(T.unpack_spinor(f.prob, T.dslash(f.prob, g, inp, T.MHATDAGMHAT, nrhs=12), T.F64, T.EVEN,
+                                      nrhs=12))
         r = T.tune_mrhs(f.prob, g, 12)
         assert r["kernel_class"] == 3 and r["candidates"] == 12 and r["rejected"] == 0
         assert r["block"] == 256 and r["order"] in (0, 1, 2, 3) and r["group"] in (0, 6, 4)
         assert 0 < r["us"] <= r["default_us"] * 1.0001
-        after = host(T.dslash(f.prob, g, inp, T.MHATDAGMHAT, nrhs=12))
+        after = host(T.unpack_spinor(f.prob, T.dslash(f.prob, g, inp, T.MHATDAGMHAT, nrhs=12), T.F64, T.EVEN,
+                                     nrhs=12))
         assert np.array_equal(before, after)
     finally:
         T.tune_clear()
