@@ -87,26 +87,13 @@ struct HopK {
 //                  ranges of q sites, range x belonging to XCD x (hardware
 //                  blocks go round-robin over the XCDs); each XCD walks through
 //                  its ranges slice by slice, so the t-neighbours it reads
-//                  belong to slices it has in flight; a grid over both
-//                  parities takes the even and the odd block of the same half
-//                  sites in turn, so that a spinor read as a neighbour by one
-//                  parity's blocks is still in the XCD's L2 when the other
-//                  parity's block reads it as its own site;
+//                  belong to slices it has in flight;
 //  kOrderColumn:   the (y, z) plane is cut into regions of by x bz (all x), and
 //                  XCD x sweeps its regions x, x + 8, ... one after the other,
 //                  each through all t: the neighbours an XCD reads lie in the
 //                  few slices of one column it has in flight, except on the
 //                  region's y and z faces.
 __device__ __forceinline__ bool block_site(const HopK& a, int b, int lane, int& par, int& h) {
-    if (a.order == kOrderSlab && a.nparity == 2) {   // 2 x 8 x lt x tq blocks
-        const int x = b & (kNumXcd - 1), kk = b / kNumXcd;
-        const int t = kk / (2 * a.tq), rem = kk - t * 2 * a.tq;
-        par = rem & 1;
-        const int first = x * a.q + (rem >> 1) * a.width + lane;
-        const int end = min((x + 1) * a.q, a.slice);
-        h = t * a.slice + first;
-        return first < end;
-    }
     if (a.order == kOrderXcdRemap) b = xcd_swizzle(b, a.nblocks);
     int lb = b;
     par = a.out_parity;
