@@ -78,7 +78,7 @@ struct ForceK {
 // and X, Y of one parity are read as neighbours by the blocks of the other parity
 // while still in the XCD's L2.  Against all even blocks followed by all odd ones
 // in lattice order this measured 40.8 vs 42.6 us at 16^3 x 32, 212 us for both at
-// 24^3 x 48 and 639 vs 683 us at 32^3 x 64 (one box, alternating runs), with
+// 24^3 x 48 and 639 vs 683 us at 32^3 x 64 (one GPU, the two builds run alternately), with
 // bitwise the same output; giving each XCD one contiguous eighth of the lattice
 // instead lost on 32^3 x 64, whose t-slice of X and Y no longer fits in L2.
 __device__ __forceinline__ bool force_block_site(const ForceK& a, int bid, int lane, int& par, int& h) {
