@@ -98,7 +98,7 @@ def main():
         counters_from(*args.counters_from)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the solver runs on a single MI355X and this build has no "
+        print("bench.py measures one GPU: the solver runs on a single MI355X and the library has no "
               "multi-GPU path (--gpus must be 1).", file=sys.stderr)
         sys.exit(2)
 
