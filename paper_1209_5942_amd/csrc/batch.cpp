@@ -249,12 +249,12 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
     }
     for (int i = 0; i < n; ++i) stats[i].hop_launches = 4 * (stats[i].iters + applies[i]);
     TRY(hipStreamSynchronize(s));
-done:
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+done:   // teardown: the status is already decided, so errors here are dropped
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (own_stream) {
-        hipStreamSynchronize(s);
-        hipStreamDestroy(s);
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int i = 0; i < n; ++i) stats[i].seconds = secs;

@@ -386,12 +386,12 @@ struct IterGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t own = nullptr;
-    ~IterGraph() {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+    ~IterGraph() {   // teardown: the solve's status is already decided, so errors here are dropped
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         if (own) {
-            hipStreamSynchronize(own);
-            hipStreamDestroy(own);
+            (void)hipStreamSynchronize(own);
+            (void)hipStreamDestroy(own);
         }
     }
 };

@@ -237,9 +237,9 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
         record(arch, key_of(arch, cls, prec, recon, g.L, 1), TuneChoice{res.block, res.order, 0, res.us});
     }
     TRY(hipStreamSynchronize(s));
-done:
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+done:   // teardown: rc is already decided, so errors here are dropped
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     return rc;
 }
 
@@ -318,9 +318,9 @@ int run_tune_mrhs(const tmqcd_problem& prob, const void* gauge, int prec, int re
     }
     record(arch, key_of(arch, kClassMultiRhs, prec, recon, g.L, nrhs), TuneChoice{res->block, res->order, res->group, res->us});
     TRY(hipStreamSynchronize(s));
-done:
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+done:   // teardown: rc is already decided, so errors here are dropped
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     return rc;
 }
 
