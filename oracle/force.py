@@ -34,15 +34,39 @@ from __future__ import annotations
 
 import numpy as np
 
-from paper_1209_5942_amd.synth import gell_mann
-
 from .dirac import (AXIS, GAMMA, ID4, apply_MdagM, apply_Mhat, apply_MhatdagMhat, cg, hop_pq, shape4, to_full,
                     twist_inv)
 
 __all__ = ["T_GEN", "fermion_force", "fermion_action", "fermion_action_eo", "fermion_force_eo", "plaquette_sum",
            "gauge_action", "gauge_force", "staple_sum"]
 
-T_GEN = gell_mann() / 2
+
+def _gell_mann() -> np.ndarray:
+    """The eight Gell-Mann matrices lambda^a (the standard su(3) basis), entry by entry.
+
+    lambda^1..3 embed the Pauli matrices in the (0, 1) block, lambda^4, lambda^5 the
+    x and y Pauli matrices in the (0, 2) rows and columns, lambda^6, lambda^7 those
+    in (1, 2), and lambda^8 = diag(1, 1, -2) / sqrt(3).  Pinned by the tests: every
+    one hermitian and traceless, Tr(lambda^a lambda^b) = 2 delta^ab, and the
+    structure constants f^123 = 1, f^458 = f^678 = sqrt(3)/2 of
+    [T^a, T^b] = i f^abc T^c.
+    """
+    s3 = 1.0 / np.sqrt(3.0)
+    lam = np.array([
+        [[0, 1, 0], [1, 0, 0], [0, 0, 0]],
+        [[0, -1j, 0], [1j, 0, 0], [0, 0, 0]],
+        [[1, 0, 0], [0, -1, 0], [0, 0, 0]],
+        [[0, 0, 1], [0, 0, 0], [1, 0, 0]],
+        [[0, 0, -1j], [0, 0, 0], [1j, 0, 0]],
+        [[0, 0, 0], [0, 0, 1], [0, 1, 0]],
+        [[0, 0, 0], [0, 0, -1j], [0, 1j, 0]],
+        [[s3, 0, 0], [0, s3, 0], [0, 0, -2 * s3]],
+    ], dtype=np.complex128)
+    return lam
+
+
+# su(3) generators T^a = lambda^a / 2 (the link parametrisation exp(i w^a T^a) U)
+T_GEN = _gell_mann() / 2
 
 
 def _bplus(dims, mu, bc) -> np.ndarray:

@@ -91,12 +91,31 @@ def _words(seed, link, sweep, sub, trial):
     return philox4x32(link, np.uint64(sweep), c2, np.uint64(0), k0, k1)
 
 
-def sample_x0(alpha, seed, link, sweep, sub, max_trials: int = 0xFFFE):
-    """x0 with density sqrt(1 - x0^2) exp(alpha x0) on [-1, 1], one per link (arrays alpha, link)."""
+def sample_x0(alpha, seed, link, sweep, sub, max_trials: int = 0xFFFE, flips=None, watch=None):
+    """x0 with density sqrt(1 - x0^2) exp(alpha x0) on [-1, 1], one per link (arrays alpha, link).
+
+    Decisions of the sampler are (link, sub, -1) for the choice of method (alpha < 2) and
+    (link, sub, t) for the acceptance of trial t.  Two test hooks, unused by default:
+    `flips`, a set of decisions taken the other way; `watch`, a dict {link: list} to which
+    the margin of every decision made for that link is appended as ((link, sub, t), margin),
+    the margin being positive for "yes" and its size the distance to the other outcome
+    (alpha - 2 for the method; sqrt(1 - x0^2) - u, or 1 - lambda^2 - r4^2, for a trial)."""
     alpha = np.asarray(alpha, dtype=np.float64)
+    link_ids = np.atleast_1d(np.asarray(link, dtype=np.uint64)).astype(np.int64)
     x0 = np.zeros_like(alpha)
     todo = np.ones(alpha.shape, dtype=bool)
     small = alpha < ALPHA_SWITCH
+
+    def flipped(i, t):
+        return flips is not None and (int(link_ids[i]), sub, t) in flips
+
+    watched = [] if watch is None else [i for i, l in enumerate(link_ids) if int(l) in watch]
+    for i in watched:
+        watch[int(link_ids[i])].append(((int(link_ids[i]), sub, -1), float(ALPHA_SWITCH - alpha[i])))
+    if flips:
+        for i in range(len(link_ids)):
+            if flipped(i, -1):
+                small[i] = not small[i]
     for trial in range(max_trials):
         if not todo.any():
             break
@@ -106,12 +125,23 @@ def sample_x0(alpha, seed, link, sweep, sub, max_trials: int = 0xFFFE):
             # alpha < 2: invert the exponential, accept with sqrt(1 - x0^2)
             xc = np.where(alpha > 0, -1.0 + np.log1p(u[0] * np.expm1(2.0 * alpha)) / np.where(alpha > 0, alpha, 1.0),
                           2.0 * u[0] - 1.0)
-            acc_c = u[1] <= np.sqrt(np.maximum(0.0, (1.0 - xc) * (1.0 + xc)))
+            marg_c = np.sqrt(np.maximum(0.0, (1.0 - xc) * (1.0 + xc))) - u[1]
+            acc_c = marg_c >= 0
             # Kennedy-Pendleton
             lam2 = -(np.log(u[0]) + np.cos(2.0 * np.pi * u[1]) ** 2 * np.log(u[2])) / (2.0 * alpha)
-            acc_k = u[3] * u[3] <= 1.0 - lam2
+            marg_k = (1.0 - lam2) - u[3] * u[3]
+            acc_k = marg_k >= 0
             xk = 1.0 - 2.0 * lam2
-        acc = np.where(small, acc_c, acc_k) & todo
+        acc = np.where(small, acc_c, acc_k)
+        for i in watched:
+            if todo[i]:
+                m = marg_c[i] if small[i] else marg_k[i]
+                watch[int(link_ids[i])].append(((int(link_ids[i]), sub, trial), float(m)))
+        if flips:
+            for i in np.nonzero(todo)[0]:
+                if flipped(i, trial):
+                    acc[i] = not acc[i]
+        acc &= todo
         x0 = np.where(acc, np.where(small, xc, xk), x0)
         todo &= ~acc
     if todo.any():
@@ -142,9 +172,9 @@ def _dag(m):
     return np.conj(np.swapaxes(m, -1, -2))
 
 
-def update_su3(u, V, beta, seed: int, link, sweep: int, heatbath: bool):
+def update_su3(u, V, beta, seed: int, link, sweep: int, heatbath: bool, flips=None, watch=None):
     """Update links u[n, 3, 3] with staple sums V[n, 3, 3] over the three subgroups; link[n] are their
-    generator ids (4 s + mu).  Returns the new links."""
+    generator ids (4 s + mu).  Returns the new links.  flips, watch: the test hooks of sample_x0."""
     u = u.copy()
     for sub, (a, b) in enumerate(SUBGROUPS):
         W = u @ V
@@ -157,7 +187,7 @@ def update_su3(u, V, beta, seed: int, link, sweep: int, heatbath: bool):
                  np.where(nz, a3 / ks, 0.0))
         if heatbath:
             alpha = (2.0 / 3.0) * beta * k
-            x0 = sample_x0(alpha, seed, link, sweep, sub)
+            x0 = sample_x0(alpha, seed, link, sweep, sub, flips=flips, watch=watch)
             wd = _words(seed, link, sweep, sub, DIR_TRIAL)
             cth = 2.0 * uniform(wd[0]) - 1.0
             phi = 2.0 * np.pi * uniform(wd[1])
@@ -174,7 +204,7 @@ def update_su3(u, V, beta, seed: int, link, sweep: int, heatbath: bool):
     return u
 
 
-def _update_links(U, dims, beta, seed, sweep, heatbath: bool):
+def _update_links(U, dims, beta, seed, sweep, heatbath: bool, flips=None, watch=None):
     """One sweep over directions and parities; returns the new links (V, 4, 3, 3)."""
     U = U.copy()
     parity = coords(dims).sum(axis=1) % 2
@@ -183,13 +213,14 @@ def _update_links(U, dims, beta, seed, sweep, heatbath: bool):
             sites = np.nonzero(parity == par)[0]
             V = staple_sum(U, dims)[sites, mu]
             link = (4 * sites + mu).astype(np.uint64)
-            U[sites, mu] = update_su3(U[sites, mu], V, beta, seed, link, sweep, heatbath)
+            U[sites, mu] = update_su3(U[sites, mu], V, beta, seed, link, sweep, heatbath, flips, watch)
     return U
 
 
-def heatbath_sweep(U, dims, beta, seed: int, sweep: int):
-    """One heatbath sweep with the generator streams of (seed, sweep)."""
-    return _update_links(U, dims, beta, seed, sweep, True)
+def heatbath_sweep(U, dims, beta, seed: int, sweep: int, flips=None, watch=None):
+    """One heatbath sweep with the generator streams of (seed, sweep).  flips, watch: the test
+    hooks of sample_x0 (decisions taken the other way; margins of a link's decisions)."""
+    return _update_links(U, dims, beta, seed, sweep, True, flips, watch)
 
 
 def overrelax_sweep(U, dims):

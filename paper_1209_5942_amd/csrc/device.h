@@ -673,6 +673,19 @@ __device__ __forceinline__ void cg_finish_update(CgState* st, double total, int 
     }
 }
 
+// Whether the solve behind st has stopped, read once per block so that every
+// wave of the block takes the same branch (another block of the same launch may
+// set the flag meanwhile).  Callable inside a loop: the second barrier keeps the
+// next call's write behind every wave's read.
+__device__ __forceinline__ bool block_stopped(const CgState* st) {
+    __shared__ int flag;
+    if (threadIdx.x == 0) flag = st->done;
+    __syncthreads();
+    const bool stopped = flag != 0;
+    __syncthreads();
+    return stopped;
+}
+
 // A whole block finishes a CG reduction of n partials unless the solve has
 // stopped; returns (in every thread) whether the solve is stopped afterwards.
 template <int BS>
@@ -680,7 +693,9 @@ __device__ __forceinline__ bool cg_finish_block(CgState* st, const double* parti
     __shared__ int stopped;
     if (threadIdx.x == 0) stopped = st->done;
     __syncthreads();
-    if (stopped) return true;
+    const bool before = stopped != 0;
+    __syncthreads();   // every wave has read the flag before it is written again
+    if (before) return true;
     double tot[1];
     sum_partials<1, BS>(partials, n, tot);
     if (threadIdx.x == 0) {
@@ -688,7 +703,9 @@ __device__ __forceinline__ bool cg_finish_block(CgState* st, const double* parti
         stopped = st->done;
     }
     __syncthreads();
-    return stopped != 0;
+    const bool after = stopped != 0;
+    __syncthreads();   // as above: the batched kernel may call this again in its loop
+    return after;
 }
 
 }  // namespace tmqcd

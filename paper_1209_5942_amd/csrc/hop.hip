@@ -15,7 +15,7 @@ __global__ __launch_bounds__(BS) void hop_kernel(const HopK a) {
                   "vector and dslash compute types differ");
     if (a.fin_n > 0 && blockIdx.x == 0) {
         if (cg_finish_block<BS>(a.st, a.fin_partials, a.fin_n, a.fin_kind)) return;
-    } else if (a.st != nullptr && a.st->done) {
+    } else if (a.st != nullptr && block_stopped(a.st)) {
         return;   // a solver stage queued after its stop
     }
     int par, h;

@@ -24,8 +24,8 @@ __global__ __launch_bounds__(kBlock) void hop_batch_kernel(const HopBatch b) {
         const HopK& a = b.lat[i];
         if (a.fin_n > 0 && tile == b.tile_start[i]) {   // the lattice's first tile finishes its reduction
             if (cg_finish_block<kBlock>(a.st, a.fin_partials, a.fin_n, a.fin_kind)) continue;
-        } else if (a.st != nullptr && a.st->done) {
-            continue;
+        } else if (a.st != nullptr && block_stopped(a.st)) {
+            continue;   // block-uniform: every wave skips the tile together
         }
         const int lt = tile - b.tile_start[i];
         int par, h;

@@ -51,11 +51,13 @@ class FermionAction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, omega, h: "HMC"):
-        U = h.U
+        # The backward pass needs the links and the solution of this call: both are kept
+        # in buffers of their own, since the HMC state's links change in place and its
+        # solve buffer is reused by every later solve.
+        U = h.U.clone()
         if bool(torch.any(omega != 0)):
-            U = h.U.clone()
             T.update_links(h.prob, U, omega, 1.0)
-        X = h.solve(h.phi, U)
+        X = h.solve(h.phi, U, x=torch.empty_like(h.X))
         s = T.dot(h.prob, h.phi, X, h.subset, ws=h.ws_aux)
         ctx.h, ctx.U, ctx.X = h, U, X
         return s[0].clone()

@@ -305,9 +305,10 @@ def bicgstab(prob: Problem, U_packed, b, x=None, *, x_is_zero=None, tol=1e-10, m
 
 
 def cg_batch(probs, U_packed, bs, xs=None, *, tol=1e-10, max_iter=10000, recon=RECON18, use_graph=True,
-             check_every=0, ws=None, stream=None, raise_on_noconv=True):
+             check_every=0, ws=None, stream=None, raise_on_noconv=True, raise_on_breakdown=True):
     """FP64 CG on Mhat^dag Mhat for several lattices in one solve (packed FP64 even fields).
 
+    A lattice that breaks down (TMQCD_EBREAKDOWN) stops alone; the others are solved.
     Returns (xs, [stats dict per lattice], return code)."""
     n = len(probs)
     cp = (CProblem * n)(*[p.c() for p in probs])
@@ -321,7 +322,8 @@ def cg_batch(probs, U_packed, bs, xs=None, *, tol=1e-10, max_iter=10000, recon=R
     st = (CCgStats * n)()
     rc = lib().tmqcd_cg_batch(n, cp, arr(U_packed), arr(bs), arr(xs), ctypes.byref(o), st, int(use_graph),
                               _ptr(ws), ws.numel(), _stream(stream))
-    if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
+    tolerated = (OK,) + (() if raise_on_noconv else (ENOCONV,)) + (() if raise_on_breakdown else (EBREAKDOWN,))
+    if rc not in tolerated:
         raise TmqcdError(rc, "tmqcd_cg_batch")
     return xs, [s.as_dict() for s in st], rc
 

@@ -93,3 +93,29 @@ def test_batch_of_one_and_of_eight():
     for k, f in enumerate(fs):
         A = lambda v, f=f: D.apply_MhatdagMhat(f.U, v, f.dims, f.kappa, f.mu, f.bc)
         assert D.true_rel_residual(A, bs[k], xs[k]) <= 1e-10
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_member_breakdown_leaves_the_others_solved(use_graph):
+    """One lattice's links hold a NaN, so its first p^+ A p is not finite and its solve
+    breaks down inside a batched launch; the call reports TMQCD_EBREAKDOWN, and the
+    other lattices, whose tiles share those launches, still equal their standalone solves."""
+    fs, bs = _setup([((8, 8, 8, 8), BC_AP), ((4, 4, 4, 8), BC_AP), ((12, 12, 12, 24), BC_AP)])
+    bad = fs[1].U.copy().reshape(-1, 4, 3, 3)
+    bad[5, 2, 0, 0] = np.nan
+    probs = [f.prob for f in fs]
+    gauges = [f.gauge(T.F64, 0) for f in fs]
+    gauges[1] = T.pack_gauge(fs[1].prob, dev(bad))
+    bp = [T.pack_spinor(f.prob, dev(b), T.F64, T.EVEN) for f, b in zip(fs, bs)]
+    xs, st, rc = T.cg_batch(probs, gauges, bp, use_graph=use_graph, check_every=4, raise_on_breakdown=False)
+    assert rc == T.EBREAKDOWN
+    assert st[1]["converged"] == 0
+    for k in (0, 2):
+        f = fs[k]
+        x = host(T.unpack_spinor(f.prob, xs[k], T.F64, T.EVEN))
+        x1, s1, _ = T.cg(f.prob, {T.F64: f.gauge(T.F64, 0)}, bp[k], tol=1e-10, check_every=4)
+        x1 = host(T.unpack_spinor(f.prob, x1, T.F64, T.EVEN))
+        assert st[k]["converged"] == 1
+        assert rel(x, x1) < 1e-12
+        A = lambda v, f=f: D.apply_MhatdagMhat(f.U, v, f.dims, f.kappa, f.mu, f.bc)
+        assert D.true_rel_residual(A, bs[k], x) <= 1e-10

@@ -81,9 +81,14 @@ def test_cg_with_rec8_links(inner):
     x, st, rc = T.cg(f.prob, gauges, T.pack_spinor(f.prob, dev(b), T.F64, T.EVEN), tol=1e-10, op=T.MHATDAGMHAT,
                      inner_prec=inner, recon=T.RECON8)
     assert rc == T.OK
-    A = lambda v: D.apply_MhatdagMhat(f.U, v, f.dims, f.kappa, f.mu, f.bc)
-    # the REC8 links equal U to FP64 rounding times the reconstruction's amplification
-    assert D.true_rel_residual(A, b, host(T.unpack_spinor(f.prob, x, T.F64, T.EVEN))) < 1e-9
+    # The solver's system is the one on the reconstructed links, which differ from U by the
+    # FP64 rounding of the stored numbers times the reconstruction's 1/(|a2|^2 + |a3|^2) (up to
+    # 1e-13 here): the oracle rebuilds the same links from its own encoding and checks the
+    # requested 1e-10 on them; the two reconstructions differ by a few ulp, which moves the
+    # residual by cond(A) times that, far below the 2 % allowed on top.
+    Ur = OC.rec8_decode(OC.rec8_encode(f.U))
+    A = lambda v: D.apply_MhatdagMhat(Ur, v, f.dims, f.kappa, f.mu, f.bc)
+    assert D.true_rel_residual(A, b, host(T.unpack_spinor(f.prob, x, T.F64, T.EVEN))) <= 1.02e-10
 
 
 def test_bicgstab_with_rec10_links():
@@ -92,8 +97,10 @@ def test_bicgstab_with_rec10_links():
     x, st, rc = T.bicgstab(f.prob, f.gauge(T.F64, T.RECON10), T.pack_spinor(f.prob, dev(b)), tol=1e-10, op=T.M,
                            recon=T.RECON10)
     assert rc == T.OK
-    A = lambda v: D.apply_M(f.U, v, f.dims, f.kappa, f.mu, f.bc)
-    assert D.true_rel_residual(A, b, host(T.unpack_spinor(f.prob, x))) < 1e-9
+    # as for CG above: the residual of the system on the reconstructed links
+    Ur = OC.rec10_decode(OC.rec10_encode(f.U))
+    A = lambda v: D.apply_M(Ur, v, f.dims, f.kappa, f.mu, f.bc)
+    assert D.true_rel_residual(A, b, host(T.unpack_spinor(f.prob, x))) <= 1.02e-10
 
 
 @pytest.mark.parametrize("recon", [T.RECON10, T.RECON8])

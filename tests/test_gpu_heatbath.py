@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from gpu_util import BC_AP, Fields, dev, host
+from oracle import dirac as D
 from oracle import force as F
 from oracle import heatbath as OHB
 from paper_1209_5942_amd import synth
@@ -80,14 +81,52 @@ def test_strong_coupling_plaquette_8x8x8x8():
     assert abs(np.mean(vals) - beta / 18.0) < 0.002, np.mean(vals)
 
 
+# A decision of the x0 sampler compares two O(1) quantities that the FP32 path forms from
+# FP32 links (alpha to ~1e-5 after the staple sum's cancellations, x0 and the acceptance
+# bound to a few 1e-7 from it): a margin below this can come out the other way in FP32.
+FP32_MARGIN = 2e-4
+
+
+def _explain_fp32_outliers(got, before, dims, beta, seed, sweep, bound):
+    """Oracle sweeps with FP32-fragile decisions taken the other way until it matches the GPU.
+
+    Links of one direction and parity are updated together and independently, so the outliers
+    of the first such group (in sweep order) that has any are primary; each must have a decision
+    whose oracle margin is below FP32_MARGIN, which is flipped; links updated later may differ
+    only through those (cascades), so the sweep is recomputed with the flips.  Returns the
+    flipped decisions with their margins and the final oracle sweep."""
+    flips, explained = set(), []
+    par = D.coords(dims).sum(axis=1) % 2
+    for _ in range(64):
+        want = OHB.heatbath_sweep(before, dims, beta, seed, sweep, flips=flips)
+        d = np.abs(got - want).reshape(got.shape[0], 4, -1).max(axis=-1)
+        out = np.argwhere(d > bound)
+        if len(out) == 0:
+            return explained, want
+        order = [(mu, p) for mu in range(4) for p in (0, 1)]
+        first = min(order.index((m, par[s])) for s, m in out)
+        mu0, p0 = order[first]
+        prim = [(s, m) for s, m in out if (m, par[s]) == (mu0, p0)]
+        watch = {4 * int(s) + int(m): [] for s, m in prim}
+        OHB.heatbath_sweep(before, dims, beta, seed, sweep, flips=flips, watch=watch)
+        for lid, recs in watch.items():
+            cand = [(abs(mg), dec) for dec, mg in recs if dec not in flips]
+            m, dec = min(cand)
+            assert m < FP32_MARGIN, f"link {lid} differs at O(1) but its closest decision has margin {m:.3e}"
+            flips.add(dec)
+            explained.append((dec, m))
+    raise AssertionError("outliers not explained after 64 rounds")
+
+
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8)])
 @pytest.mark.parametrize("beta", [1.0, 5.7])
 def test_fp32_sweeps_match_oracle(dims, beta):
     """FP32 links and arithmetic against the FP64 oracle, sweep by sweep from the same (FP32-rounded)
     links.  One FP64 sweep magnifies input rounding by up to ~3000 at beta <= 1 and ~100 at 5.7 (the
-    spreads of test_sweeps_match_oracle over 1e-16), so FP32 (6e-8) allows 1e-3 and 1e-4; a decision of
-    the x0 sampler that FP32 rounding flips changes one link at O(1), so up to 0.5 % of the links may
-    differ by more (their count is printed)."""
+    spreads of test_sweeps_match_oracle over 1e-16), so FP32 (6e-8) allows 1e-3 and 1e-4.  A link that
+    differs by more must be an accept/reject (or method) decision of the x0 sampler whose oracle
+    margin lies within FP32 rounding, or a link whose staple holds such a link: with those decisions
+    taken the other way the oracle's sweep matches the GPU's everywhere."""
     print(f"\nFP32 heatbath dims={dims} beta={beta}", flush=True)
     f = Fields(dims, 0.5, 641, 0.15, 0.0, BC_AP)
     seed = 0x5151_7272
@@ -97,15 +136,18 @@ def test_fp32_sweeps_match_oracle(dims, beta):
     for kind, sweep in (("hb", 3), ("hb", 4), ("or", 0)):
         if kind == "hb":
             T.heatbath(f.prob, g, beta, seed, sweep, prec=T.F32)
-            want = OHB.heatbath_sweep(before, dims, beta, seed, sweep)
         else:
             T.overrelax(f.prob, g, prec=T.F32)
-            want = OHB.overrelax_sweep(before, dims)
         got = host(T.unpack_gauge(f.prob, g, T.F32))
+        if kind == "hb":
+            explained, want = _explain_fp32_outliers(got, before, dims, beta, seed, sweep, bound)
+        else:
+            explained, want = [], OHB.overrelax_sweep(before, dims)
         d = np.abs(got - want).reshape(got.shape[0], 4, -1).max(axis=-1)
-        n_out = int((d > bound).sum())
-        print(f"{kind}{sweep}: median {np.median(d):.1e}, links beyond {bound:g}: {n_out} of {d.size}", flush=True)
-        assert n_out <= 0.005 * d.size
+        print(f"{kind}{sweep}: median {np.median(d):.1e}, max {d.max():.1e}; FP32-close decisions taken "
+              f"the other way: {[(dec, f'{m:.1e}') for dec, m in explained]}", flush=True)
+        assert d.max() <= bound
+        assert len(explained) <= 0.005 * d.size
         assert np.median(d) < bound / 10
         np.testing.assert_allclose(np.linalg.det(got), 1.0, atol=1e-5)
         before = got

@@ -186,3 +186,34 @@ def test_mixed_precision_trajectory_equals_fp64_16x16x16x32():
         assert abs(out[0]["dH"] - out[k]["dH"]) < 1e-6, (out[0]["dH"], out[k]["dH"])
         assert np.abs(links[0] - links[k]).max() < 1e-9
     assert iters[2] < iters[1]
+
+
+@pytest.mark.parametrize("eo", [False, True])
+def test_fermion_action_backward_keeps_its_own_links_and_solution(eo):
+    """Two forwards at different omega summed, the HMC's links and solve buffer changed in
+    between, then one backward: each omega receives the oracle's force at its own links
+    exp(i omega.T) U with its own solution."""
+    dims, kappa, mu = (4, 4, 4, 4), 0.15, 0.01
+    f = Fields(dims, 0.3, 251, kappa, mu, BC_AP)
+    v = f.prob.volume
+    h = H.HMC(f.prob, f.U_dev, 0.0, tol=1e-13, eo=eo)
+    n = v // 2 if eo else v
+    h.set_pseudofermion(dev(synth.gaussian_spinor(n, 252)))
+    phi = host(T.unpack_spinor(f.prob, h.phi, T.F64, h.subset))
+    w2 = 0.05 * synth.gaussian_momenta(v, 253)
+    om1 = torch.zeros((v, 4, 8), dtype=torch.float64, device="cuda", requires_grad=True)
+    om2 = torch.tensor(w2, dtype=torch.float64, device="cuda", requires_grad=True)
+    s = H.FermionAction.apply(om1, h) + H.FermionAction.apply(om2, h)
+    # the state moves on before the backward pass: another solve and a link update
+    h.solve(h.phi)
+    T.update_links(f.prob, h.U, dev(synth.gaussian_momenta(v, 254)), 0.1)
+    s.backward()
+    U2 = OH.su3_exp(w2, 1.0) @ f.U.reshape(-1, 4, 3, 3)
+    for om, U in ((om1, f.U.reshape(-1, 4, 3, 3)), (om2, U2)):
+        if eo:
+            Xe, _ = D.cg(lambda x: D.apply_MhatdagMhat(U, x, dims, kappa, mu, BC_AP), phi, 1e-14)
+            want = F.fermion_force_eo(U, Xe, dims, kappa, mu, BC_AP)
+        else:
+            X, _ = D.cg(lambda x: D.apply_MdagM(U, x, dims, kappa, mu, BC_AP), phi, 1e-14)
+            want = F.fermion_force(U, X, D.apply_M(U, X, dims, kappa, mu, BC_AP), dims, kappa, BC_AP)
+        assert rel(host(om.grad), want) < 1e-10

@@ -136,3 +136,32 @@ def test_trajectory_accept_rule():
     assert out["accepted"] == (0.5 < np.exp(-out["dH"]))
     # a uniform draw of 0 always accepts, of 1 accepts only when dH <= 0
     assert H.trajectory(U, p, eta, 0.0, dims, kappa, mu, BC, beta, 10, 0.1)["accepted"]
+
+
+# The standard su(3) structure constants f^abc (1-based labels, totally antisymmetric):
+# the non-zero ones up to permutation.
+_F_ABC = {(1, 2, 3): 1.0, (1, 4, 7): 0.5, (1, 5, 6): -0.5, (2, 4, 6): 0.5, (2, 5, 7): 0.5, (3, 4, 5): 0.5,
+          (3, 6, 7): -0.5, (4, 5, 8): np.sqrt(3) / 2, (6, 7, 8): np.sqrt(3) / 2}
+
+
+def test_oracle_su3_generators_are_the_gell_mann_basis():
+    """T^a = lambda^a / 2: hermitian, traceless, Tr T^a T^b = delta^ab / 2, and
+    [T^a, T^b] = i f^abc T^c with the textbook f^abc (f^123 = 1, f^458 = sqrt(3)/2, ...).
+    A swapped label, a sign or a factor in any entry breaks one of these."""
+    T = F.T_GEN
+    assert T.shape == (8, 3, 3)
+    for a in range(8):
+        assert np.allclose(T[a], T[a].conj().T, atol=1e-15)
+        assert abs(np.trace(T[a])) < 1e-15
+    gram = np.einsum("aij,bji->ab", T, T)
+    assert np.allclose(gram, 0.5 * np.eye(8), atol=1e-15)
+    want = np.zeros((8, 8, 8))
+    for (a, b, c), v in _F_ABC.items():
+        for (i, j, k), s in (((a, b, c), 1), ((b, c, a), 1), ((c, a, b), 1), ((b, a, c), -1), ((a, c, b), -1),
+                             ((c, b, a), -1)):
+            want[i - 1, j - 1, k - 1] = s * v
+    comm = np.einsum("aij,bjk->abik", T, T) - np.einsum("bij,ajk->abik", T, T)
+    # f^abc = -2 i Tr([T^a, T^b] T^c)
+    f = (-2j * np.einsum("abik,cki->abc", comm, T)).real
+    assert np.allclose(f, want, atol=1e-14)
+    assert np.allclose((-2j * np.einsum("abik,cki->abc", comm, T)).imag, 0, atol=1e-14)

@@ -126,3 +126,25 @@ def test_generator_statistics():
     # one flipped key bit changes about half of the output bits
     flips = np.unpackbits((w[0] ^ w_k[0]).astype(">u4").view(np.uint8)).reshape(n, 32).sum(axis=1)
     assert abs(flips.mean() - 16.0) < 0.1
+
+
+def test_decision_hooks_record_margins_and_flip_outcomes():
+    """The sampler's test hooks: every watched decision's margin has the sign of the outcome
+    taken (the accepted trial >= 0, the rejected ones < 0), and flipping the acceptance of
+    the accepted trial moves x0 to a later trial."""
+    alpha = np.array([0.7, 3.5, 1.9, 6.0])
+    link = np.array([11, 12, 13, 14], dtype=np.uint64)
+    watch = {int(l): [] for l in link}
+    x0 = HB.sample_x0(alpha, 99, link, 5, 1, watch=watch)
+    for i, l in enumerate(link):
+        recs = watch[int(l)]
+        assert recs[0][0] == (int(l), 1, -1) and (recs[0][1] > 0) == (alpha[i] < 2)
+        trials = recs[1:]
+        assert all(m < 0 for _, m in trials[:-1]) and trials[-1][1] >= 0
+        last = trials[-1][0]
+        x1 = HB.sample_x0(alpha, 99, link, 5, 1, flips={last})
+        assert np.array_equal(np.delete(x1, i), np.delete(x0, i))
+        assert x1[i] != x0[i]
+    # the method switch taken the other way also changes the sample
+    x2 = HB.sample_x0(alpha, 99, link, 5, 1, flips={(13, 1, -1)})
+    assert x2[2] != x0[2] and np.array_equal(np.delete(x2, 2), np.delete(x0, 2))

@@ -52,3 +52,24 @@ def test_native_sources_include_nothing_from_the_oracle():
             for line in fh:
                 if line.lstrip().startswith("#include"):
                     assert "oracle" not in line, f"{f}: {line.strip()}"
+
+
+def test_oracle_reads_only_the_input_generator_from_the_package():
+    """The oracle shares no arithmetic with the product: the only product module it may
+    import is the seeded input generator (no tables, constants or helpers)."""
+    odir = os.path.join(ROOT, "oracle")
+    for f in os.listdir(odir):
+        if not f.endswith(".py"):
+            continue
+        path = os.path.join(odir, f)
+        with open(path) as fh:
+            tree = ast.parse(fh.read(), path)
+        for node in ast.walk(tree):
+            names = []
+            if isinstance(node, ast.Import):
+                names = [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom):
+                names = [node.module or ""]
+            for n in names:
+                if n.split(".")[0] == "paper_1209_5942_amd":
+                    assert n == "paper_1209_5942_amd.synth", f"{path} imports {n}"
