@@ -40,8 +40,9 @@
  *     scratch.  Scratch memory comes from the caller's workspace `ws` of
  *     `ws_bytes` bytes, sized by tmqcd_workspace_bytes (tmqcd_cg_batch with
  *     graphs creates a HIP graph, and on the null stream a stream, and destroys
- *     them before it returns).  Problem, option and stats structs are host
- *     memory.
+ *     them before it returns), except for tmqcd_dslash_noalloc, whose scratch is
+ *     a static device array of the library.  Problem, option and stats structs
+ *     are host memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     tmqcd_pack_*, tmqcd_unpack_*, tmqcd_dslash, the forces, the link update,
  *     the reductions, tmqcd_heatbath and tmqcd_overrelax are stream-ordered
@@ -50,7 +51,7 @@
  *     solve has ended.
  *
  * Entry points: sizes and workspaces (*_bytes); packing; tmqcd_dslash (the
- * operators, 1..16 right-hand sides); solvers tmqcd_cg (CG on M^+M or
+ * operators, 1..16 right-hand sides) and tmqcd_dslash_noalloc; solvers tmqcd_cg (CG on M^+M or
  * Mhat^+Mhat, FP64 or mixed precision), tmqcd_cg_batch (several lattices),
  * tmqcd_bicgstab (M or Mhat); HMC pieces tmqcd_force, tmqcd_force_eo,
  * tmqcd_gauge_force, tmqcd_gauge_force_tlsym, tmqcd_update_links,
@@ -84,6 +85,7 @@ extern "C" {
 #define TMQCD_EBREAKDOWN  -5  /* NaN/Inf residual or p^+ A p <= 0 in CG */
 #define TMQCD_EHIP        -6  /* a HIP call failed; see tmqcd_last_hip_error() */
 #define TMQCD_EWORKSPACE  -7  /* ws is NULL or smaller than tmqcd_workspace_bytes() */
+#define TMQCD_ESCRATCH    -8  /* tmqcd_dslash_noalloc: temporaries exceed the library's static scratch */
 
 /* ---- problem description --------------------------------------------------- */
 typedef struct {
@@ -161,6 +163,27 @@ int tmqcd_unpack_spinor(const tmqcd_problem* prob, const void* in_packed, void* 
  * across the right-hand sides. */
 int tmqcd_dslash(const tmqcd_problem* prob, const void* U_packed, const void* in, void* out,
                  int op, int prec, int recon, int nrhs, void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that forbid hipMalloc): tmqcd_dslash with the operator's
+ * temporaries (the odd half fields of MHAT, MHATDAG and MHATDAGMHAT, the full
+ * field of MDAGM; nrhs * tmqcd_workspace_bytes(prob, op, 1 << prec, 1) bytes) in
+ * a static device array of the library, TMQCD_NOALLOC_SCRATCH_BYTES (128 MiB) per
+ * GPU, held from the library's load until the process ends.  Arguments, layouts,
+ * results and errors are those of tmqcd_dslash (the same kernels, bitwise the same
+ * output), minus ws; TMQCD_ESCRATCH when the temporaries do not fit (checked on
+ * the host before any device call; e.g. MHATDAGMHAT in FP64 fits up to 24^3 x 48
+ * with one right-hand side).  The call allocates nothing (no hipMalloc, hipFree
+ * or allocating library routine); on its first call for a device it looks up
+ * that device's address of the array (the device of `stream`, or the current
+ * device for the null stream).  Every call on one GPU uses the same array: calls
+ * that overlap in time on one GPU (different streams, or host threads) race on it
+ * and must be ordered by the caller.  The operators without temporaries
+ * (DSLASH_EO, DSLASH_OE, M, MDAG) do not touch it. */
+#define TMQCD_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+size_t tmqcd_noalloc_scratch_bytes(void);
+int tmqcd_dslash_noalloc(const tmqcd_problem* prob, const void* U_packed, const void* in, void* out, int op,
+                         int prec, int recon, int nrhs, void* stream);
 
 /* ---- the solver: CG on M^+M (full) or Mhat^+ Mhat (even sites) -------------- */
 typedef struct {

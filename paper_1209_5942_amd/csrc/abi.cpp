@@ -515,6 +515,7 @@ const char* tmqcd_error_string(int code) {
         case TMQCD_EBREAKDOWN: return "CG breakdown (non-finite residual or p^+ A p <= 0)";
         case TMQCD_EHIP: return "HIP runtime error (see tmqcd_last_hip_error)";
         case TMQCD_EWORKSPACE: return "workspace missing or smaller than tmqcd_workspace_bytes";
+        case TMQCD_ESCRATCH: return "temporaries larger than the static scratch of tmqcd_dslash_noalloc";
     }
     return "unknown error code";
 }

@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtmqcd.so")
 
 # constants of include/tmqcd.h
-OK, EINVAL, EALIAS, EALIGN, ENOCONV, EBREAKDOWN, EHIP, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, EALIAS, EALIGN, ENOCONV, EBREAKDOWN, EHIP, EWORKSPACE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F64, F32, F16 = 0, 1, 2
 RECON18, RECON12, RECON10, RECON8 = 0, 1, 2, 3
 FULL, EVEN, ODD = 0, 1, 2
@@ -34,7 +34,8 @@ ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_byte
                 "tmqcd_overrelax", "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune",
                 "tmqcd_tune_save", "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set",
                 "tmqcd_tune_mrhs_workspace_bytes", "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2",
-                "tmqcd_dot", "tmqcd_hbm_probe", "tmqcd_error_string", "tmqcd_last_hip_error")
+                "tmqcd_dot", "tmqcd_hbm_probe", "tmqcd_error_string", "tmqcd_last_hip_error",
+                "tmqcd_noalloc_scratch_bytes", "tmqcd_dslash_noalloc")
 
 
 class TmqcdLibraryMissing(RuntimeError):
@@ -126,6 +127,8 @@ def lib():
             "tmqcd_hbm_probe": (I, [V, V, S, I, V, V]),
             "tmqcd_error_string": (ctypes.c_char_p, [I]),
             "tmqcd_last_hip_error": (I, []),
+            "tmqcd_noalloc_scratch_bytes": (S, []),
+            "tmqcd_dslash_noalloc": (I, [P, V, V, V, I, I, I, I, V]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -248,6 +251,14 @@ def dslash(prob: Problem, U_packed, inp, op, prec=F64, recon=RECON18, nrhs=1, ws
         ws = _bytes(workspace_bytes(prob, op, 1 << prec, nrhs))
     _check(lib().tmqcd_dslash(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(inp), _ptr(out), op, prec, recon, nrhs,
                               _ptr(ws), ws.numel(), _stream(stream)), "tmqcd_dslash")
+    return out
+
+
+def dslash_noalloc(prob: Problem, U_packed, inp, out, op, prec=F64, recon=RECON18, nrhs=1, stream=None):
+    """out = op(inp) on packed fields, the temporaries in the library's static scratch (no allocation
+    by the library; `out` is the caller's)."""
+    _check(lib().tmqcd_dslash_noalloc(ctypes.byref(prob.c()), _ptr(U_packed), _ptr(inp), _ptr(out), op, prec, recon,
+                                      nrhs, _stream(stream)), "tmqcd_dslash_noalloc")
     return out
 
 
