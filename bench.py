@@ -43,10 +43,35 @@ CG_ITER_BYTES_PER_SITE = 1536 + 1728 + 1536 + 2496 + 576
 WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.5, kappa=0.16, mu=0.005, seed=24, src_seed=26)
 MIXED = dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.162, mu=0.003, seed=32, src_seed=34)
 HOP_SOURCES = ("hop.hip", "stencil.h", "device.h", "layout.h")
+_HOST = {}   # host fields drawn by one leg and reused by a later one (the 32^3 x 64 links, source, x* stats)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def oracle_error(op, U, b, x, x_star, dims, kappa, mu, bc=(1, 1, 1, -1), U_solve=None):
+    """The C++ oracle's check of a GPU solution x of op x = b: the true relative residual
+    ||b - op x|| / ||b|| on the links the solver used (U_solve, e.g. the oracle's own
+    reconstruction of compressed links; default U) and the relative error ||x - x*|| / ||x*||
+    against the oracle's solution x* (a CG on the same system to 1e-12)."""
+    import numpy as np
+
+    from oracle import cref
+    res = cref.true_rel_residual(op, U if U_solve is None else U_solve, b, x, dims, kappa, mu, bc)
+    out = {"oracle_rel_residual": res}
+    if x_star is not None:
+        out["rel_error_vs_oracle_solution"] = float(np.linalg.norm(x - x_star) / np.linalg.norm(x_star))
+    return out
+
+
+def oracle_solution(op, U, b, dims, kappa, mu, bc=(1, 1, 1, -1), tol=1e-12):
+    """x* = op^{-1} b by the C++ oracle's CG (all host threads), and its statistics (the iterate at
+    which the recursive residual first reached 1e-10 is timed separately)."""
+    from oracle import cref
+    x, st, rc = cref.cg(op, U, b, dims, kappa, mu, bc, tol=tol, report_tol=1e-10)
+    assert rc == 0 and st["true_rel_residual"] <= 2 * tol, st
+    return x, st
 
 
 def hop_source_hash() -> str:
@@ -275,116 +300,205 @@ def main():
 
     # ---------------------------------------------- FP64 vs mixed CG -------
     if not args.no_mixed:
-        m = MIXED
-        pm = T.Problem(m["dims"], m["kappa"], m["mu"], (1, 1, 1, -1))
-        log(f"drawing links {m['dims']}")
-        Um_host = synth.random_links(m["dims"], m["eps"], m["seed"])
-        Um = torch.from_numpy(Um_host).to(dev)
-        gm = {p: T.pack_gauge(pm, Um, p, 0) for p in (T.F64, T.F32, T.F16)}
-        del Um
-        for p in (T.F64, T.F32, T.F16):      # every precision in its tuned launch shapes
-            T.tune(pm, gm[p], p, 0)
-        bm_host = synth.gaussian_spinor(pm.volume // 2, m["src_seed"])
-        bm = T.pack_spinor(pm, torch.from_numpy(bm_host).to(dev), T.F64, T.EVEN)
-        xm = torch.empty(T.spinor_bytes(pm, T.F64, T.EVEN), dtype=torch.uint8, device=dev)
-        wsm = T.workspace(pm, T.MHATDAGMHAT)
-        mixed = {}
-        for p, name in ((T.F64, "fp64"), (T.F32, "mixed_f32"), (T.F16, "mixed_f16")):
-            best = None
-            for _ in range(3):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, st, _ = T.cg(pm, gm, bm, xm, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT,
-                                inner_prec=p, ws=wsm, check_every=16)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                if best is None or dt < best[0]:
-                    best = (dt, st)
-            dt, st = best
-            mixed[name] = {"ms": round(1e3 * dt, 2), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
-                           "true_rel_residual": st["true_rel_residual"], "converged": st["converged"]}
-            log(f"32^3x64 {name}: {1e3 * dt:.1f} ms, {st['iters']} iters, res {st['true_rel_residual']:.2e}")
-        for k in ("mixed_f32", "mixed_f16"):
-            mixed[k]["speedup_vs_fp64"] = round(mixed["fp64"]["ms"] / mixed[k]["ms"], 3)
-        mixed["workload"] = "Mhat^dag Mhat, 32^3x64, kappa 0.162, mu 0.003, eps 0.5, tol 1e-10 (FP64 true residual)"
-        # the same solves with compressed links (REC12, REC10, REC8) in every precision; the FP16-inner
-        # REC8 solution is kept for an oracle check
-        xr8 = torch.empty_like(xm)
-        for rec, rname in ((1, "rec12"), (2, "rec10"), (3, "rec8")):
-            Um = torch.from_numpy(Um_host).to(dev)
-            gr = {p: T.pack_gauge(pm, Um, p, rec) for p in (T.F64, T.F32, T.F16)}
-            del Um
-            for p in (T.F64, T.F32, T.F16):
-                T.tune(pm, gr[p], p, rec)
-            res = {}
-            for p, name in ((T.F64, "fp64"), (T.F32, "mixed_f32"), (T.F16, "mixed_f16")):
-                out_x = xr8 if (rec == 3 and p == T.F16) else xm
-                best = None
-                for _ in range(3):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    _, st, _ = T.cg(pm, gr, bm, out_x, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT,
-                                    inner_prec=p, recon=rec, ws=wsm, check_every=16)
-                    torch.cuda.synchronize()
-                    dt = time.perf_counter() - t0
-                    if best is None or dt < best[0]:
-                        best = (dt, st)
-                dt, st = best
-                res[name] = {"ms": round(1e3 * dt, 2), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
-                             "true_rel_residual": st["true_rel_residual"], "converged": st["converged"],
-                             "speedup_vs_fp64_rec18": round(mixed["fp64"]["ms"] / (1e3 * dt), 3)}
-                log(f"32^3x64 {rname} {name}: {1e3 * dt:.1f} ms, {st['iters']} iters")
-            mixed[rname] = res
-            del gr
-        # the REC18 FP16-inner solution again, for the oracle check below
-        T.cg(pm, gm, bm, xm, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT, inner_prec=T.F16, ws=wsm,
-             check_every=16)
-        result["cg_32x32x32x64"] = mixed
-        if not args.no_oracle:   # the last solution is the FP16-inner one
-            from oracle import dirac as D
-            log("oracle check of the 32^3x64 FP16-inner solution")
-            xs = T.unpack_spinor(pm, xm, T.F64, T.EVEN).cpu().numpy()
-            Am = lambda v: D.apply_MhatdagMhat(Um_host, v, m["dims"], m["kappa"], m["mu"], (1, 1, 1, -1))
-            mixed["mixed_f16"]["oracle_rel_residual"] = D.true_rel_residual(Am, bm_host, xs)
-            xs8 = T.unpack_spinor(pm, xr8, T.F64, T.EVEN).cpu().numpy()
-            mixed["rec8"]["mixed_f16"]["oracle_rel_residual"] = D.true_rel_residual(Am, bm_host, xs8)
-        del gm, bm, xm, xr8, wsm, Um_host
+        result["cg_32x32x32x64"] = bench_mixed(T, synth, dev, not args.no_oracle)
 
     if not args.no_extras:
         result["small_4x4x4x4"] = bench_small(T, synth, dev, not args.no_oracle)
         result["dslash_sizes_f64_rec18"] = bench_sizes(T, dev)
         result["multi_rhs_24x24x24x48"] = bench_multi_rhs(T, prob, U, dev)
-        result["batch_cg"] = bench_batch(T, synth, dev)
+        result["cg_multi_rhs_24x24x24x48"] = bench_cg_mrhs(T, synth, U, dev, not args.no_oracle)
+        result["batch_cg"] = bench_batch(T, synth, dev, not args.no_oracle)
         result["hmc_16x16x16x32"] = bench_hmc(T, synth, dev)
         result["heatbath"] = bench_heatbath(T, synth, dev)
 
     # ------------------------------------- oracle check and CPU baseline ---
     if not args.no_oracle:
-        from threadpoolctl import threadpool_limits
-
-        from oracle import dirac as D
-        log("oracle check of the 24^3x48 solution")
+        from oracle import cref
+        U64 = U.reshape(-1, 4, 3, 3)
+        kap, mu_ = w["kappa"], w["mu"]
+        log("oracle solution x* on 24^3x48 and CPU baseline (C++ oracle)")
+        x_star, ost = oracle_solution("MHATDAGMHAT", U64, b, dims, kap, mu_)
         x = T.unpack_spinor(prob, x_dev, T.F64, T.EVEN).cpu().numpy()
-        A = lambda v: D.apply_MhatdagMhat(U, v, dims, w["kappa"], w["mu"], (1, 1, 1, -1))
-        result["cg_fp64_24x24x24x48"]["oracle_rel_residual"] = D.true_rel_residual(A, b, x)
-        Ahat = lambda v: D.apply_Mhat(U, v, dims, w["kappa"], w["mu"], (1, 1, 1, -1))
+        result["cg_fp64_24x24x24x48"].update(oracle_error("MHATDAGMHAT", U64, b, x, x_star, dims, kap, mu_))
+        # BiCGStab and CGNE solve Mhat x = b: x* = (Mhat^dag Mhat)^{-1} Mhat^dag b, all by the oracle
+        bh = cref.apply("MHATDAG", U64, b, dims, kap, mu_, (1, 1, 1, -1))
+        xh_star, _ = oracle_solution("MHATDAGMHAT", U64, bh, dims, kap, mu_)
         for name, xd in (("bicgstab", xb_dev), ("cgne", xc_dev)):
             xh = T.unpack_spinor(prob, xd, T.F64, T.EVEN).cpu().numpy()
-            result["bicgstab_24x24x24x48"][f"{name}_oracle_rel_residual_of_Mhat_x_eq_b"] = D.true_rel_residual(Ahat, b, xh)
-        log("CPU baseline: oracle hop")
-        psi = synth.gaussian_spinor(prob.volume, 27)
-        with threadpool_limits(1):
-            reps = 5
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                D.hop(U, psi, dims, (1, 1, 1, -1))
-            dt = time.perf_counter() - t0
-        result["cpu_baseline"] = {
-            "value": round(reps * prob.volume * BYTES_PER_SITE[(0, 0)] / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{reps} whole-lattice hops H psi of the FP64 NumPy oracle at 24^3x48 "
-                      f"({reps * prob.volume} output sites x 1536 B), {dt:.1f} s, one thread"}
+            e = oracle_error("MHAT", U64, b, xh, xh_star, dims, kap, mu_)
+            result["bicgstab_24x24x24x48"][f"{name}_oracle_rel_residual_of_Mhat_x_eq_b"] = e["oracle_rel_residual"]
+            result["bicgstab_24x24x24x48"][f"{name}_rel_error_vs_oracle_solution"] = e["rel_error_vs_oracle_solution"]
+        result["cpu_baseline"] = cpu_baseline(T, synth, U64, b, ost, cg_seconds=elapsed / args.steps)
     print(json.dumps(result), flush=True)
+    # leave at once: nothing below needs the interpreter's teardown (GPU buffers, thread pools)
+    sys.stdout.flush()
+    sys.stderr.flush()
+    os._exit(0)
+
+
+def cpu_baseline(T, synth, U64, b, ost, cg_seconds):
+    """The C++ FP64 oracle on the host cores: `value` is its Dslash GB/s inside its CG on Mhat^dag Mhat
+    at 24^3 x 48 (the bench step's solve, in the same unit as `value`: 1536 B per hop output site, four
+    hops per iteration), timed up to the iterate that first reached 1e-10 (the iterations of the x*
+    solve above).  Beside it: the hop, Mhat and Mhat^dag Mhat at 4^4, 24^3 x 48 and 32^3 x 64 with all
+    threads and with one, CG time to 1e-10 at 4^4 (all threads and one) and 32^3 x 64 (all threads,
+    the x* solve of the mixed-precision leg), and two hops of the NumPy oracle (one thread)."""
+    import platform
+
+    import numpy as np
+
+    from oracle import cref
+    from oracle import dirac as D
+    threads = cref.threads()
+    cpu_model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            names = [l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")]
+        cpu_model = names[0] if names else cpu_model
+    except OSError:
+        pass
+    bc = (1, 1, 1, -1)
+
+    def timed(fn, reps):
+        if reps > 1:
+            fn()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        return (time.perf_counter() - t0) / reps
+
+    vh1 = U64.shape[0] // 2
+    cg_gbs = ost["report_iters"] * 4 * vh1 * BYTES_PER_SITE[(0, 0)] / ost["report_seconds"] / 1e9
+    out = {"value": round(cg_gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": (f"the C++ FP64 oracle's CG on Mhat^dag Mhat at 24^3x48 (kappa 0.16, mu 0.005, the bench "
+                      f"step's links and source) up to 1e-10: {ost['report_iters']} iterations in "
+                      f"{ost['report_seconds']:.1f} s on {threads} threads (4 hops of 1536 B per even site each); "
+                      f"the GPU step takes {1e3 * cg_seconds:.1f} ms"),
+           "host": {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "threads_used": threads,
+                    "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "cpu_model": cpu_model},
+           "cg_to_1e-10_24x24x24x48": {"threads": threads, "iters": ost["report_iters"],
+                                       "seconds": round(ost["report_seconds"], 3),
+                                       "true_rel_residual": ost["report_true_rel_residual"]}}
+    cfgs = [("4x4x4x4", (4, 4, 4, 4), 0.3, 0.15, 0.01, 1, 2), ("24x24x24x48", (24, 24, 24, 48), None, 0.16, 0.005, 0, 0),
+            ("32x32x32x64", MIXED["dims"], MIXED["eps"], MIXED["kappa"], MIXED["mu"], MIXED["seed"], MIXED["src_seed"])]
+    for name, dims, eps, kappa, mu, seed, src_seed in cfgs:
+        ost_n = None
+        if eps is None:
+            U, src = U64, b
+        elif name == "32x32x32x64" and "mixed" in _HOST:
+            U, src, ost_n = _HOST["mixed"]
+        else:
+            log(f"CPU baseline {name}: drawing links")
+            U = synth.random_links(dims, eps, seed).reshape(-1, 4, 3, 3)
+            src = synth.gaussian_spinor(U.shape[0] // 2, src_seed)
+        vh = U.shape[0] // 2
+        reps = 200 if vh < 1000 else 1
+        rec = {}
+        for nt in sorted({threads, 1}, reverse=True):
+            cref.set_threads(nt)
+            t_hop = timed(lambda: cref.apply("HOP_OE", U, src, dims, kappa, mu, bc), reps)
+            t_mhat = timed(lambda: cref.apply("MHAT", U, src, dims, kappa, mu, bc), reps)
+            t_nrm = timed(lambda: cref.apply("MHATDAGMHAT", U, src, dims, kappa, mu, bc), reps)
+            rec[f"threads_{nt}"] = {"hop_ms": round(1e3 * t_hop, 4), "hop_GB_s": round(vh * 1536 / t_hop / 1e9, 3),
+                                    "mhat_ms": round(1e3 * t_mhat, 4), "mhatdagmhat_ms": round(1e3 * t_nrm, 4)}
+            if vh < 1000:
+                _, st = oracle_solution("MHATDAGMHAT", U, src, dims, kappa, mu, bc, tol=1e-10)
+                rec[f"threads_{nt}"]["cg_to_1e-10"] = {"iters": st["iters"], "seconds": round(st["seconds"], 4),
+                                                       "true_rel_residual": st["true_rel_residual"]}
+            elif ost_n is not None and nt == threads:   # the x* solve of the mixed-precision leg, up to 1e-10
+                rec[f"threads_{nt}"]["cg_to_1e-10"] = {"iters": ost_n["report_iters"],
+                                                       "seconds": round(ost_n["report_seconds"], 3),
+                                                       "true_rel_residual": ost_n["report_true_rel_residual"]}
+        cref.set_threads(threads)
+        out[name] = rec
+    # the NumPy definitional oracle, for information: two whole-lattice hops at 24^3 x 48, one thread
+    from threadpoolctl import threadpool_limits
+    psi = synth.gaussian_spinor(U64.shape[0], 27)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        for _ in range(2):
+            D.hop(U64, psi, (24, 24, 24, 48), bc)
+        dt = (time.perf_counter() - t0) / 2
+    out["numpy_oracle_hop_24x24x24x48"] = {"threads": 1, "seconds": round(dt, 2),
+                                           "GB_s": round(U64.shape[0] * 1536 / dt / 1e9, 4)}
+    return out
+
+
+
+def bench_mixed(T, synth, dev, check):
+    """32^3 x 64 (kappa 0.162, mu 0.003, eps 0.5): CG on Mhat^dag Mhat to a true FP64 residual of 1e-10
+    with FP64, FP32-inner and FP16-inner hops, for each link encoding (REC18/12/10/8).  Each solve is the
+    best of three; its solution is checked by the C++ oracle: the true residual on the links the solver
+    used (for REC10/REC8 the oracle's own reconstruction from its encoding of the same links) and the
+    relative error against the oracle's solution x* (CG to 1e-12 on the uncompressed links)."""
+    import numpy as np
+    import torch
+    m = MIXED
+    dims, kappa, mu = m["dims"], m["kappa"], m["mu"]
+    pm = T.Problem(dims, kappa, mu, (1, 1, 1, -1))
+    log(f"drawing links {dims}")
+    Um_host = synth.random_links(dims, m["eps"], m["seed"]).reshape(-1, 4, 3, 3)
+    bm_host = synth.gaussian_spinor(pm.volume // 2, m["src_seed"])
+    bm = T.pack_spinor(pm, torch.from_numpy(bm_host).to(dev), T.F64, T.EVEN)
+    xm = torch.empty(T.spinor_bytes(pm, T.F64, T.EVEN), dtype=torch.uint8, device=dev)
+    wsm = T.workspace(pm, T.MHATDAGMHAT)
+    x_star, ost = None, None
+    if check:
+        log("oracle solution x* on 32^3x64 (C++ oracle, CG to 1e-12)")
+        x_star, ost = oracle_solution("MHATDAGMHAT", Um_host, bm_host, dims, kappa, mu)
+    _HOST["mixed"] = (Um_host, bm_host, ost)
+    out = {"workload": "Mhat^dag Mhat, 32^3x64, kappa 0.162, mu 0.003, eps 0.5, tol 1e-10 (FP64 true residual)"}
+    if ost is not None:
+        out["oracle_solution"] = {"iters": ost["iters"], "true_rel_residual": ost["true_rel_residual"],
+                                  "seconds": round(ost["seconds"], 2)}
+    fp64_ms = None
+    for rec, rname in ((0, "rec18"), (1, "rec12"), (2, "rec10"), (3, "rec8")):
+        Um = torch.from_numpy(Um_host).to(dev)
+        gr = {p: T.pack_gauge(pm, Um, p, rec) for p in (T.F64, T.F32, T.F16)}
+        del Um
+        for p in (T.F64, T.F32, T.F16):      # every precision in its tuned launch shapes
+            T.tune(pm, gr[p], p, rec)
+        U_solve = None
+        if check and rec != 0:               # the links the solver sees, rebuilt by the oracle
+            from oracle import compress as OC
+            U_solve = {1: lambda u: OC.rec12_decode(u[..., :2, :]), 2: lambda u: OC.rec10_decode(OC.rec10_encode(u)),
+                       3: lambda u: OC.rec8_decode(OC.rec8_encode(u))}[rec](Um_host)
+        res = {}
+        for p, name in ((T.F64, "fp64"), (T.F32, "mixed_f32"), (T.F16, "mixed_f16")):
+            best = None
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st, _ = T.cg(pm, gr, bm, xm, x_is_zero=True, tol=1e-10, max_iter=20000, op=T.MHATDAGMHAT,
+                                inner_prec=p, recon=rec, ws=wsm, check_every=16)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if best is None or dt < best[0]:
+                    best = (dt, st)
+            dt, st = best
+            if fp64_ms is None:
+                fp64_ms = 1e3 * dt
+            r = {"ms": round(1e3 * dt, 2), "iters": st["iters"], "reliable_updates": st["reliable_updates"],
+                 "true_rel_residual": st["true_rel_residual"], "converged": st["converged"],
+                 "speedup_vs_fp64_rec18": round(fp64_ms / (1e3 * dt), 3)}
+            if check:
+                xs = T.unpack_spinor(pm, xm, T.F64, T.EVEN).cpu().numpy()
+                r.update(oracle_error("MHATDAGMHAT", Um_host, bm_host, xs, x_star, dims, kappa, mu, U_solve=U_solve))
+                if U_solve is not None:
+                    r["oracle_rel_residual_uncompressed_links"] = oracle_error(
+                        "MHATDAGMHAT", Um_host, bm_host, xs, None, dims, kappa, mu)["oracle_rel_residual"]
+            res[name] = r
+            log(f"32^3x64 {rname} {name}: {1e3 * dt:.1f} ms, {st['iters']} iters, "
+                f"oracle res {r.get('oracle_rel_residual', float('nan')):.2e}, "
+                f"err {r.get('rel_error_vs_oracle_solution', float('nan')):.2e}")
+        for k in ("mixed_f32", "mixed_f16"):
+            res[k]["speedup_vs_fp64"] = round(res["fp64"]["ms"] / res[k]["ms"], 3)
+        if rec == 0:
+            out.update(res)                   # REC18 at the top level, as before
+        else:
+            out[rname] = res
+        del gr, U_solve
+    return out
 
 
 def kernel_only(T, prob, gauges, b, dev):
@@ -635,40 +749,106 @@ def bench_multi_rhs(T, prob, U, dev):
     return out
 
 
+def bench_cg_mrhs(T, synth, U, dev, check):
+    """The 12 spin-colour point sources at the origin on 24^3 x 48 (the step's links, kappa 0.155, mu 0.01):
+    one 12-RHS FP64 CG on Mhat^dag Mhat to 1e-10 (every operator application one multi-RHS launch) against
+    12 single-RHS solves, both in their tuned launch shapes; each column's true residual recomputed by the
+    C++ oracle, and column 0 against the oracle's own solution."""
+    import numpy as np
+    import torch
+    log("12-RHS CG, point sources")
+    dims, kappa, mu = WORKLOAD["dims"], 0.155, 0.01
+    prob = T.Problem(dims, kappa, mu, (1, 1, 1, -1))
+    vh = prob.volume // 2
+    b = synth.point_sources(vh, 0)
+    g = T.pack_gauge(prob, torch.from_numpy(U).to(dev))
+    T.tune(prob, g, T.F64, T.RECON18)
+    T.tune_mrhs(prob, g, 12, T.F64, T.RECON18)
+    bp = T.pack_spinor(prob, torch.from_numpy(b).to(dev), T.F64, T.EVEN, nrhs=12)
+    fe = T.spinor_bytes(prob, T.F64, T.EVEN)
+    x = torch.empty(12 * fe, dtype=torch.uint8, device=dev)
+    ws12 = T.workspace(prob, T.MHATDAGMHAT, 1, 12)
+    ws1 = T.workspace(prob, T.MHATDAGMHAT, 1)
+
+    def multi():
+        return T.cg(prob, {T.F64: g}, bp, x, x_is_zero=True, tol=1e-10, op=T.MHATDAGMHAT, nrhs=12, ws=ws12,
+                    check_every=16)[1]
+
+    def singles():
+        return [T.cg(prob, {T.F64: g}, bp[k * fe:(k + 1) * fe], x[k * fe:(k + 1) * fe], x_is_zero=True, tol=1e-10,
+                     op=T.MHATDAGMHAT, ws=ws1, check_every=16)[1] for k in range(12)]
+
+    res = {}
+    for name, fn in (("twelve_single_solves", singles), ("multi_rhs_solve", multi)):
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = (dt, st) if best is None or dt < best[0] else best
+        res[name + "_ms"] = round(1e3 * best[0], 2)
+        res[name + "_iters"] = [s["iters"] for s in best[1]]
+        res[name + "_hop_launches"] = best[1][0]["hop_launches"] if name == "multi_rhs_solve" else \
+            sum(s["hop_launches"] for s in best[1])
+    res["speedup"] = round(res["twelve_single_solves_ms"] / res["multi_rhs_solve_ms"], 3)
+    log(f"12-RHS CG {res['multi_rhs_solve_ms']} ms vs 12 solves {res['twelve_single_solves_ms']} ms")
+    if check:    # x holds the multi-RHS solution (its solve ran last)
+        from oracle import cref
+        xs = T.unpack_spinor(prob, x, T.F64, T.EVEN, 12).cpu().numpy()
+        U64 = U.reshape(-1, 4, 3, 3)
+        res["oracle_rel_residual"] = [cref.true_rel_residual("MHATDAGMHAT", U64, b[k], xs[k], dims, kappa, mu,
+                                                             (1, 1, 1, -1)) for k in range(12)]
+        x0, _ = oracle_solution("MHATDAGMHAT", U64, b[0], dims, kappa, mu)
+        res["rel_error_vs_oracle_solution_column0"] = float(np.linalg.norm(xs[0] - x0) / np.linalg.norm(x0))
+    res["workload"] = ("Mhat^dag Mhat x_k = b_k for the 12 spin-colour point sources at the origin, 24^3x48, "
+                       "eps 0.5 links, kappa 0.155, mu 0.01, FP64, tol 1e-10")
+    return res
+
+
 def bench_small(T, synth, dev, check):
-    """4^4 (eps 0.3, kappa 0.15, mu 0.01): every operator once (latency-bound: microseconds per call) and FP64 CG
-    on M^dag M and Mhat^dag Mhat to 1e-10, with the oracle's residuals."""
+    """4^4 (eps 0.3, kappa 0.15, mu 0 and 0.01): every operator once (latency-bound: microseconds per call)
+    and FP64 CG on M^dag M and Mhat^dag Mhat to 1e-10, each solution checked by the oracle: its true
+    residual and its error against the dense LU solution."""
+    import numpy as np
     import torch
     log("4^4 operators and solves")
-    dims, kappa, mu, bc = (4, 4, 4, 4), 0.15, 0.01, (1, 1, 1, -1)
-    prob = T.Problem(dims, kappa, mu, bc)
+    dims, kappa, bc = (4, 4, 4, 4), 0.15, (1, 1, 1, -1)
     U = synth.random_links(dims, 0.3, 1)
-    g = T.pack_gauge(prob, torch.from_numpy(U).to(dev))
-    out = {"op_us": {}}
-    for name, op in T.OPS.items():
-        sub_in, _ = T.OP_SUBSETS[op]
-        n = prob.volume // (1 if sub_in == T.FULL else 2)
-        src = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(n, 3)).to(dev), T.F64, sub_in)
-        ws = T.workspace(prob, op, 1)
-        out["op_us"][name] = round(_events_time(lambda: T.dslash(prob, g, src, op, ws=ws), 50) * 1e6, 2)
-    for op, name in ((T.MDAGM, "cg_MdagM"), (T.MHATDAGMHAT, "cg_MhatdagMhat")):
-        n = prob.volume if op == T.MDAGM else prob.volume // 2
-        b = synth.gaussian_spinor(n, 4)
-        bp = T.pack_spinor(prob, torch.from_numpy(b).to(dev), T.F64, T.FULL if op == T.MDAGM else T.EVEN)
-        T.cg(prob, {T.F64: g}, bp, tol=1e-10, op=op)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, st, _ = T.cg(prob, {T.F64: g}, bp, tol=1e-10, op=op)
-        torch.cuda.synchronize()
-        rec = {"us": round((time.perf_counter() - t0) * 1e6, 1), "iters": st["iters"],
-               "true_rel_residual": st["true_rel_residual"]}
-        if check:
-            from oracle import dirac as D
-            xs = T.unpack_spinor(prob, x, T.F64, T.FULL if op == T.MDAGM else T.EVEN).cpu().numpy()
-            A = (lambda v: D.apply_MdagM(U, v, dims, kappa, mu, bc)) if op == T.MDAGM else \
-                (lambda v: D.apply_MhatdagMhat(U, v, dims, kappa, mu, bc))
-            rec["oracle_rel_residual"] = D.true_rel_residual(A, b, xs)
-        out[name] = rec
+    out = {}
+    for mu in (0.0, 0.01):
+        prob = T.Problem(dims, kappa, mu, bc)
+        g = T.pack_gauge(prob, torch.from_numpy(U).to(dev))
+        rec = {"op_us": {}}
+        for name, op in T.OPS.items():
+            sub_in, _ = T.OP_SUBSETS[op]
+            n = prob.volume // (1 if sub_in == T.FULL else 2)
+            src = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(n, 3)).to(dev), T.F64, sub_in)
+            ws = T.workspace(prob, op, 1)
+            rec["op_us"][name] = round(_events_time(lambda: T.dslash(prob, g, src, op, ws=ws), 50) * 1e6, 2)
+        for op, name in ((T.MDAGM, "cg_MdagM"), (T.MHATDAGMHAT, "cg_MhatdagMhat")):
+            n = prob.volume if op == T.MDAGM else prob.volume // 2
+            b = synth.gaussian_spinor(n, 4)
+            bp = T.pack_spinor(prob, torch.from_numpy(b).to(dev), T.F64, T.FULL if op == T.MDAGM else T.EVEN)
+            T.cg(prob, {T.F64: g}, bp, tol=1e-10, op=op)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st, _ = T.cg(prob, {T.F64: g}, bp, tol=1e-10, op=op)
+            torch.cuda.synchronize()
+            r = {"us": round((time.perf_counter() - t0) * 1e6, 1), "iters": st["iters"],
+                 "true_rel_residual": st["true_rel_residual"]}
+            if check:
+                from oracle import dirac as D
+                xs = T.unpack_spinor(prob, x, T.F64, T.FULL if op == T.MDAGM else T.EVEN).cpu().numpy()
+                A = (lambda v: D.apply_MdagM(U, v, dims, kappa, mu, bc)) if op == T.MDAGM else \
+                    (lambda v: D.apply_MhatdagMhat(U, v, dims, kappa, mu, bc))
+                r["oracle_rel_residual"] = D.true_rel_residual(A, b, xs)
+                dense = D.dense_matrix(A, n)
+                x_lu = np.linalg.solve(dense, b.reshape(-1)).reshape(b.shape)
+                r["rel_error_vs_dense_lu"] = float(np.linalg.norm(xs - x_lu) / np.linalg.norm(x_lu))
+            rec[name] = r
+        out[f"mu_{mu:g}"] = rec
     return out
 
 
@@ -698,17 +878,20 @@ def bench_sizes(T, dev):
     return out
 
 
-def bench_batch(T, synth, dev):
-    """8^4 + 12^3x24 + 16^3x32 (kappa 0.155, mu 0.01): one batched solve (graph / eager) vs three solves."""
+def bench_batch(T, synth, dev, check=True):
+    """8^4 + 12^3x24 + 16^3x32 (kappa 0.155, mu 0.01): one batched solve (graph / eager) vs three solves;
+    the batched solutions checked by the C++ oracle (true residual, error against its own solution)."""
     import torch
     log("batched CG over three lattices")
     dims_list = [(8, 8, 8, 8), (12, 12, 12, 24), (16, 16, 16, 32)]
     probs = [T.Problem(d, 0.155, 0.01, (1, 1, 1, -1)) for d in dims_list]
-    gauges, bs = [], []
+    gauges, bs, hostf = [], [], []
     for k, (pr, d) in enumerate(zip(probs, dims_list)):
-        gauges.append(T.pack_gauge(pr, torch.from_numpy(synth.random_links(d, 0.4, 60 + k)).to(dev)))
-        bs.append(T.pack_spinor(pr, torch.from_numpy(synth.gaussian_spinor(pr.volume // 2, 70 + k)).to(dev),
-                                T.F64, T.EVEN))
+        Uh = synth.random_links(d, 0.4, 60 + k)
+        bh = synth.gaussian_spinor(pr.volume // 2, 70 + k)
+        hostf.append((Uh.reshape(-1, 4, 3, 3), bh))
+        gauges.append(T.pack_gauge(pr, torch.from_numpy(Uh).to(dev)))
+        bs.append(T.pack_spinor(pr, torch.from_numpy(bh).to(dev), T.F64, T.EVEN))
     side = torch.cuda.Stream()
     res = {}
     with torch.cuda.stream(side):
@@ -733,6 +916,14 @@ def bench_batch(T, synth, dev):
             if name == "graph_batch":
                 res["iters"] = [st["iters"] for st in r[1]]
                 res["true_rel_residual"] = [st["true_rel_residual"] for st in r[1]]
+                sols = [T.unpack_spinor(pr, x, T.F64, T.EVEN, stream=side).cpu().numpy() for pr, x in zip(probs, xs)]
+    if check:
+        errs = []
+        for pr, (Uh, bh), xh in zip(probs, hostf, sols):
+            xst, _ = oracle_solution("MHATDAGMHAT", Uh, bh, pr.dims, pr.kappa, pr.mu)
+            errs.append(oracle_error("MHATDAGMHAT", Uh, bh, xh, xst, pr.dims, pr.kappa, pr.mu))
+        res["oracle_rel_residual"] = [e["oracle_rel_residual"] for e in errs]
+        res["rel_error_vs_oracle_solution"] = [e["rel_error_vs_oracle_solution"] for e in errs]
     res["sites"] = sum(pr.volume for pr in probs)
     res["speedup_graph_vs_three"] = round(res["three_solves_ms"] / res["graph_batch_ms"], 3)
     return res

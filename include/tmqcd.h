@@ -55,7 +55,7 @@
  * Mhat^+Mhat, FP64 or mixed precision), tmqcd_cg_batch (several lattices),
  * tmqcd_bicgstab (M or Mhat); HMC pieces tmqcd_force, tmqcd_force_eo,
  * tmqcd_gauge_force, tmqcd_gauge_force_tlsym, tmqcd_update_links,
- * tmqcd_plaquette, tmqcd_rectangle, tmqcd_momentum_norm2, tmqcd_dot; pure-gauge
+ * tmqcd_plaquette, tmqcd_rectangle, tmqcd_momentum_norm2, tmqcd_dot, tmqcd_delta_h; pure-gauge
  * updates tmqcd_heatbath and tmqcd_overrelax; the autotuner (tmqcd_tune*);
  * tmqcd_hbm_probe; errors (tmqcd_error_string, tmqcd_last_hip_error).
  *   - No exceptions cross the interface; functions return TMQCD_OK (0) or a
@@ -129,12 +129,19 @@ typedef struct {
 #define TMQCD_MHATDAGMHAT   7  /* even:  Mhat^+ Mhat                          */
 
 /* ---- size queries (host only, never fail: 0 means invalid arguments) -------- */
+/* Bytes of a packed gauge field and of nrhs packed spinor fields.  The FP64
+ * sizes per site are the paper's Table 3 (its memory-requirements section, 4.1):
+ * 576 / 384 / 320 / 256 B of links for REC18 / 12 / 10 / 8 and 192 B per spinor
+ * site, plus padding of each array to a wavefront of sites and 256 bytes. */
 size_t tmqcd_gauge_bytes(const tmqcd_problem* prob, int prec, int recon);
 size_t tmqcd_spinor_bytes(const tmqcd_problem* prob, int prec, int subset, int nrhs);
 /* Workspace for tmqcd_dslash (op), tmqcd_cg (op = TMQCD_MDAGM or
- * TMQCD_MHATDAGMHAT) and the reductions of the HMC helpers (op = -1).  prec_mask:
- * bit (1 << prec) for every storage precision the call will use (for CG: F64 and
- * the inner one). */
+ * TMQCD_MHATDAGMHAT; nrhs > 1 for the multi-RHS solve) and the reductions of the
+ * HMC helpers (op = -1).  prec_mask: bit (1 << prec) for every storage precision
+ * the call will use (for CG: F64 and the inner one).  The temporaries are those
+ * of the operator compositions of the paper's section 2.1 (one odd half field per
+ * right-hand side between the two hops of Mhat, a full field between M and M^+)
+ * and, for CG, the solver's vectors r, p, A p and its reduction partials. */
 size_t tmqcd_workspace_bytes(const tmqcd_problem* prob, int op, int prec_mask, int nrhs);
 
 /* ---- layout conversion (the paper's transparent AoS <-> SoA conversion) ----- */
@@ -186,6 +193,13 @@ int tmqcd_dslash_noalloc(const tmqcd_problem* prob, const void* U_packed, const 
                          int prec, int recon, int nrhs, void* stream);
 
 /* ---- the solver: CG on M^+M (full) or Mhat^+ Mhat (even sites) -------------- */
+/* The paper's section 2.1: D phi = psi is solved with a Krylov method (CG or
+ * BiCGStab) because D is a large sparse matrix whose matrix-vector product is
+ * repeated at every iteration; CG needs a hermitian positive-definite operator,
+ * here the normal operator M^+M, or Mhat^+Mhat of the even-odd Schur complement
+ * (the same section's even-odd preconditioning).  Mixed precision (an FP32 or
+ * FP16 inner operator inside an FP64 defect correction) is the mixed solver the
+ * paper's conclusions (section 6) leave to future work. */
 typedef struct {
     double  tol;             /* stop when ||b - A x||_2 / ||b||_2 <= tol, recomputed in FP64 */
     int32_t max_iter;        /* cap on (inner) CG iterations */
@@ -204,26 +218,46 @@ typedef struct {
                                 every iteration.  Results are bitwise those of the eager launches.
                                 With 1 on the null stream the solve runs on a blocking stream of its
                                 own. */
+    int32_t nrhs;            /* tmqcd_cg: right-hand sides solved together (0 or 1: one; up to 16).
+                                With nrhs > 1 (FP64 only: inner_prec = TMQCD_F64, use_graph 0 or -1)
+                                b and x hold nrhs packed fields one after the other, stats points at
+                                nrhs structs, and every operator application is one multi-RHS launch
+                                reading each link once for all columns; each column has its own FP64
+                                scalars, residuals and stop test (the paper's section 2.1: a
+                                propagator needs one inversion per spin-colour source). */
 } tmqcd_cg_opts;
 
 typedef struct {
-    int32_t iters;             /* CG iterations (inner iterations for mixed precision) */
-    int32_t reliable_updates;  /* FP64 residual recomputations inside the solve */
+    int32_t iters;             /* CG iterations, all precisions */
+    int32_t reliable_updates;  /* outer cycles: FP64 true-residual recomputations that ended an inner
+                                  cycle (the last one confirms convergence) */
     int32_t converged;         /* 1 if the true residual met tol */
-    int32_t hop_launches;      /* hop kernels launched (for bandwidth accounting) */
+    int32_t hop_launches;      /* hop kernels launched (for bandwidth accounting; with nrhs > 1 the
+                                  multi-RHS launches, shared by the columns) */
     double  true_rel_residual; /* ||b - A x|| / ||b|| in FP64 at exit */
     double  iter_rel_residual; /* recursively updated residual at exit */
     double  seconds;           /* host wall time of the call */
+    int32_t inner_iters;       /* iterations whose operator ran in the inner (FP32 / FP16) precision:
+                                  iters for a mixed solve, 0 for FP64 */
+    int32_t reserved;          /* 0 */
 } tmqcd_cg_stats;
 
-/* Solve A x = b, A = op.  b and x are packed FP64 fields (full for MDAGM, even
- * for MHATDAGMHAT); x may not overlap b.  U_packed[p] is the gauge field packed
- * at precision p (index TMQCD_F64/F32/F16) with opts->recon; U_packed[TMQCD_F64]
- * is always required, U_packed[inner_prec] for mixed precision; unused entries
- * may be NULL.  Mixed precision runs the inner CG with FP32 or FP16 Dslash
- * storage and FP64 reductions, and restarts it with an FP64 residual b - A x
- * whenever the iterated residual dropped by reliable_delta (defect correction
- * with reliable updates).  Returns TMQCD_ENOCONV if max_iter was reached. */
+/* Solve A x = b, A = op (the paper's section 2.1, CG on the normal operator).
+ * b and x are packed FP64 fields (full for MDAGM, even for MHATDAGMHAT; opts->nrhs
+ * of them one after the other for the multi-RHS solve); x may not overlap b.
+ * U_packed[p] is the gauge field packed at precision p (index TMQCD_F64/F32/F16)
+ * with opts->recon; U_packed[TMQCD_F64] is always required, U_packed[inner_prec]
+ * for mixed precision; unused entries may be NULL.  Mixed precision runs the inner
+ * CG with FP32 or FP16 Dslash storage and FP64 reductions, and restarts it with an
+ * FP64 residual b - A x whenever the iterated residual dropped by reliable_delta
+ * (defect correction with reliable updates).  stats: host memory, one struct (nrhs
+ * structs for nrhs > 1).  ws: tmqcd_workspace_bytes(prob, op, 1 | 1 << inner_prec,
+ * nrhs) bytes of device memory, 256-byte aligned, overlapping neither b nor x.
+ * Returns TMQCD_ENOCONV if max_iter was reached (x holds the last iterate),
+ * TMQCD_EBREAKDOWN on a non-finite residual or p^+ A p <= 0 (for nrhs > 1: in some
+ * column; the other columns are solved), TMQCD_EINVAL / EALIGN / EALIAS /
+ * EWORKSPACE on bad arguments (checked before any device call), TMQCD_EHIP if a
+ * HIP call failed. */
 int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const void* b, void* x,
              const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes,
              void* stream);
@@ -246,7 +280,10 @@ int tmqcd_bicgstab(const tmqcd_problem* prob, const void* U_packed, const void* 
                    const tmqcd_cg_opts* opts, tmqcd_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- several lattices at once ------------------------------------------------ */
-/* FP64 CG on Mhat^+ Mhat for n (1..8) lattices of any volumes in one solve:
+/* The paper's section 2.1 notes that thermal lattices (small temporal extent)
+ * are simulated with less parallelism and need many parameter values and high
+ * statistics: several such lattices are solved together here.
+ * FP64 CG on Mhat^+ Mhat for n (1..8) lattices of any volumes in one solve:
  * every stage of an iteration is a single grid-stride launch over the tiles of
  * all lattices (each with its own solver state; converged lattices are skipped),
  * and with use_graph = 1 one iteration is captured once in a hipGraph and
@@ -264,16 +301,25 @@ int tmqcd_cg_batch(int n, const tmqcd_problem* probs, const void* const* U_packe
 /* ---- the fermion force -------------------------------------------------------- */
 /* The gradient G^a_mu(x) = dS_f/dw^a of S_f = phi^+ (M^+ M)^{-1} phi with respect
  * to U_mu(x) -> exp(i w^a T^a) U_mu(x), T^a = lambda^a / 2, given X = (M^+ M)^{-1} phi
- * and Y = M X as packed FP64 full fields (the paper's force section: the fermion
- * force needs one inversion, and only the hopping part of M depends on U):
+ * and Y = M X as packed FP64 full fields (the paper's section 2.2, the fermion
+ * force: the derivative of D^{-1} needs one inversion, and only the hopping part
+ * of M depends on U):
  *   G^a = -2 kappa Im Tr[T^a (b+ Q1 - conj(b+) Q2)],
  *   Q1 = sum_spin [(1 - gamma_mu) U_mu(x) X(x+mu)] (x) Y(x)^+,
  *   Q2 = sum_spin X(x) (x) [U_mu(x) (1 + gamma_mu) Y(x+mu)]^+.
+ * Y = NULL: the call computes Y = M X itself, into ws (tmqcd_force_workspace_bytes
+ * bytes: one packed FP64 full field; device, 256-byte aligned, caller-owned,
+ * overwritten); with Y given, ws may be NULL.
  * dSdw[V][4][8] (device, float64, canonical) receives scale * G (accumulate = 0)
  * or has scale * G added (accumulate = 1): with dSdw = p and scale = -dt this is
- * the HMC momentum update.  U_packed: FP64, RECON18 or RECON12. */
-int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X,
-                const void* Y, double* dSdw, double scale, int accumulate, void* stream);
+ * the HMC momentum update.  U_packed: FP64 with the given recon.
+ * Errors: TMQCD_EINVAL (bad problem or recon, X or dSdw NULL, non-finite scale,
+ * accumulate not 0/1), TMQCD_EALIGN, TMQCD_EWORKSPACE (Y NULL and ws missing or
+ * short), TMQCD_EALIAS (dSdw overlaps X, Y, U_packed or ws; ws overlaps X or
+ * U_packed); TMQCD_EHIP if a launch fails. */
+size_t tmqcd_force_workspace_bytes(const tmqcd_problem* prob);
+int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X, const void* Y,
+                double* dSdw, double scale, int accumulate, void* ws, size_t ws_bytes, void* stream);
 
 /* The force of the even-odd pseudofermion action S_f = phi_e^+ (Mhat^+ Mhat)^{-1} phi_e
  * (the paper's force section for the Schur complement of its even-odd
@@ -285,7 +331,7 @@ int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, cons
  * Three hops build X_o, Y_e and Y_o in ws (tmqcd_force_eo_workspace_bytes(prob)
  * bytes, device, 256-byte aligned, caller-owned, overwritten), then the force
  * kernel writes or accumulates scale * G into dSdw[V][4][8] as tmqcd_force does.
- * U_packed: FP64, RECON18 or RECON12.  dSdw may not overlap X_e, U_packed or ws.
+ * U_packed: FP64 with the given recon (any of the four encodings).  dSdw may not overlap X_e, U_packed or ws.
  * Errors: TMQCD_EINVAL (bad problem, recon, null pointer, non-finite scale,
  * accumulate not 0/1), TMQCD_EALIGN, TMQCD_EWORKSPACE (ws missing or short),
  * TMQCD_EALIAS; TMQCD_EHIP if a launch fails. */
@@ -348,6 +394,26 @@ int tmqcd_heatbath(const tmqcd_problem* prob, void* U_packed, int prec, double b
                    void* stream);
 int tmqcd_overrelax(const tmqcd_problem* prob, void* U_packed, int prec, void* stream);
 
+/* The change of the HMC Hamiltonian H = 1/2 sum p^2 + S_g + S_f (the paper's section
+ * 2.2: the Metropolis step accepts with min(1, exp(-(H' - H)))) between the states
+ * (U0, p0, X0) and (U1, p1, X1), summed site by site in FP64 so that no difference of
+ * two large totals is formed:
+ *   dH = sum_x [ 1/2 sum_{mu,a} (p1^2 - p0^2)
+ *               + (beta/3) (c0 sum_{mu<nu} Re Tr(P0 - P1) + c1 sum_{mu!=nu} Re Tr(R0 - R1))
+ *               + Re phi(x)^+ (X1(x) - X0(x)) ],   c0 = 1 - 8 c1,
+ * the gauge action of tmqcd_gauge_force_tlsym (c1 = 0: Wilson; beta = 0: none) and
+ * S_f = Re phi^+ X with X the solution of the pseudofermion's system at each state
+ * (X = (M^+M)^{-1} phi for subset TMQCD_FULL, (Mhat^+Mhat)^{-1} phi_e for TMQCD_EVEN).
+ * U0, U1: packed FP64 RECON18 links; p0, p1: double[V][4][8]; phi, X0, X1: packed FP64
+ * fields of `subset`.  result[0..3] (device): dH and its kinetic, gauge and
+ * fermion parts.  ws: tmqcd_workspace_bytes(prob, -1, 1, 1) bytes.
+ * Errors: TMQCD_EINVAL (bad problem, null pointer, subset not FULL/EVEN, non-finite
+ * beta or c1), TMQCD_EALIGN, TMQCD_EWORKSPACE, TMQCD_EALIAS (ws or result overlapping
+ * an input); TMQCD_EHIP if a launch fails. */
+int tmqcd_delta_h(const tmqcd_problem* prob, const void* U0, const void* U1, const double* p0, const double* p1,
+                  const void* phi, const void* X0, const void* X1, int subset, double beta, double c1,
+                  double* result, void* ws, size_t ws_bytes, void* stream);
+
 /* Deterministic FP64 reductions into device memory.  ws: tmqcd_workspace_bytes(prob, -1, 1, 1) bytes.
  *   tmqcd_plaquette:      result[0] = sum_{x, mu<nu} Re Tr P_mu_nu(x)       (U_packed FP64 RECON18)
  *   tmqcd_rectangle:      result[0] = sum_{x, mu!=nu} Re Tr R_mu_nu(x)      (the 12 V rectangles of
@@ -364,8 +430,8 @@ int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subse
               void* ws, size_t ws_bytes, void* stream);
 
 /* ---- autotuning --------------------------------------------------------------- */
-/* The paper tuned its kernels per GPU (memory stride, lattice extents compiled
- * in); here the launch shape of each hop kernel class is chosen by timing on
+/* The paper tuned its kernels per GPU (its implementation-strategy section 4:
+ * memory stride, lattice extents compiled in); here the launch shape of each hop kernel class is chosen by timing on
  * the caller's problem.  A shape is a block size (128 or 256 threads) and a
  * block order, i.e. which output sites a block covers:
  *   0  linear: block b covers half sites [b*w, b*w + w) of its parity;
@@ -373,7 +439,10 @@ int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subse
  *   2  every t-slice cut into 8 site ranges, one per XCD, each XCD walking
  *      through t (its t-neighbours are in slices it has in flight);
  *   3  the (y, z) plane cut into square regions sized to the L2, each XCD
- *      sweeping its regions one by one through all t.
+ *      sweeping its regions one by one through all t;
+ *   4  the lattice cut into 4 z-ranges (runs of z-planes) x 2 t-ranges, one
+ *      block of them per XCD, each XCD walking through its t-range;
+ *   5  as 4 with 2 z-ranges x 4 t-ranges.
  * Kernel classes: 0 hop (+ twisted-mass own term), 1 hop + |out|^2 (CG),
  * 2 hop + CG update, 3 multi-RHS hop (256 threads: 64 sites x 4 waves; the
  * order and the number of right-hand sides a block serves are tuned: with
@@ -389,18 +458,18 @@ int tmqcd_dot(const tmqcd_problem* prob, const void* x, const void* y, int subse
 typedef struct {
     int32_t kernel_class;  /* 0..3 as above */
     int32_t block;         /* chosen threads per block */
-    int32_t order;         /* chosen block order, 0..3 as above */
+    int32_t order;         /* chosen block order, 0..5 as above */
     int32_t group;         /* class 3: right-hand sides per block (0: all of them); else 0 */
     int32_t candidates;    /* shapes tried */
     int32_t rejected;      /* shapes whose output differed from the default's */
     double  us;            /* time per launch of the chosen shape */
     double  default_us;    /* time per launch of the default shape */
 } tmqcd_tune_result;
-/* Classes 0, 1, 2 (8 shapes each).  ws: at least tmqcd_tune_workspace_bytes. */
+/* Classes 0, 1, 2 (12 shapes each).  ws: at least tmqcd_tune_workspace_bytes. */
 size_t tmqcd_tune_workspace_bytes(const tmqcd_problem* prob, int prec);
 int tmqcd_tune(const tmqcd_problem* prob, const void* U_packed, int prec, int recon, void* ws,
                size_t ws_bytes, tmqcd_tune_result results[3], void* stream);
-/* Class 3 for nrhs in [2, 16] (4 orders x groups of all, about half and
+/* Class 3 for nrhs in [2, 16] (6 orders x groups of all, about half and
  * about a third of the right-hand sides).  ws: at least
  * tmqcd_tune_mrhs_workspace_bytes(prob, prec, nrhs) bytes. */
 size_t tmqcd_tune_mrhs_workspace_bytes(const tmqcd_problem* prob, int prec, int nrhs);
@@ -415,7 +484,7 @@ void tmqcd_tune_clear(void);
 /* Pins the shape of one class for this problem, precision and link
  * compression, as a tuning run would: classes 0..2 take nrhs = 1, block 128
  * or 256 and group 0; class 3 takes nrhs in [2, 16], block 256 and group in
- * [0, nrhs]; order 0..3.  TMQCD_EINVAL for any other value.  Host only. */
+ * [0, nrhs]; order 0..5.  TMQCD_EINVAL for any other value.  Host only. */
 int tmqcd_tune_set(const tmqcd_problem* prob, int prec, int recon, int kernel_class, int nrhs, int block,
                    int order, int group);
 

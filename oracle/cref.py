@@ -80,10 +80,20 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _check_shapes(op: str, U, psi, dims):
+    """The C++ side trusts the sizes: check them here (links (V, 4, 3, 3); fields (n, 4, 3))."""
+    v = int(np.prod([int(d) for d in dims]))
+    n = v if op in FULL_OPS else v // 2
+    if U.size != v * 36 or psi.size != n * 12:
+        raise ValueError(f"{op}: links of {U.size // 36} sites and a field of {psi.size // 12} sites for extents "
+                         f"{tuple(dims)} (want {v} and {n})")
+
+
 def apply(op: str, U, psi, dims, kappa, mu, bc) -> np.ndarray:
     """op(psi) for op in OPS; psi (V, 4, 3) for the full-lattice ops, (V/2, 4, 3) otherwise."""
     d, b = _args(dims, bc)
     U, psi = _c128(U), _c128(psi)
+    _check_shapes(op, U, psi, dims)
     out = np.empty_like(psi)
     rc = lib().ref_apply(OPS[op], d, float(kappa), float(mu), _p(b), _p(U), _p(psi), _p(out))
     if rc != 0:
@@ -95,6 +105,8 @@ def true_rel_residual(op: str, U, b, x, dims, kappa, mu, bc) -> float:
     """||b - op x|| / ||b|| in FP64."""
     d, bcv = _args(dims, bc)
     U, b, x = _c128(U), _c128(b), _c128(x)
+    _check_shapes(op, U, b, dims)
+    _check_shapes(op, U, x, dims)
     return lib().ref_true_rel_residual(OPS[op], d, float(kappa), float(mu), _p(bcv), _p(U), _p(b), _p(x))
 
 
@@ -102,6 +114,7 @@ def cg(op: str, U, b, dims, kappa, mu, bc, tol=1e-10, max_iter=100000, report_to
     """CG on MDAGM or MHATDAGMHAT from x = 0.  Returns (x, stats dict, return code)."""
     d, bcv = _args(dims, bc)
     U, b = _c128(U), _c128(b)
+    _check_shapes(op, U, b, dims)
     x = np.empty_like(b)
     st = np.zeros(6)
     rc = lib().ref_cg(OPS[op], d, float(kappa), float(mu), _p(bcv), _p(U), _p(b), _p(x), float(tol), int(max_iter),

@@ -68,7 +68,8 @@ int hip_fail(hipError_t e) {
     return TMQCD_EHIP;
 }
 
-int64_t cg_workspace(const Geom& g, int op, int prec_mask) {
+int64_t cg_workspace(const Geom& g, int op, int prec_mask, int nrhs) {
+    if (nrhs > 1) return carve_cg_mrhs(g, op, nrhs, nullptr).total;   // FP64 multi-RHS solve
     int64_t need = carve_cg(g, op, TMQCD_F64, nullptr).total;
     if (prec_mask & (1 << TMQCD_F32)) {
         const int64_t t = carve_cg(g, op, TMQCD_F32, nullptr).total;
@@ -112,7 +113,7 @@ size_t tmqcd_workspace_bytes(const tmqcd_problem* prob, int op, int prec_mask, i
     const Geom g = make_geom(*prob);
     int64_t need = dslash_workspace(g, op, prec_mask, nrhs);
     if (op == TMQCD_MDAGM || op == TMQCD_MHATDAGMHAT) {
-        const int64_t t = cg_workspace(g, op, prec_mask);
+        const int64_t t = cg_workspace(g, op, prec_mask, nrhs);
         need = t > need ? t : need;
     }
     return (size_t)(need > 256 ? need : 256);
@@ -222,20 +223,24 @@ int tmqcd_cg(const tmqcd_problem* prob, const void* const U_packed[3], const voi
     if (o.op != TMQCD_MDAGM && o.op != TMQCD_MHATDAGMHAT) return TMQCD_EINVAL;
     if (!valid_prec(o.inner_prec) || !valid_recon(o.recon) || o.max_iter < 1) return TMQCD_EINVAL;
     if (!(o.tol > 0.0) || !std::isfinite(o.tol) || o.reliable_delta < 0 || o.reliable_delta >= 1 ||
-        o.check_every < 0 || o.use_graph < -1 || o.use_graph > 1)
+        o.check_every < 0 || o.use_graph < -1 || o.use_graph > 1 || o.nrhs < 0 || o.nrhs > kMaxRhs)
         return TMQCD_EINVAL;
+    const int nrhs = o.nrhs > 1 ? o.nrhs : 1;
+    if (nrhs > 1 && (o.inner_prec != TMQCD_F64 || o.use_graph == 1)) return TMQCD_EINVAL;
     if (!U_packed[TMQCD_F64] || !U_packed[o.inner_prec]) return TMQCD_EINVAL;
     if (!aligned(b, kAlignBytes) || !aligned(x, kAlignBytes) || !aligned(U_packed[TMQCD_F64], kAlignBytes) ||
         !aligned(U_packed[o.inner_prec], kAlignBytes))
         return TMQCD_EALIGN;
     const Geom g = make_geom(*prob);
     const int subset = o.op == TMQCD_MDAGM ? TMQCD_FULL : TMQCD_EVEN;
-    const int64_t fb = field_bytes(g, TMQCD_F64, subset);
+    const int64_t fb = nrhs * field_bytes(g, TMQCD_F64, subset);
     if (overlap(b, fb, x, fb)) return TMQCD_EALIAS;
-    const int64_t need = carve_cg(g, o.op, o.inner_prec, nullptr).total;
+    const int64_t need = nrhs > 1 ? carve_cg_mrhs(g, o.op, nrhs, nullptr).total
+                                  : carve_cg(g, o.op, o.inner_prec, nullptr).total;
     if (!ws || (int64_t)ws_bytes < need) return TMQCD_EWORKSPACE;
     if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
     if (overlap(ws, need, b, fb) || overlap(ws, need, x, fb)) return TMQCD_EALIAS;
+    if (nrhs > 1) return run_cg_mrhs(*prob, U_packed[TMQCD_F64], b, x, o, stats, ws, (hipStream_t)stream);
     return run_cg(*prob, U_packed, b, x, o, *stats, ws, (hipStream_t)stream);
 }
 
@@ -274,26 +279,42 @@ int tmqcd_cg_batch(int n, const tmqcd_problem* probs, const void* const* U_packe
     return run_cg_batch(n, probs, U_packed, b, x, o, stats, use_graph == 1, ws, (hipStream_t)stream);
 }
 
+size_t tmqcd_force_workspace_bytes(const tmqcd_problem* prob) {
+    if (!valid_problem(prob)) return 0;
+    return (size_t)field_bytes(make_geom(*prob), TMQCD_F64, TMQCD_FULL);
+}
+
 int tmqcd_force(const tmqcd_problem* prob, const void* U_packed, int recon, const void* X, const void* Y,
-                double* dSdw, double scale, int accumulate, void* stream) {
-    if (!valid_problem(prob) || !valid_recon(recon) || !U_packed || !X || !Y || !dSdw || !std::isfinite(scale) ||
+                double* dSdw, double scale, int accumulate, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_problem(prob) || !valid_recon(recon) || !U_packed || !X || !dSdw || !std::isfinite(scale) ||
         (accumulate != 0 && accumulate != 1))
         return TMQCD_EINVAL;
-    if (!aligned(U_packed, kAlignBytes) || !aligned(X, kAlignBytes) || !aligned(Y, kAlignBytes) ||
+    if (!aligned(U_packed, kAlignBytes) || !aligned(X, kAlignBytes) || (Y && !aligned(Y, kAlignBytes)) ||
         !aligned(dSdw, 16))
         return TMQCD_EALIGN;
     const Geom g = make_geom(*prob);
-    const int64_t fb = field_bytes(g, TMQCD_F64, TMQCD_FULL), ob = mom_bytes(g);
-    if (overlap(dSdw, ob, X, fb) || overlap(dSdw, ob, Y, fb) ||
-        overlap(dSdw, ob, U_packed, gauge_bytes(g, TMQCD_F64, recon)))
+    const int64_t fb = field_bytes(g, TMQCD_F64, TMQCD_FULL), ob = mom_bytes(g), gb = gauge_bytes(g, TMQCD_F64, recon);
+    if (overlap(dSdw, ob, X, fb) || (Y && overlap(dSdw, ob, Y, fb)) || overlap(dSdw, ob, U_packed, gb))
         return TMQCD_EALIAS;
+    if (!Y) {   // Y = M X is computed into the workspace
+        if (!ws || (int64_t)ws_bytes < fb) return TMQCD_EWORKSPACE;
+        if (!aligned(ws, kAlignBytes)) return TMQCD_EALIGN;
+        if (overlap(ws, fb, X, fb) || overlap(ws, fb, U_packed, gb) || overlap(ws, fb, dSdw, ob)) return TMQCD_EALIAS;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (!Y) {
+        const OpCtx c = make_ctx(*prob, TMQCD_F64, recon, U_packed, s);
+        e = apply_operator(c, TMQCD_M, X, ws, nullptr, 1);
+        if (e != hipSuccess) return hip_fail(e);
+        Y = ws;
+    }
     Cplx bc[4];
     for (int i = 0; i < 4; ++i) bc[i] = {prob->bc[i][0], prob->bc[i][1]};
     const int64_t hb = half_field_bytes(g, TMQCD_F64);
     const void* const Xp[2] = {X, static_cast<const char*>(X) + hb};
     const void* const Yp[2] = {Y, static_cast<const char*>(Y) + hb};
-    const hipError_t e =
-        launch_force(g, U_packed, recon, Xp, Yp, dSdw, bc, prob->kappa, scale, accumulate, (hipStream_t)stream);
+    e = launch_force(g, U_packed, recon, Xp, Yp, dSdw, bc, prob->kappa, scale, accumulate, s);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 
@@ -428,6 +449,29 @@ int tmqcd_momentum_norm2(const tmqcd_problem* prob, const double* p, double* res
     if (rc != TMQCD_OK) return rc;
     if (overlap(ws, ws_bytes, p, mom_bytes(g)) || overlap(ws, ws_bytes, result, 8)) return TMQCD_EALIAS;
     const hipError_t e = launch_mom_norm2(g, p, result, static_cast<double*>(ws), (hipStream_t)stream);
+    return e == hipSuccess ? TMQCD_OK : hip_fail(e);
+}
+
+int tmqcd_delta_h(const tmqcd_problem* prob, const void* U0, const void* U1, const double* p0, const double* p1,
+                  const void* phi, const void* X0, const void* X1, int subset, double beta, double c1,
+                  double* result, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_problem(prob) || !U0 || !U1 || !p0 || !p1 || !phi || !X0 || !X1 || !result ||
+        (subset != TMQCD_FULL && subset != TMQCD_EVEN) || !std::isfinite(beta) || !std::isfinite(c1))
+        return TMQCD_EINVAL;
+    if (!aligned(U0, kAlignBytes) || !aligned(U1, kAlignBytes) || !aligned(p0, 16) || !aligned(p1, 16) ||
+        !aligned(phi, kAlignBytes) || !aligned(X0, kAlignBytes) || !aligned(X1, kAlignBytes) || !aligned(result, 8))
+        return TMQCD_EALIGN;
+    const Geom g = make_geom(*prob);
+    const int rc = aux_ws_check(g, ws, ws_bytes);
+    if (rc != TMQCD_OK) return rc;
+    const int64_t ub = gauge_bytes(g, TMQCD_F64, TMQCD_RECON18), pb = mom_bytes(g), fb = field_bytes(g, TMQCD_F64, subset);
+    const void* ins[7] = {U0, U1, p0, p1, phi, X0, X1};
+    const int64_t sz[7] = {ub, ub, pb, pb, fb, fb, fb};
+    for (int i = 0; i < 7; ++i)
+        if (overlap(ws, ws_bytes, ins[i], sz[i]) || overlap(result, 32, ins[i], sz[i])) return TMQCD_EALIAS;
+    if (overlap(ws, ws_bytes, result, 32)) return TMQCD_EALIAS;
+    const hipError_t e = launch_delta_h(g, U0, U1, p0, p1, phi, X0, X1, subset == TMQCD_FULL ? 2 : 1, beta, c1, result,
+                                        static_cast<double*>(ws), (hipStream_t)stream);
     return e == hipSuccess ? TMQCD_OK : hip_fail(e);
 }
 

@@ -113,6 +113,33 @@ __global__ __launch_bounds__(kBlock) void xpay_kernel(VecK v, char* p, int64_t p
     SpinorIO<PP>::store(p + half * pbytes, v.stride, h, pv);
 }
 
+// p = r + beta p inside the CG iteration: beta = rr_new / rr with rr_new the sum of
+// the update hop's partials, formed by every block in the same fixed order (so all
+// blocks use the same beta) while st->rr still holds the previous |r|^2; the state
+// itself is updated by the next launch that finishes the pending beta.
+template <int PP, int PR>
+__global__ __launch_bounds__(kBlock) void xpay_fused_kernel(VecK v, char* p, int64_t pbytes, const char* r,
+                                                            int64_t rbytes, CgState* st, const double* partials,
+                                                            int n) {
+    if (block_stopped(st)) return;
+    double tot[1];
+    sum_partials<1>(partials, n, tot);
+    const double beta_d = tot[0] / st->rr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->beta_pending = 1;
+    int half, h;
+    if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
+    using T = typename Prec<PP>::T;
+    const T beta = (T)beta_d;
+    Spinor<T> pv, rv;
+    SpinorIO<PP>::load(pv, p + half * pbytes, v.stride, h);
+    SpinorIO<PR>::load(rv, r + half * rbytes, v.stride, h);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pv.s[s][c] = rv.s[s][c] + scale(beta, pv.s[s][c]);
+    SpinorIO<PP>::store(p + half * pbytes, v.stride, h, pv);
+}
+
 constexpr int kMaxBatchVec = 8;
 struct XpayBatch {
     int n;
@@ -216,7 +243,10 @@ __global__ void set_state_kernel(CgState* st, StateInit v) {
     if (v.set_iter) st->iter = v.iter;
     if (v.set_max_iter) st->max_iter = v.max_iter;
     if (v.set_cycle_end) st->cycle_end = v.cycle_end;
-    if (v.set_done) st->done = v.done;
+    if (v.set_done) {   // a solve (re)starts or stops here: no beta finish is pending
+        st->done = v.done;
+        st->beta_pending = 0;
+    }
 }
 
 __global__ void rr_from_result_kernel(CgState* st, int slot, double stop_factor) {
@@ -241,10 +271,37 @@ struct FinishBatch {
     int n[kMaxFinish];
 };
 
-static_assert(kFinishAlpha == 0 && kFinishBeta == 1, "finish kinds as cg_finish_update numbers them");
+static_assert(kFinishAlpha == 0 && kFinishBeta == 1 && kFinishBetaPending == 2,
+              "finish kinds as cg_finish_block numbers them");
 
 __global__ __launch_bounds__(kBlock) void cg_finish_kernel(const FinishBatch f, int kind) {
     cg_finish_block<kBlock>(f.st[blockIdx.x], f.partials[blockIdx.x], f.n[blockIdx.x], kind);
+}
+
+// The multi-RHS CG: block b finishes column b's reduction (tiles partials at partials + b * tiles).
+__global__ __launch_bounds__(kBlock) void cg_finish_cols_kernel(CgState* st, const double* partials, int tiles,
+                                                                int kind) {
+    cg_finish_block<kBlock>(st + blockIdx.x, partials + (int64_t)blockIdx.x * tiles, tiles, kind);
+}
+
+// p_c = r_c + beta_c p_c for every column c = blockIdx.y whose solve runs (FP64 fields fstride apart).
+__global__ __launch_bounds__(kBlock) void xpay_cols_kernel(VecK v, char* p, const char* r, int64_t hbytes,
+                                                           int64_t fstride, const CgState* st) {
+    const int c = blockIdx.y;
+    if (st[c].done) return;
+    int half, h;
+    if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
+    const double beta = st[c].beta;
+    char* pc = p + c * fstride + half * hbytes;
+    const char* rc = r + c * fstride + half * hbytes;
+    Spinor<double> pv, rv;
+    SpinorIO<TMQCD_F64>::load(pv, pc, v.stride, h);
+    SpinorIO<TMQCD_F64>::load(rv, rc, v.stride, h);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pv.s[s][k] = rv.s[s][k] + scale(beta, pv.s[s][k]);
+    SpinorIO<TMQCD_F64>::store(pc, v.stride, h, pv);
 }
 
 template <template <int> class F, typename... A>
@@ -343,6 +400,26 @@ hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr,
     return hipGetLastError();
 }
 
+hipError_t launch_xpay_fused(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st,
+                             const double* partials, int n, hipStream_t s) {
+    const VecK k = make_veck(v);
+    char* pc = static_cast<char*>(p);
+    const char* rc = static_cast<const char*>(r);
+    const int64_t pb = half_field_bytes(*v.g, pp), rb = half_field_bytes(*v.g, pr);
+    if (pp == TMQCD_F64 && pr == TMQCD_F64)
+        hipLaunchKernelGGL((xpay_fused_kernel<TMQCD_F64, TMQCD_F64>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb,
+                           rc, rb, st, partials, n);
+    else if (pp == TMQCD_F32 && pr == TMQCD_F32)
+        hipLaunchKernelGGL((xpay_fused_kernel<TMQCD_F32, TMQCD_F32>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb,
+                           rc, rb, st, partials, n);
+    else if (pp == TMQCD_F16 && pr == TMQCD_F32)
+        hipLaunchKernelGGL((xpay_fused_kernel<TMQCD_F16, TMQCD_F32>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb,
+                           rc, rb, st, partials, n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_accumulate(const VecSpec& v, void* x64, void* xs, int ps, hipStream_t s) {
     const VecK k = make_veck(v);
     const int64_t xb = half_field_bytes(*v.g, TMQCD_F64), sb = half_field_bytes(*v.g, ps);
@@ -377,6 +454,21 @@ hipError_t launch_cg_finish_batch(CgState* const* st, const double* const* parti
 
 hipError_t launch_cg_finish(CgState* st, const double* partials, int n, int kind, hipStream_t s) {
     return launch_cg_finish_batch(&st, &partials, &n, 1, kind, s);
+}
+
+hipError_t launch_cg_finish_cols(CgState* st, const double* partials, int tiles, int ncol, int kind, hipStream_t s) {
+    if (ncol < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cg_finish_cols_kernel, dim3(ncol), dim3(kBlock), 0, s, st, partials, tiles, kind);
+    return hipGetLastError();
+}
+
+hipError_t launch_xpay_cols(const VecSpec& v, void* p, const void* r, int64_t fstride, int ncol, const CgState* st,
+                            hipStream_t s) {
+    const VecK k = make_veck(v);
+    if (ncol < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(xpay_cols_kernel, dim3(k.nblocks, ncol), dim3(kBlock), 0, s, k, static_cast<char*>(p),
+                       static_cast<const char*>(r), half_field_bytes(*v.g, TMQCD_F64), fstride, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipStream_t s) {

@@ -575,6 +575,7 @@ struct CgState {
     int max_iter;
     int cycle_end;    // the update kernel flags done when iter reaches it (reliable-update cycle cap)
     int done;         // 0 running, 1 reached stop_rr or cycle_end, 2 breakdown, 3 iteration cap
+    int beta_pending; // the search-direction update used partial sums whose finish is still due
     double result[4]; // scratch results of standalone reductions
 };
 enum { kDoneRunning = 0, kDoneStop = 1, kDoneBreakdown = 2, kDoneMaxIter = 3 };
@@ -688,18 +689,26 @@ __device__ __forceinline__ bool block_stopped(const CgState* st) {
 
 // A whole block finishes a CG reduction of n partials unless the solve has
 // stopped; returns (in every thread) whether the solve is stopped afterwards.
+// kind 2 (kFinishBetaPending in internal.h): the beta finish of an iteration whose
+// search-direction update already formed beta from the same partials, done only
+// when st->beta_pending is set (and then cleared).
 template <int BS>
 __device__ __forceinline__ bool cg_finish_block(CgState* st, const double* partials, int n, int kind) {
-    __shared__ int stopped;
-    if (threadIdx.x == 0) stopped = st->done;
+    __shared__ int stopped, skip;
+    if (threadIdx.x == 0) {
+        stopped = st->done;
+        skip = kind == 2 && !st->beta_pending;
+    }
     __syncthreads();
-    const bool before = stopped != 0;
-    __syncthreads();   // every wave has read the flag before it is written again
+    const bool before = stopped != 0, nothing = skip != 0;
+    __syncthreads();   // every wave has read the flags before they are written again
     if (before) return true;
+    if (nothing) return false;
     double tot[1];
     sum_partials<1, BS>(partials, n, tot);
     if (threadIdx.x == 0) {
-        cg_finish_update(st, tot[0], kind);
+        cg_finish_update(st, tot[0], kind == 2 ? 1 : kind);
+        if (kind == 2) st->beta_pending = 0;
         stopped = st->done;
     }
     __syncthreads();

@@ -14,6 +14,11 @@
 #include "device.h"
 #include "internal.h"
 
+// waves per SIMD the force kernel is compiled for (launch bounds)
+#ifndef FORCE_WAVES
+#define FORCE_WAVES 3
+#endif
+
 namespace tmqcd {
 namespace {
 
@@ -92,37 +97,64 @@ __device__ __forceinline__ bool force_block_site(const ForceK& a, int bid, int l
 }
 
 template <int R, int MU>
-__device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int nh, bool cross,
-                                          const Spinor<double>& xo, const Spinor<double>& yo, double* g) {
-    const char* Xn = a.X[1 - par];
-    const char* Yn = a.Y[1 - par];
+__device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int nh, bool cross, double* g) {
+    // Q = b+ Q1 - conj(b+) Q2 with Q1 = sum_r [U P- X(x+mu)]_r (x) [P- Y(x)]_r^+ and
+    // Q2 = sum_r [P+ X(x)]_r (x) [U P+ Y(x+mu)]_r^+, accumulated one term at a time:
+    // each spinor is projected right after its load and each outer product added to Q
+    // as soon as both of its half spinors exist, so few of them are live at once.
+    const C<double> b = cross ? a.bc[MU] : C<double>{1.0, 0.0};
     Su3<double> u;
     LinkIO<TMQCD_F64, R>::template load<true>(u, a.gauge, a.gstride, par, MU, h);
-    Spinor<double> xn, yn;
-    SpinorIO<TMQCD_F64>::load(xn, Xn, a.stride, nh);
-    SpinorIO<TMQCD_F64>::load(yn, Yn, a.stride, nh);
-    // Q1 = sum_r [U P- X(x+mu)]_r (x) [P- Y(x)]_r^+,  Q2 = sum_r [P+ X(x)]_r (x) [U P+ Y(x+mu)]_r^+
-    Half<double> hh, g1, g2, z1, z2;
-    project<MU, -1>(hh, xn);
-    umul(g1, u, hh);
-    project<MU, +1>(hh, yn);
-    umul(g2, u, hh);
-    project<MU, -1>(z1, yo);
-    project<MU, +1>(z2, xo);
-    C<double> b = cross ? a.bc[MU] : C<double>{1.0, 0.0};
     C<double> q[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            C<double> q1 = {0, 0}, q2 = {0, 0};
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                q1 = q1 + cmul_cj(z1.s[r][j], g1.s[r][i]);   // g1_i conj(z1_j)
-                q2 = q2 + cmul_cj(g2.s[r][j], z2.s[r][i]);   // z2_i conj(g2_j)
-            }
-            q[i][j] = b * q1 - conj(b) * q2;
+    {
+        Half<double> z, w;
+        {
+            Spinor<double> v;
+            SpinorIO<TMQCD_F64>::load(v, a.Y[par], a.stride, h);
+            project<MU, -1>(z, v);
         }
+        {
+            Spinor<double> v;
+            Half<double> hh;
+            SpinorIO<TMQCD_F64>::load(v, a.X[1 - par], a.stride, nh);
+            project<MU, -1>(hh, v);
+            umul(w, u, hh);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                C<double> q1 = {0, 0};
+#pragma unroll
+                for (int r = 0; r < 2; ++r) q1 = q1 + cmul_cj(z.s[r][j], w.s[r][i]);   // w_i conj(z_j)
+                q[i][j] = b * q1;
+            }
+    }
+    {
+        Half<double> z, w;
+        {
+            Spinor<double> v;
+            SpinorIO<TMQCD_F64>::load(v, a.X[par], a.stride, h);
+            project<MU, +1>(z, v);
+        }
+        {
+            Spinor<double> v;
+            Half<double> hh;
+            SpinorIO<TMQCD_F64>::load(v, a.Y[1 - par], a.stride, nh);
+            project<MU, +1>(hh, v);
+            umul(w, u, hh);
+        }
+        const C<double> bc = conj(b);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                C<double> q2 = {0, 0};
+#pragma unroll
+                for (int r = 0; r < 2; ++r) q2 = q2 + cmul_cj(w.s[r][j], z.s[r][i]);   // z_i conj(w_j)
+                q[i][j] = q[i][j] - bc * q2;
+            }
+    }
     // Im Tr(lambda^a Q) for the eight Gell-Mann matrices
     const double k = -a.kappa;   // -2 kappa * (1/2) from T^a = lambda^a / 2
     g[0] = k * (q[1][0].im + q[0][1].im);
@@ -138,12 +170,13 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
 // A block covers 64 sites and its wave w computes direction w (a wave-uniform
 // branch), so each thread holds one direction's operands; the four waves read
 // the same X(x), Y(x) (cache hits after the first; staging them in LDS once per
-// block measured 3 % slower).  Launch bounds ask for two
-// waves per SIMD (at most 256 registers; the kernel does not spill).  Holding
-// all four directions per thread needed 260 registers, one wave per SIMD, and
-// ran 14 % slower.
+// block measured 3 % slower).  Projecting every spinor as it arrives and adding
+// each outer product to Q at once keeps the kernel within 168 registers (three
+// waves per SIMD; 242-256 registers and two waves when the four spinors were
+// held whole).  Holding all four directions per thread needed 260 registers,
+// one wave per SIMD, and ran 14 % slower.
 template <int R>
-__global__ __launch_bounds__(kBlock, 2) void force_dir_kernel(const ForceK a) {
+__global__ __launch_bounds__(kBlock, FORCE_WAVES) void force_dir_kernel(const ForceK a) {
     // the block's 64 output records (32 doubles each, +1 against bank conflicts) and their sites
     __shared__ double otile[64][33];
     __shared__ int64_t srec[64];
@@ -161,24 +194,21 @@ __global__ __launch_bounds__(kBlock, 2) void force_dir_kernel(const ForceK a) {
         const int bit = (par + y + z + t) & 1;
         const int x = 2 * xh + bit;
 
-        Spinor<double> xo, yo;
-        SpinorIO<TMQCD_F64>::load(xo, a.X[par], a.stride, h);
-        SpinorIO<TMQCD_F64>::load(yo, a.Y[par], a.stride, h);
         double g[8];
         if (mu == 0) {
             const int xf = x + 1 == lx ? 0 : x + 1;
-            force_dir<R, 0>(a, par, h, (h - xh) + (xf >> 1), x == lx - 1, xo, yo, g);
+            force_dir<R, 0>(a, par, h, (h - xh) + (xf >> 1), x == lx - 1, g);
         } else if (mu == 1) {
             const int nf = y == ly - 1 ? h - (ly - 1) * lxh : h + lxh;
-            force_dir<R, 1>(a, par, h, nf, y == ly - 1, xo, yo, g);
+            force_dir<R, 1>(a, par, h, nf, y == ly - 1, g);
         } else if (mu == 2) {
             const int st = lxh * ly;
             const int nf = z == lz - 1 ? h - (lz - 1) * st : h + st;
-            force_dir<R, 2>(a, par, h, nf, z == lz - 1, xo, yo, g);
+            force_dir<R, 2>(a, par, h, nf, z == lz - 1, g);
         } else {
             const int st = lxh * ly * lz;
             const int nf = t == lt - 1 ? h - (lt - 1) * st : h + st;
-            force_dir<R, 3>(a, par, h, nf, t == lt - 1, xo, yo, g);
+            force_dir<R, 3>(a, par, h, nf, t == lt - 1, g);
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) otile[lane][mu * 8 + i] = a.scale * g[i];

@@ -10,8 +10,9 @@
 //   * link update U_mu(x) <- exp(i dt p^a T^a) U_mu(x): the exponential of the
 //     anti-hermitian generator by a degree-16 Taylor polynomial after scaling
 //     by 2^-n (||dt P|| / 2^n <= 1/4) and n squarings;
-//   * deterministic two-pass reductions: the plaquette and rectangle sums, sum p^2, and the
-//     complex inner product of two packed FP64 spinor fields.
+//   * deterministic two-pass reductions: the plaquette and rectangle sums, sum p^2, the
+//     complex inner product of two packed FP64 spinor fields, and the change of the
+//     Hamiltonian between two HMC states summed site by site (the Metropolis step's dH).
 // Momenta and forces use the canonical layout double[V][4][8]; links are the
 // packed FP64 18-real field, updated in place.
 #include "device.h"
@@ -339,6 +340,47 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const double* partials
         for (int i = 0; i < N; ++i) result[i] = tot[i];
 }
 
+// sum over the site's 6 plaquettes P_mu_nu(x), mu < nu, of Re Tr
+__device__ double plaquette_site(const LatK& k, const char* gauge, const int c[4]) {
+    const int zero[4] = {0, 0, 0, 0};
+    double v = 0.0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            int dm[4] = {0, 0, 0, 0}, dn[4] = {0, 0, 0, 0};
+            dm[mu] = 1;
+            dn[nu] = 1;
+            Su3<double> a, b, t1, t2;
+            link_at(a, k, gauge, c, zero, mu);
+            link_at(b, k, gauge, c, dm, nu);
+            mat_mul(t1, a, b);                     // U_mu(x) U_nu(x+mu)
+            link_at(a, k, gauge, c, zero, nu);
+            link_at(b, k, gauge, c, dn, mu);
+            mat_mul(t2, a, b);                     // U_nu(x) U_mu(x+nu)
+            // Re Tr[t1 t2^+]
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) v += t1.m[i][j].re * t2.m[i][j].re + t1.m[i][j].im * t2.m[i][j].im;
+        }
+    return v;
+}
+
+// sum over the site's 12 rectangles R_mu_nu(x), mu != nu, of Re Tr
+__device__ double rectangle_site(const LatK& k, const char* gauge, const int c[4]) {
+    double v = 0.0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int nu = 0; nu < 4; ++nu) {
+            if (nu == mu) continue;
+            const int m = mu + 1, n = nu + 1;
+            int pos[4] = {0, 0, 0, 0};
+            const int st[6] = {m, m, n, -m, -m, -n};
+            Su3<double> r;
+            walk(r, k, gauge, c, pos, st);
+            v += r.m[0][0].re + r.m[1][1].re + r.m[2][2].re;
+        }
+    return v;
+}
+
 __global__ __launch_bounds__(kBlock) void plaquette_kernel(LatK k, const char* gauge, double* partials) {
     const int par = blockIdx.x >= (unsigned)k.nb_half ? 1 : 0;
     const int h = (blockIdx.x - par * k.nb_half) * kBlock + threadIdx.x;
@@ -346,30 +388,11 @@ __global__ __launch_bounds__(kBlock) void plaquette_kernel(LatK k, const char* g
     if (h < k.vh) {
         int c[4];
         coords_of(k, par, h, c);
-        const int zero[4] = {0, 0, 0, 0};
-        for (int mu = 0; mu < 4; ++mu)
-            for (int nu = mu + 1; nu < 4; ++nu) {
-                int dm[4] = {0, 0, 0, 0}, dn[4] = {0, 0, 0, 0};
-                dm[mu] = 1;
-                dn[nu] = 1;
-                Su3<double> a, b, t1, t2;
-                link_at(a, k, gauge, c, zero, mu);
-                link_at(b, k, gauge, c, dm, nu);
-                mat_mul(t1, a, b);                     // U_mu(x) U_nu(x+mu)
-                link_at(a, k, gauge, c, zero, nu);
-                link_at(b, k, gauge, c, dn, mu);
-                mat_mul(t2, a, b);                     // U_nu(x) U_mu(x+nu)
-                // Re Tr[t1 t2^+]
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) v[0] += t1.m[i][j].re * t2.m[i][j].re + t1.m[i][j].im * t2.m[i][j].im;
-            }
+        v[0] = plaquette_site(k, gauge, c);
     }
     block_partial<1>(v, partials, blockIdx.x);
 }
 
-// sum over the site's 12 rectangles R_mu_nu(x), mu != nu, of Re Tr
 __global__ __launch_bounds__(kBlock) void rectangle_kernel(LatK k, const char* gauge, double* partials) {
     const int par = blockIdx.x >= (unsigned)k.nb_half ? 1 : 0;
     const int h = (blockIdx.x - par * k.nb_half) * kBlock + threadIdx.x;
@@ -377,18 +400,66 @@ __global__ __launch_bounds__(kBlock) void rectangle_kernel(LatK k, const char* g
     if (h < k.vh) {
         int c[4];
         coords_of(k, par, h, c);
-        for (int mu = 0; mu < 4; ++mu)
-            for (int nu = 0; nu < 4; ++nu) {
-                if (nu == mu) continue;
-                const int m = mu + 1, n = nu + 1;
-                int pos[4] = {0, 0, 0, 0};
-                const int st[6] = {m, m, n, -m, -m, -n};
-                Su3<double> r;
-                walk(r, k, gauge, c, pos, st);
-                v[0] += r.m[0][0].re + r.m[1][1].re + r.m[2][2].re;
-            }
+        v[0] = rectangle_site(k, gauge, c);
     }
     block_partial<1>(v, partials, blockIdx.x);
+}
+
+// The change of the HMC Hamiltonian between two states, accumulated site by site
+// in FP64 (no difference of two large totals): per site x
+//   kinetic   1/2 sum_{mu,a} (p1^2 - p0^2)
+//   gauge     (beta/3) [c0 sum_{mu<nu} Re Tr(P0 - P1) + c1 sum_{mu!=nu} Re Tr(R0 - R1)]
+//   fermion   Re phi(x)^+ (X1(x) - X0(x))      (sites of the pseudofermion's subset)
+// and their sum; block sums of (total, kinetic, gauge, fermion), finished by a
+// second launch in a fixed order.
+struct DeltaHK {
+    LatK k;
+    const char *u0, *u1;
+    const double *p0, *p1;
+    const char *phi, *x0, *x1;
+    int64_t stride, hbytes;
+    double beta, c0, c1;
+    int fermion_parities;   // 1: even sites only (the even-odd action), 2: all
+};
+
+__global__ __launch_bounds__(kBlock) void delta_h_kernel(DeltaHK a, double* partials) {
+    const LatK& k = a.k;
+    const int par = blockIdx.x >= (unsigned)k.nb_half ? 1 : 0;
+    const int h = (blockIdx.x - par * k.nb_half) * kBlock + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (h < k.vh) {
+        int c[4];
+        coords_of(k, par, h, c);
+        const int64_t s = 2 * (int64_t)h + (c[0] & 1);
+        double kin = 0.0;
+        for (int i = 0; i < 32; ++i) {
+            const double q1 = a.p1[s * 32 + i], q0 = a.p0[s * 32 + i];
+            kin += 0.5 * (q1 - q0) * (q1 + q0);
+        }
+        double gauge = 0.0;
+        if (a.beta != 0.0) {
+            gauge = a.c0 * (plaquette_site(k, a.u0, c) - plaquette_site(k, a.u1, c));
+            if (a.c1 != 0.0) gauge += a.c1 * (rectangle_site(k, a.u0, c) - rectangle_site(k, a.u1, c));
+            gauge *= a.beta / 3.0;
+        }
+        double ferm = 0.0;
+        if (par < a.fermion_parities) {
+            const int64_t off = par * a.hbytes;
+            Spinor<double> f, y0, y1;
+            SpinorIO<TMQCD_F64>::load(f, a.phi + off, a.stride, h);
+            SpinorIO<TMQCD_F64>::load(y0, a.x0 + off, a.stride, h);
+            SpinorIO<TMQCD_F64>::load(y1, a.x1 + off, a.stride, h);
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) ferm += cmul_cj(f.s[sp][cc], y1.s[sp][cc] - y0.s[sp][cc]).re;
+        }
+        v[0] = kin + gauge + ferm;
+        v[1] = kin;
+        v[2] = gauge;
+        v[3] = ferm;
+    }
+    block_partial<4>(v, partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void mom_norm2_kernel(const double* mom, int64_t n, double* partials) {
@@ -425,8 +496,10 @@ __global__ __launch_bounds__(kBlock) void spinor_dot_kernel(const char* x, const
 }  // namespace
 
 int64_t aux_partials_doubles(const Geom& g) {
-    // the largest grid among the reductions (momentum norm: 4 V threads), two values per block
-    return 2 * ((8 * g.vh + kBlock - 1) / kBlock) + 2;
+    // the largest among the reductions: the momentum norm (8 V_h threads, one value per block) and the
+    // Hamiltonian difference (2 V_h threads, four values per block)
+    const int64_t mom = (8 * g.vh + kBlock - 1) / kBlock, dh = 4 * 2 * ((g.vh + kBlock - 1) / kBlock);
+    return 2 * (mom > dh ? mom : dh) + 4;
 }
 
 hipError_t launch_gauge_force(const Geom& g, const void* gauge, double beta, double* out, double scale, int accumulate,
@@ -502,6 +575,30 @@ hipError_t launch_mom_norm2(const Geom& g, const double* mom, double* result, do
     const int nb = (int)((n + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(mom_norm2_kernel, dim3(nb), dim3(kBlock), 0, s, mom, n, partials);
     hipLaunchKernelGGL((finalize_kernel<1>), dim3(1), dim3(kBlock), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_delta_h(const Geom& g, const void* u0, const void* u1, const double* p0, const double* p1,
+                          const void* phi, const void* x0, const void* x1, int fermion_parities, double beta, double c1,
+                          double* result, double* partials, hipStream_t s) {
+    DeltaHK a;
+    a.k = make_latk(g);
+    a.u0 = static_cast<const char*>(u0);
+    a.u1 = static_cast<const char*>(u1);
+    a.p0 = p0;
+    a.p1 = p1;
+    a.phi = static_cast<const char*>(phi);
+    a.x0 = static_cast<const char*>(x0);
+    a.x1 = static_cast<const char*>(x1);
+    a.stride = g.stride;
+    a.hbytes = half_field_bytes(g, TMQCD_F64);
+    a.beta = beta;
+    a.c0 = 1.0 - 8.0 * c1;
+    a.c1 = c1;
+    a.fermion_parities = fermion_parities;
+    const int nb = 2 * a.k.nb_half;
+    hipLaunchKernelGGL(delta_h_kernel, dim3(nb), dim3(kBlock), 0, s, a, partials);
+    hipLaunchKernelGGL((finalize_kernel<4>), dim3(1), dim3(kBlock), 0, s, partials, nb, result);
     return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ hipError_t launch_inst(const HopK& k, int block, hipStream_t s) {
 
 template <int P, int R>
 hipError_t dispatch_variant(const HopParams& a, const HopK& k, hipStream_t s) {
-    if (a.nrhs > 1) return a.epi == kEpiStore ? launch_hop_mrhs(a, k, s) : hipErrorInvalidValue;
+    if (a.nrhs > 1) return launch_hop_mrhs(a, k, s);
     const bool own = a.own != nullptr;
     switch (a.epi) {
         case kEpiStore:
@@ -74,6 +74,23 @@ int hop_blocks(const Geom& g, int nparity) {
     return nparity * most;
 }
 
+int mrhs_tiles_max(const Geom& g, int nparity) {
+    HopParams a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = g;
+    a.nparity = nparity;
+    a.nrhs = 2;
+    int most = 0;
+    for (int prec = TMQCD_F64; prec <= TMQCD_F16; ++prec)
+        for (int order = 0; order < kNumOrders; ++order) {
+            a.prec = prec;
+            a.order = order;
+            const HopK k = make_hopk(a, 64);
+            most = k.nblocks > most ? k.nblocks : most;
+        }
+    return most;
+}
+
 hipError_t launch_hop(const HopParams& a_in, hipStream_t s, int* nblocks) {
     HopParams a = a_in;
     if (a.block == 0) {   // not chosen by the caller: the tuned choice, else the default shape
@@ -91,7 +108,7 @@ hipError_t launch_hop(const HopParams& a_in, hipStream_t s, int* nblocks) {
     }
     if (a.block != 128 && a.block != 256) return hipErrorInvalidValue;
     const HopK k = make_hopk(a, a.nrhs > 1 ? 64 : a.block);
-    if (nblocks) *nblocks = a.nrhs > 1 ? 0 : k.nblocks;
+    if (nblocks) *nblocks = k.nblocks;   // multi-RHS: tiles per column (its reduction partials per column)
     const int want_vprec = a.prec == TMQCD_F64 ? TMQCD_F64 : TMQCD_F32;
     if (a.epi == kEpiCgUpdate && a.vprec != want_vprec) return hipErrorInvalidValue;
     return with_link_format(a.prec, a.recon, [&](auto p, auto r) {

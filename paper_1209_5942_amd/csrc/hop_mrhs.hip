@@ -12,12 +12,25 @@ namespace {
 // lattice is swept once per group: fewer fields in flight per sweep keep more
 // of their t-neighbours in the L2, at the price of re-reading the links.
 // Fields of consecutive right-hand sides are `*_fstride` bytes apart.
+//
+// Inside the multi-RHS CG (FP64) the launch also carries one solver state per
+// column: columns whose solve has stopped are skipped (a column belongs to one
+// wave at a time, so the test is wave-uniform), and the epilogues of the CG
+// stages run per column: kEpiStoreNorm stores the output and sums its |out|^2,
+// kEpiCgUpdate updates x += alpha p, r -= alpha out and sums |r|^2; the sums of
+// a wave's 64 sites go to partials[column * tiles + tile] (no block-level step).
 struct MrhsK {
     int nrhs, group, tiles;
     int64_t in_fstride, own_fstride, out_fstride;
+    const CgState* st;       // per column, or nullptr outside CG
+    double* partials;        // [nrhs][tiles]
+    char* x;                 // CG update: x, r (FP64), p; vector fields v_fstride apart
+    char* r;
+    const char* p;
+    int64_t v_fstride;
 };
 
-template <int P, int R, bool DAG, bool OWN>
+template <int P, int R, bool DAG, bool OWN, int EPI>
 __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const MrhsK m) {
     using T = typename Prec<P>::T;
     using LIO = LinkIO<P, R>;
@@ -47,17 +60,21 @@ __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const Mr
         }
     }
     __syncthreads();
-    if (!valid) return;
+    if (EPI == kEpiStore && !valid) return;   // the reducing epilogues keep every lane for the wave sums
     const char* lt = reinterpret_cast<const char*>(tile);
     const C<T> cuh = cvt<T>(a.cu_hop), cdh = cvt<T>(a.cd_hop);
     const int64_t hoff = two ? (int64_t)par * a.hbytes : 0;
     const int64_t ioff = two ? (int64_t)(1 - par) * a.hbytes : 0;
     const int rend = min(m.nrhs, (g + 1) * m.group);
+    const int tile_id = blockIdx.x - g * m.tiles;
 #pragma unroll 1
     for (int r = g * m.group + wave; r < rend; r += kWaves) {
+        if (m.st != nullptr && m.st[r].done) continue;   // this column's solve has stopped
         // The link reads from the tile do not depend on r; without this barrier
         // the compiler hoists all eight links out of the loop into registers.
         __asm__ volatile("" ::: "memory");
+        double red = 0.0;
+        if (valid) {
         const char* in = a.in + r * m.in_fstride + ioff;
         Spinor<T> acc;
 #pragma unroll
@@ -94,7 +111,38 @@ __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const Mr
                 acc.s[3][c] = acc.s[3][c] + cdo * o.s[3][c];
             }
         }
-        SpinorIO<P>::template store<true>(a.out + r * m.out_fstride + hoff, a.stride, h, acc);
+        if constexpr (EPI == kEpiStore) {
+            SpinorIO<P>::template store<true>(a.out + r * m.out_fstride + hoff, a.stride, h, acc);
+        } else if constexpr (EPI == kEpiStoreNorm) {
+            SpinorIO<P>::store(a.out + r * m.out_fstride + hoff, a.stride, h, acc);   // read by the next stage
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) red += (double)norm2(acc.s[s][c]);
+        } else {
+            static_assert(P == TMQCD_F64, "the multi-RHS CG update runs in FP64");
+            const T alpha = (T)m.st[r].alpha;
+            const int64_t voff = two ? (int64_t)par * a.vhbytes : 0;
+            Spinor<T> pv, xv, rv;
+            SpinorIO<P>::load(pv, m.p + r * m.v_fstride + voff, a.stride, h);
+            SpinorIO<P>::load(xv, m.x + r * m.v_fstride + voff, a.stride, h);
+            SpinorIO<P>::load(rv, m.r + r * m.v_fstride + voff, a.stride, h);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
+                    rv.s[s][c] = rv.s[s][c] - scale(alpha, acc.s[s][c]);
+                    red += (double)norm2(rv.s[s][c]);
+                }
+            SpinorIO<P>::store(m.x + r * m.v_fstride + voff, a.stride, h, xv);
+            SpinorIO<P>::store(m.r + r * m.v_fstride + voff, a.stride, h, rv);
+        }
+        }   // valid
+        if constexpr (EPI != kEpiStore) {
+            red = wave_sum(red);
+            if (lane == 0) m.partials[(int64_t)r * m.tiles + tile_id] = red;
+        }
     }
 }
 
@@ -107,13 +155,33 @@ hipError_t launch_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
     m.in_fstride = a.in_fstride;
     m.own_fstride = a.own_fstride;
     m.out_fstride = a.out_fstride;
+    m.st = a.st;
+    m.partials = a.partials;
+    m.x = static_cast<char*>(a.x);
+    m.r = static_cast<char*>(a.r);
+    m.p = static_cast<const char*>(a.p);
+    m.v_fstride = a.v_fstride;
     const bool own = a.own != nullptr;
     const dim3 grid(k.nblocks * ((m.nrhs + m.group - 1) / m.group)), block(kBlock);
-    if (!a.dag && !own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, false>), grid, block, 0, s, k, m);
-    else if (a.dag && !own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, false>), grid, block, 0, s, k, m);
-    else if (!a.dag && own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, true>), grid, block, 0, s, k, m);
-    else hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, true>), grid, block, 0, s, k, m);
-    return hipGetLastError();
+    if (a.epi == kEpiStore) {
+        if (!a.dag && !own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, false, kEpiStore>), grid, block, 0, s, k, m);
+        else if (a.dag && !own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, false, kEpiStore>), grid, block, 0, s, k, m);
+        else if (!a.dag && own) hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, true, kEpiStore>), grid, block, 0, s, k, m);
+        else hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, true, kEpiStore>), grid, block, 0, s, k, m);
+        return hipGetLastError();
+    }
+    // the CG stages (FP64): store + |out|^2 of A p (no dagger, own term), update after A^+ (dagger, own term)
+    if constexpr (P == TMQCD_F64) {
+        if (a.st == nullptr || a.partials == nullptr || !own) return hipErrorInvalidValue;
+        if (a.epi == kEpiStoreNorm && !a.dag)
+            hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, true, kEpiStoreNorm>), grid, block, 0, s, k, m);
+        else if (a.epi == kEpiCgUpdate && a.dag && a.x && a.r && a.p)
+            hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, true, kEpiCgUpdate>), grid, block, 0, s, k, m);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace

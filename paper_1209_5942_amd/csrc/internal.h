@@ -47,9 +47,11 @@ struct HopParams {
     void* r;          // vector precision
     const void* p;    // dslash precision
     int vprec;        // precision of x and r
-    // several right-hand sides (epi == kEpiStore): fields nrhs apart by these byte strides
+    // several right-hand sides: fields nrhs apart by these byte strides; inside the multi-RHS CG
+    // (FP64; st points at nrhs states, partials holds nrhs x tiles sums) the vector fields x, r, p
+    // are v_fstride apart
     int nrhs;
-    int64_t in_fstride, own_fstride, out_fstride;
+    int64_t in_fstride, own_fstride, out_fstride, v_fstride;
     // launch shape: block 128 or 256 threads and the block order (kOrder*); block = 0 takes the tuned choice;
     // group: right-hand sides per block of the multi-RHS kernel (0: all)
     int block;
@@ -62,7 +64,13 @@ struct HopParams {
 };
 
 // Block orders of the hop launches (which sites a block covers, see block_site in stencil.h).
-enum BlockOrder { kOrderLinear = 0, kOrderXcdRemap = 1, kOrderSlab = 2, kOrderColumn = 3, kNumOrders = 4 };
+// kOrderSlab, kOrderSlabT2, kOrderSlabT4: each XCD owns one of (8, 4, 2) z-ranges of the t-slices of one of
+// (1, 2, 4) t-ranges and walks through its t-range (see block_site).
+enum BlockOrder {
+    kOrderLinear = 0, kOrderXcdRemap = 1, kOrderSlab = 2, kOrderColumn = 3, kOrderSlabT2 = 4, kOrderSlabT4 = 5,
+    kNumOrders = 6
+};
+__host__ __device__ inline bool slab_order(int order) { return order == kOrderSlab || order == kOrderSlabT2 || order == kOrderSlabT4; }
 
 constexpr int kMaxRhs = 16;   // right-hand sides of one multi-RHS launch
 
@@ -84,6 +92,7 @@ hipError_t launch_hop(const HopParams& a, hipStream_t s, int* nblocks = nullptr)
 // nblocks[i] (if given): the number of reduction partials lattice i receives
 hipError_t launch_hop_batch(const HopParams* ps, int n, int max_grid, hipStream_t s, int* nblocks = nullptr);
 int hop_blocks(const Geom& g, int nparity);   // grid size (and partial count) of a hop launch
+int mrhs_tiles_max(const Geom& g, int nparity);   // tiles of a multi-RHS launch (its partials per column)
 
 // ---- BLAS-1 over packed fields of nhalf half fields -------------------------
 // Calls f(integral_constant<P>, integral_constant<R>) for the run-time storage precision and
@@ -117,6 +126,10 @@ hipError_t launch_residual(const VecSpec& v, void* r, const void* b, const void*
 // p = r + beta p with beta = st->beta; nothing when st->done and skip_if_done
 hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st, bool skip_if_done,
                        hipStream_t s);
+// p = r + beta p with beta = (sum of the n partials) / st->rr formed by every block in a fixed order
+// (the partials of the update hop's |r|^2); sets st->beta_pending; nothing once st->done
+hipError_t launch_xpay_fused(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st,
+                             const double* partials, int n, hipStream_t s);
 // p = r + beta p for n <= 8 lattices (FP64 even fields), skipping lattices whose solve has stopped
 hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* const* r, CgState* const* st, int n,
                              int max_grid, hipStream_t s);
@@ -137,11 +150,19 @@ hipError_t launch_set_state(CgState* st, const StateInit& v, hipStream_t s);
 // Second pass of a CG reduction over n partials (one block per lattice):
 //   kFinishAlpha: pAp = sum, alpha = rr / pAp (done = breakdown unless pAp > 0)
 //   kFinishBeta:  rr_prev = rr, rr = sum, beta = rr / rr_prev, iter + 1, stop tests
+//   kFinishBetaPending: kFinishBeta if st->beta_pending (then cleared), else nothing: the CG
+//                 iteration forms beta in its search-direction update (launch_xpay_fused) and
+//                 leaves this finish to the next launch that carries it
 // Nothing happens for a lattice whose st->done is set.
-enum FinishKind { kFinishAlpha = 0, kFinishBeta = 1 };
+enum FinishKind { kFinishAlpha = 0, kFinishBeta = 1, kFinishBetaPending = 2 };
 hipError_t launch_cg_finish(CgState* st, const double* partials, int n, int kind, hipStream_t s);
 hipError_t launch_cg_finish_batch(CgState* const* st, const double* const* partials, const int* n, int count,
                                   int kind, hipStream_t s);
+// The multi-RHS CG: column c's reduction (tiles partials at partials + c * tiles) finished on st[c]
+// for c < ncol; p_c = r_c + beta_c p_c for the running columns (FP64 fields fstride bytes apart)
+hipError_t launch_cg_finish_cols(CgState* st, const double* partials, int tiles, int ncol, int kind, hipStream_t s);
+hipError_t launch_xpay_cols(const VecSpec& v, void* p, const void* r, int64_t fstride, int ncol, const CgState* st,
+                            hipStream_t s);
 // st->rr = st->result[slot]; optionally stop_rr = factor * rr
 hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipStream_t s);
 
@@ -179,5 +200,10 @@ hipError_t launch_su3_sweep(const Geom& g, void* gauge, int prec, double beta, u
 hipError_t launch_mom_norm2(const Geom& g, const double* mom, double* result, double* partials, hipStream_t s);
 hipError_t launch_spinor_dot(const Geom& g, const void* x, const void* y, int nhalf, double* result, double* partials,
                              hipStream_t s);
+// result[0..3] = (dH, kinetic, gauge, fermion parts) between (u0, p0, x0) and (u1, p1, x1), summed site by site
+// (pseudofermion phi and the solutions x0, x1 on the first fermion_parities halves: 1 even, 2 full)
+hipError_t launch_delta_h(const Geom& g, const void* u0, const void* u1, const double* p0, const double* p1,
+                          const void* phi, const void* x0, const void* x1, int fermion_parities, double beta, double c1,
+                          double* result, double* partials, hipStream_t s);
 
 }  // namespace tmqcd

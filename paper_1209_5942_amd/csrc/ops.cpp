@@ -7,16 +7,19 @@
 // the upper two spins as (1 - i w) and on the lower two as (1 + i w).  The
 // adjoints use H^+ (gamma_mu -> -gamma_mu) and A^+ = A(-mu).
 //
-// One CG iteration on Mhat^+ Mhat is four hop launches, a one-block
-// reduction finish and one BLAS launch:
-//   t1 = A^{-1} H_oe p
+// One CG iteration on Mhat^+ Mhat is four hop launches and one BLAS launch:
+//   t1 = A^{-1} H_oe p                         its block 0 first finishes the
+//                                               previous iteration's |r|^2, beta
+//                                               and stop tests (when pending)
 //   t2 = A p - kappa^2 H_eo t1                 and per-block sums of |t2|^2
 //   t3 = A(-mu)^{-1} H^+_oe t2                 its block 0 first finishes
 //                                               p^+ A p = |t2|^2 and alpha
 //   (A p) = A(-mu) t2 - kappa^2 H^+_eo t3      fused with x += alpha p,
 //                                               r -= alpha A p, per-block |r|^2
-//   finish: |r|^2, beta, stop tests
-//   p = r + beta p
+//   p = r + beta p                             every block forms beta itself
+//                                               from those partials (the same
+//                                               fixed order in every block)
+// and the host reads the state after a one-block finish of the last beta.
 // The reductions finish in a later launch: a last-block-done scheme would
 // need a device-wide release in every block, which on this chip writes back
 // the XCD's L2 and costs more than a launch.
@@ -97,7 +100,7 @@ hipError_t op_dslash_pq(const OpCtx& c, const void* in, void* out, int out_parit
 }
 
 // full field: out = A(+-mu) in - kappa H(^+) in
-static HopParams hp_full(const OpCtx& c, const void* in, void* out, bool dag, int epi, CgState* st, double* partials,
+HopParams hp_full(const OpCtx& c, const void* in, void* out, bool dag, int epi, CgState* st, double* partials,
                          void* x, void* r, const void* p, const Rhs& rh) {
     HopParams a = base_params(c);
     a.in = in;
@@ -276,6 +279,7 @@ CgWorkspace carve_cg(const Geom& g, int op, int inner_prec, char* base) {
     };
     w.st = reinterpret_cast<CgState*>(take(sizeof(CgState)));
     w.partials = reinterpret_cast<double*>(take(partial_bytes(g)));
+    w.partials_b = reinterpret_cast<double*>(take(partial_bytes(g)));
     const int64_t h64 = half_field_bytes(g, TMQCD_F64);
     w.r = take(nh * h64);
     w.p = take(nh * h64);
@@ -318,39 +322,56 @@ struct Fields {
 };
 
 // Queue one CG iteration (all precisions): see the file header.  Every stage
-// carries the solver state, so stages queued after the stop return at once.
-hipError_t queue_iteration(const OpCtx& c, bool full, const Fields& f, CgState* st, double* partials, int pv) {
+// carries the solver state, so stages queued after the stop return at once.  The
+// alpha reductions use partials_a, the beta reductions partials_b: the first hop
+// of an iteration finishes the previous iteration's beta (from partials_b) while
+// it writes nothing there.  nb_update: the partial count of the update hop (set
+// by the first iteration queued; the first hop of that one has no pending finish).
+hipError_t queue_iteration(const OpCtx& c, bool full, const Fields& f, CgState* st, double* partials_a,
+                           double* partials_b, int pv, int& nb_update) {
     hipError_t e;
     int nb = 0;
     VecSpec vs{&c.g, full ? 2 : 1};
     if (full) {
-        e = launch_hop(hp_full(c, f.p, f.t1, false, kEpiStoreNorm, st, partials, nullptr, nullptr, nullptr, kOne), c.s,
-                       &nb);
-        if (e == hipSuccess) e = launch_cg_finish(st, partials, nb, kFinishAlpha, c.s);
+        HopParams k1 = hp_full(c, f.p, f.t1, false, kEpiStoreNorm, st, partials_a, nullptr, nullptr, nullptr, kOne);
+        k1.fin_partials = partials_b;
+        k1.fin_n = nb_update;
+        k1.fin_kind = kFinishBetaPending;
+        e = launch_hop(k1, c.s, &nb);
+        if (e == hipSuccess) e = launch_cg_finish(st, partials_a, nb, kFinishAlpha, c.s);
         if (e == hipSuccess)
-            e = launch_hop(hp_full(c, f.t1, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p, kOne), c.s, &nb);
+            e = launch_hop(hp_full(c, f.t1, nullptr, true, kEpiCgUpdate, st, partials_b, f.x, f.r, f.p, kOne), c.s,
+                           &nb_update);
     } else {
         HopParams k1 = hp_schur_first(c, f.p, f.t1, false, kOne);
         HopParams k3 = hp_schur_first(c, f.t2, f.t3, true, kOne);
         k1.st = k3.st = st;
+        k1.fin_partials = partials_b;
+        k1.fin_n = nb_update;
+        k1.fin_kind = kFinishBetaPending;
         e = launch_hop(k1, c.s);
         if (e == hipSuccess)
-            e = launch_hop(hp_schur_second(c, f.t1, f.p, f.t2, false, kEpiStoreNorm, st, partials, nullptr, nullptr,
+            e = launch_hop(hp_schur_second(c, f.t1, f.p, f.t2, false, kEpiStoreNorm, st, partials_a, nullptr, nullptr,
                                            nullptr, kOne),
                            c.s, &nb);
         // the first block of the next hop finishes p^+ A p and alpha (the update hop after it needs alpha)
-        k3.fin_partials = partials;
+        k3.fin_partials = partials_a;
         k3.fin_n = nb;
         k3.fin_kind = kFinishAlpha;
         if (e == hipSuccess) e = launch_hop(k3, c.s);
         if (e == hipSuccess)
-            e = launch_hop(hp_schur_second(c, f.t3, f.t2, nullptr, true, kEpiCgUpdate, st, partials, f.x, f.r, f.p,
+            e = launch_hop(hp_schur_second(c, f.t3, f.t2, nullptr, true, kEpiCgUpdate, st, partials_b, f.x, f.r, f.p,
                                            kOne),
-                           c.s, &nb);
+                           c.s, &nb_update);
     }
-    if (e == hipSuccess) e = launch_cg_finish(st, partials, nb, kFinishBeta, c.s);
     if (e != hipSuccess) return e;
-    return launch_xpay(vs, f.p, c.prec, f.r, pv, st, true, c.s);
+    // p = r + beta p with beta formed from the update's partials; the state's beta finish is pending
+    return launch_xpay_fused(vs, f.p, c.prec, f.r, pv, st, partials_b, nb_update, c.s);
+}
+
+// The pending beta finish of the last iteration queued (before the host reads the state).
+hipError_t finish_pending(CgState* st, const double* partials_b, int nb_update, hipStream_t s) {
+    return nb_update > 0 ? launch_cg_finish(st, partials_b, nb_update, kFinishBetaPending, s) : hipSuccess;
 }
 
 struct HostState {
@@ -494,10 +515,13 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
         return launch_set_state(w.st, v, s);
     };
     TRY(start_cycle(rr));
+    int nb_update = 0;   // partials of the update hop (known once an iteration has been queued)
     if (graph) {   // every stage of an iteration queued after the stop returns at once, so replays are safe
         TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipError_t ec = hipSuccess;
-        for (int k = 0; k < kGraphIters && ec == hipSuccess; ++k) ec = queue_iteration(cq, full, f, w.st, w.partials, pv);
+        for (int k = 0; k < kGraphIters && ec == hipSuccess; ++k)
+            ec = queue_iteration(cq, full, f, w.st, w.partials, w.partials_b, pv, nb_update);
+        if (ec == hipSuccess) ec = finish_pending(w.st, w.partials_b, nb_update, s);   // each replay ends finished
         const hipError_t ee = hipStreamEndCapture(s, &ig.graph);
         TRY(ec);
         TRY(ee);
@@ -517,7 +541,9 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
                 if (graph) {
                     for (int k = 0; k < batch; k += kGraphIters) TRY(hipGraphLaunch(ig.exec, s));
                 } else {
-                    for (int k = 0; k < batch; ++k) TRY(queue_iteration(cq, full, f, w.st, w.partials, pv));
+                    for (int k = 0; k < batch; ++k)
+                        TRY(queue_iteration(cq, full, f, w.st, w.partials, w.partials_b, pv, nb_update));
+                    TRY(finish_pending(w.st, w.partials_b, nb_update, s));
                 }
                 TRY(read_state(w.st, hs, s));
                 if (hs.s.done != kDoneRunning) break;
@@ -575,6 +601,7 @@ int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b,
         TRY(start_cycle(rr));
     }
     stats.iters = iters_done;
+    stats.inner_iters = mixed ? iters_done : 0;
     stats.hop_launches = hops_per_apply * (iters_done + applies);
     stats.true_rel_residual = std::sqrt(rr / bb);
     TRY(hipStreamSynchronize(s));

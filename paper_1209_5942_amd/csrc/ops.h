@@ -32,6 +32,10 @@ HopParams hp_schur_first(const OpCtx& c, const void* in_e, void* t_o, bool dag, 
 HopParams hp_schur_second(const OpCtx& c, const void* t_o, const void* own_e, void* out_e, bool dag, int epi,
                           CgState* st, double* partials, void* x, void* r, const void* p, const Rhs& rh);
 
+// full field: out = A(+-mu) in - kappa H(^+) in, with the epilogue epi (see ops.cpp)
+HopParams hp_full(const OpCtx& c, const void* in, void* out, bool dag, int epi, CgState* st, double* partials,
+                  void* x, void* r, const void* p, const Rhs& rh);
+
 // out = op(in) for nrhs consecutive fields; tmp must hold nrhs * dslash_tmp_bytes(g, op, prec) bytes
 hipError_t apply_operator(const OpCtx& c, int op, const void* in, void* out, char* tmp, int nrhs);
 int64_t dslash_tmp_bytes(const Geom& g, int op, int prec);
@@ -43,7 +47,8 @@ int64_t force_eo_tmp_bytes(const Geom& g);
 
 struct CgWorkspace {
     CgState* st;
-    double* partials;
+    double* partials;                         // the alpha reductions (and standalone ones)
+    double* partials_b;                       // the beta reductions of the update hop
     void *r, *p, *ax, *t1, *t2, *t3;          // FP64
     void *rs, *xs, *ps, *t1s, *t2s, *t3s;     // inner precision (mixed)
     int64_t total;
@@ -81,5 +86,18 @@ int64_t bicgstab_workspace(const Geom& g, int op);
 
 int run_cg(const tmqcd_problem& prob, const void* const gauge[3], const void* b, void* x, const tmqcd_cg_opts& o,
            tmqcd_cg_stats& stats, void* ws, hipStream_t s);
+
+// CG on o.nrhs > 1 right-hand sides at once (FP64; cg_mrhs.cpp): b, x hold o.nrhs packed fields one after
+// the other, stats[o.nrhs]; workspace carve_cg_mrhs(g, op, n, nullptr).total bytes
+struct MrhsWorkspace {
+    CgState* st;                 // CgState[n]
+    double* partials;            // [n][tiles_max]: the multi-RHS launches' per-column sums
+    double* setup_partials;      // [n][col_partials]: per-column set-up and residual reductions
+    char *r, *p, *ax, *t1, *t2;  // n columns each, fstride bytes apart (t1, t2: the operator's temporaries)
+    int64_t fstride, tiles_max, col_partials, total;
+};
+MrhsWorkspace carve_cg_mrhs(const Geom& g, int op, int n, char* base);
+int run_cg_mrhs(const tmqcd_problem& prob, const void* gauge, const void* b, void* x, const tmqcd_cg_opts& o,
+                tmqcd_cg_stats* stats, void* ws, hipStream_t s);
 
 }  // namespace tmqcd

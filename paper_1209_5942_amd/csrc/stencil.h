@@ -70,7 +70,8 @@ struct HopK {
     int L[4];
     int lxh, vh, nb_half, nblocks, out_parity, nparity;
     int order, width;        // block order (kOrder*) and output sites per block
-    int slice, q, tq, lt;    // slab order: half sites per t-slice, per XCD range, blocks per range
+    int slice, q, tq, lt;    // slab orders: half sites per t-slice, per z-range, blocks per (slice, range)
+    int nz, tlen;            // slab orders: z-ranges per slice, slices per t-range
     int by, bz, nry, nreg;   // column order: region extent in y and z, regions in y, regions
     const double* fin_partials;   // the previous launch's reduction, finished by block 0 first
     int fin_n, fin_kind;
@@ -84,10 +85,15 @@ struct HopK {
 //  kOrderXcdRemap: the same after the per-XCD remap of the block index (each
 //                  XCD gets a contiguous range of tiles);
 //  kOrderSlab:     the half sites of every t-slice are cut into 8 contiguous
-//                  ranges of q sites, range x belonging to XCD x (hardware
-//                  blocks go round-robin over the XCDs); each XCD walks through
-//                  its ranges slice by slice, so the t-neighbours it reads
-//                  belong to slices it has in flight;
+//                  ranges of q sites (runs of z-planes), range x belonging to
+//                  XCD x (hardware blocks go round-robin over the XCDs); each
+//                  XCD walks through its ranges slice by slice, so the
+//                  t-neighbours it reads belong to slices it has in flight;
+//  kOrderSlabT2/4: the same with the lattice cut into nz = 4 (2) z-ranges
+//                  times nt = 2 (4) t-ranges, XCD x owning z-range x % nz of
+//                  t-range x / nz: half (a quarter) of the faces between the
+//                  XCDs' z-ranges, for one t-face per t-range and a working
+//                  set per slice twice (four times) as large;
 //  kOrderColumn:   the (y, z) plane is cut into regions of by x bz (all x), and
 //                  XCD x sweeps its regions x, x + 8, ... one after the other,
 //                  each through all t: the neighbours an XCD reads lie in the
@@ -106,12 +112,14 @@ __device__ __forceinline__ bool block_site(const HopK& a, int b, int lane, int& 
         return h < a.vh;
     }
     const int x = lb & (kNumXcd - 1), k = lb / kNumXcd;
-    if (a.order == kOrderSlab) {
-        const int t = k / a.tq, j = k - t * a.tq;
-        const int first = x * a.q + j * a.width + lane;
-        const int end = min((x + 1) * a.q, a.slice);
+    if (slab_order(a.order)) {
+        const int zr = x % a.nz, tr = x / a.nz;
+        const int tl = k / a.tq, j = k - tl * a.tq;
+        const int t = tr * a.tlen + tl;
+        const int first = zr * a.q + j * a.width + lane;
+        const int end = min((zr + 1) * a.q, a.slice);
         h = t * a.slice + first;
-        return first < end;
+        return t < a.lt && first < end;
     }
     const int per = a.lt * a.tq;             // blocks per region
     const int ri = k / per, rem = k - ri * per;
@@ -371,10 +379,13 @@ inline HopK make_hopk(const HopParams& a, int w) {
     k.fin_kind = a.fin_kind;
     k.lt = a.g.L[3];
     k.slice = (int)(a.g.vh / a.g.L[3]);
-    k.q = (k.slice + kNumXcd - 1) / kNumXcd;
+    k.nz = a.order == kOrderSlabT2 ? 4 : (a.order == kOrderSlabT4 ? 2 : kNumXcd);
+    const int nt = kNumXcd / k.nz;
+    k.tlen = (k.lt + nt - 1) / nt;
+    k.q = (k.slice + k.nz - 1) / k.nz;
     k.tq = (k.q + w - 1) / w;
     column_regions(a, k);
-    if (a.order == kOrderSlab) k.nb_half = kNumXcd * k.lt * k.tq;
+    if (slab_order(a.order)) k.nb_half = kNumXcd * k.tlen * k.tq;
     else if (a.order == kOrderColumn) {
         const int tqc = (k.lxh * k.by * k.bz + w - 1) / w;
         k.nb_half = kNumXcd * ((k.nreg + kNumXcd - 1) / kNumXcd) * k.lt * tqc;

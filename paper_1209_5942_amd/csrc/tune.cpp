@@ -139,9 +139,11 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
     const VecSpec vs{&g, 1};
     const int64_t hd = half_field_bytes(g, prec), hv = half_field_bytes(g, pv);
     // block size x block order; the first is the default and the reference
-    const int shapes[8][2] = {{256, kOrderXcdRemap}, {256, kOrderLinear}, {128, kOrderXcdRemap},
-                              {128, kOrderLinear},   {256, kOrderSlab},   {128, kOrderSlab},
-                              {256, kOrderColumn},   {128, kOrderColumn}};
+    constexpr int kShapes = 2 * kNumOrders;
+    const int shapes[kShapes][2] = {{256, kOrderXcdRemap}, {256, kOrderLinear}, {128, kOrderXcdRemap},
+                                    {128, kOrderLinear},   {256, kOrderSlab},   {128, kOrderSlab},
+                                    {256, kOrderColumn},   {128, kOrderColumn}, {256, kOrderSlabT2},
+                                    {128, kOrderSlabT2},   {256, kOrderSlabT4}, {128, kOrderSlabT4}};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const std::string arch = current_arch();
     TRY(hipEventCreate(&e0));
@@ -156,7 +158,7 @@ int run_tune(const tmqcd_problem& prob, const void* gauge, int prec, int recon, 
         res.kernel_class = cls;
         double ref_scalar = 0;
         double best = 1e30;
-        for (int v = 0; v < 8; ++v) {
+        for (int v = 0; v < kShapes; ++v) {
             HopParams a;
             if (cls == 0) a = hp_schur_first(c, w.in_e, w.t_o, false, kOne);
             else if (cls == 1)
@@ -263,7 +265,8 @@ int run_tune_mrhs(const tmqcd_problem& prob, const void* gauge, int prec, int re
     char* ref = out + nrhs * hd;
     const OpCtx c = make_ctx(prob, prec, recon, gauge, s);
     const VecSpec vs{&g, 1};
-    const int orders[kNumOrders] = {kOrderSlab, kOrderLinear, kOrderXcdRemap, kOrderColumn};   // first: default
+    const int orders[kNumOrders] = {kOrderSlab,   kOrderLinear,  kOrderXcdRemap,
+                                    kOrderColumn, kOrderSlabT2,  kOrderSlabT4};   // first: default
     // right-hand sides per block: all (the default), about a half, about a third
     const int groups[3] = {0, (nrhs + 1) / 2, (nrhs + 2) / 3};
     hipEvent_t e0 = nullptr, e1 = nullptr;

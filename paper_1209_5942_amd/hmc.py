@@ -19,7 +19,8 @@ Metropolis step.  Here:
   2MN steps of the gauge force (Sexton-Weingarten nesting); lam = LAMBDA_2MN.
   Adjacent kicks at the same links are merged, so an outer step costs two
   fermion forces (one solve each);
-* Metropolis: accept with probability min(1, exp(-(H' - H))).
+* Metropolis: accept with probability min(1, exp(-(H' - H))), with H' - H summed site
+  by site in FP64 on the device (tmqcd_delta_h) from both states.
 
 Every step runs in libtmqcd kernels (CG, force, gauge force, link update,
 reductions); torch provides device buffers and the copies that keep the
@@ -67,9 +68,8 @@ class FermionAction(torch.autograd.Function):
         h = ctx.h
         if h.eo:
             return T.force_eo(h.prob, ctx.U, ctx.X, scale=float(grad_out), ws=h.ws_force), None
-        Y = T.dslash(h.prob, ctx.U, ctx.X, T.M, ws=h.ws_dslash)
-        G = T.force(h.prob, ctx.U, ctx.X, Y, scale=float(grad_out))
-        return G, None
+        # Y = M X is formed by the force call itself, in its workspace
+        return T.force(h.prob, ctx.U, ctx.X, None, scale=float(grad_out), ws=h.ws_force), None
 
 
 class HMC:
@@ -114,10 +114,9 @@ class HMC:
         self.ws_cg = T.workspace(prob, self.op, 1 | (1 << inner_prec))
         self.ws_dslash = T.workspace(prob, self.op, 1)
         self.ws_aux = T.aux_workspace(prob)
-        self.ws_force = T._bytes(T.force_eo_workspace_bytes(prob), dev) if eo else None
+        self.ws_force = T._bytes(T.force_eo_workspace_bytes(prob) if eo else T.force_workspace_bytes(prob), dev)
         self.ws_gauge = T._bytes(T.gauge_force_tlsym_workspace_bytes(prob), dev) if c1 != 0.0 else None
         self.X = torch.empty(fb, dtype=torch.uint8, device=dev)
-        self.Y = torch.empty(fb, dtype=torch.uint8, device=dev)
         self.phi = torch.empty(fb, dtype=torch.uint8, device=dev)
         self.solves = 0
         self.cg_iters = 0
@@ -161,8 +160,7 @@ class HMC:
         if self.eo:
             T.force_eo(self.prob, self.U, X, out=p, scale=scale, accumulate=True, ws=self.ws_force)
         else:
-            T.dslash(self.prob, self.U, X, T.M, out=self.Y, ws=self.ws_dslash)
-            T.force(self.prob, self.U, X, self.Y, out=p, scale=scale, accumulate=True)
+            T.force(self.prob, self.U, X, None, out=p, scale=scale, accumulate=True, ws=self.ws_force)
 
     def add_gauge_gradient(self, p, scale):
         """p += scale * G_gauge at the current links."""
@@ -242,15 +240,19 @@ class HMC:
         self.refresh_low()            # the links may have been set from outside
         self.set_pseudofermion(eta_canon)
         e0 = self.energies(p)
-        U0 = self.U.clone()
+        U0, p0, X0 = self.U.clone(), p.clone(), self.X.clone()
         if integrator == "leapfrog":
             self.leapfrog(p, n_steps, dt)
         else:
             self.omelyan(p, n_steps, dt, n_inner)
         e1 = self.energies(p)
-        dh = sum(e1) - sum(e0)
+        # dH summed site by site in FP64 on the device, from both states' links, momenta and solutions
+        d = T.delta_h(self.prob, U0, self.U, p0, p, self.phi, X0, self.X, self.subset, self.beta, self.c1,
+                      ws=self.ws_aux)
+        dh = float(d[0])
         accepted = bool(uniform < math.exp(-dh)) if dh > 0 else True
         if not accepted:
             self.U.copy_(U0)
             self.refresh_low()
-        return {"dH": dh, "accepted": accepted, "H0": sum(e0), "H1": sum(e1), "energies0": e0, "energies1": e1}
+        return {"dH": dh, "accepted": accepted, "H0": sum(e0), "H1": sum(e1), "energies0": e0, "energies1": e1,
+                "dH_parts": [float(v) for v in d[1:].cpu()], "dH_from_totals": sum(e1) - sum(e0)}

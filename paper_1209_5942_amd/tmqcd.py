@@ -29,12 +29,12 @@ OP_SUBSETS = {DSLASH_EO: (ODD, EVEN), DSLASH_OE: (EVEN, ODD), M: (FULL, FULL), M
 ENTRY_POINTS = ("tmqcd_gauge_bytes", "tmqcd_spinor_bytes", "tmqcd_workspace_bytes", "tmqcd_pack_gauge",
                 "tmqcd_unpack_gauge", "tmqcd_pack_spinor", "tmqcd_unpack_spinor", "tmqcd_dslash", "tmqcd_cg",
                 "tmqcd_cg_batch_workspace_bytes", "tmqcd_cg_batch", "tmqcd_bicgstab_workspace_bytes",
-                "tmqcd_bicgstab", "tmqcd_force", "tmqcd_force_eo_workspace_bytes", "tmqcd_force_eo",
+                "tmqcd_bicgstab", "tmqcd_force_workspace_bytes", "tmqcd_force", "tmqcd_force_eo_workspace_bytes", "tmqcd_force_eo",
                 "tmqcd_gauge_force", "tmqcd_gauge_force_tlsym_workspace_bytes", "tmqcd_gauge_force_tlsym", "tmqcd_rectangle", "tmqcd_heatbath",
                 "tmqcd_overrelax", "tmqcd_update_links", "tmqcd_tune_workspace_bytes", "tmqcd_tune",
                 "tmqcd_tune_save", "tmqcd_tune_load", "tmqcd_tune_clear", "tmqcd_tune_set",
                 "tmqcd_tune_mrhs_workspace_bytes", "tmqcd_tune_mrhs", "tmqcd_plaquette", "tmqcd_momentum_norm2",
-                "tmqcd_dot", "tmqcd_hbm_probe", "tmqcd_error_string", "tmqcd_last_hip_error",
+                "tmqcd_dot", "tmqcd_delta_h", "tmqcd_hbm_probe", "tmqcd_error_string", "tmqcd_last_hip_error",
                 "tmqcd_noalloc_scratch_bytes", "tmqcd_dslash_noalloc")
 
 
@@ -56,16 +56,18 @@ class CProblem(ctypes.Structure):
 class CCgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("op", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("recon", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
-                ("check_every", ctypes.c_int32), ("x_is_zero", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("x_is_zero", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("nrhs", ctypes.c_int32)]
 
 
 class CCgStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("hop_launches", ctypes.c_int32), ("true_rel_residual", ctypes.c_double),
-                ("iter_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("iter_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("inner_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class CTuneResult(ctypes.Structure):
@@ -103,7 +105,8 @@ def lib():
             "tmqcd_bicgstab_workspace_bytes": (S, [P, I]),
             "tmqcd_bicgstab": (I, [P, V, V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats), V, S, V]),
             "tmqcd_cg_batch": (I, [I, P, V, V, V, ctypes.POINTER(CCgOpts), ctypes.POINTER(CCgStats), I, V, S, V]),
-            "tmqcd_force": (I, [P, V, I, V, V, V, D, I, V]),
+            "tmqcd_force_workspace_bytes": (S, [P]),
+            "tmqcd_force": (I, [P, V, I, V, V, V, D, I, V, S, V]),
             "tmqcd_force_eo_workspace_bytes": (S, [P]),
             "tmqcd_force_eo": (I, [P, V, I, V, V, D, I, V, S, V]),
             "tmqcd_gauge_force": (I, [P, V, D, V, D, I, V]),
@@ -116,6 +119,7 @@ def lib():
             "tmqcd_plaquette": (I, [P, V, V, V, S, V]),
             "tmqcd_momentum_norm2": (I, [P, V, V, V, S, V]),
             "tmqcd_dot": (I, [P, V, V, I, V, V, S, V]),
+            "tmqcd_delta_h": (I, [P, V, V, V, V, V, V, V, I, D, D, V, V, S, V]),
             "tmqcd_tune_workspace_bytes": (S, [P, I]),
             "tmqcd_tune": (I, [P, V, I, I, V, S, ctypes.POINTER(CTuneResult), V]),
             "tmqcd_tune_save": (I, [ctypes.c_char_p]),
@@ -264,29 +268,33 @@ def dslash_noalloc(prob: Problem, U_packed, inp, out, op, prec=F64, recon=RECON1
 
 def cg(prob: Problem, U_packed: dict, b, x=None, *, x_is_zero=None, tol=1e-10, max_iter=10000, op=MHATDAGMHAT,
        inner_prec=F64, recon=RECON18, reliable_delta=0.0, check_every=0, ws=None, stream=None,
-       raise_on_noconv=True, use_graph=0):
+       raise_on_noconv=True, use_graph=0, nrhs=1, raise_on_breakdown=True):
     """Solve op x = b (packed FP64 fields).  U_packed maps precision -> packed gauge field.
 
     x: output buffer (allocated when None).  x_is_zero: start from x0 = 0 (default: when x is None);
     otherwise the contents of x are the start vector.  use_graph: 1 replays the iterations from a
-    captured hipGraph, 0 or -1 launches them one by one.  Returns (x, stats dict, return code)."""
+    captured hipGraph, 0 or -1 launches them one by one.  nrhs > 1: b and x hold nrhs fields solved
+    together (FP64), and the stats are a list of per-column dicts.  TMQCD_ENOCONV and TMQCD_EBREAKDOWN
+    raise unless raise_on_noconv / raise_on_breakdown is False.  Returns (x, stats, return code)."""
     subset = FULL if op == MDAGM else EVEN
     if x_is_zero is None:
         x_is_zero = x is None
     if x is None:
-        x = _bytes(spinor_bytes(prob, F64, subset))
+        x = _bytes(spinor_bytes(prob, F64, subset, nrhs))
     if ws is None:
-        ws = _bytes(workspace_bytes(prob, op, 1 | (1 << inner_prec)))
+        ws = _bytes(workspace_bytes(prob, op, 1 | (1 << inner_prec), nrhs))
     gp = (ctypes.c_void_p * 3)(*[_ptr(U_packed.get(p)) for p in (F64, F32, F16)])
     o = CCgOpts(tol=tol, max_iter=max_iter, op=op, inner_prec=inner_prec, recon=recon,
                 reliable_delta=reliable_delta, check_every=check_every, x_is_zero=int(x_is_zero),
-                use_graph=int(use_graph))
-    st = CCgStats()
+                use_graph=int(use_graph), nrhs=int(nrhs))
+    st = (CCgStats * max(1, nrhs))()
     rc = lib().tmqcd_cg(ctypes.byref(prob.c()), ctypes.byref(gp), _ptr(b), _ptr(x), ctypes.byref(o),
-                        ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream))
-    if rc not in (OK, ENOCONV) or (rc == ENOCONV and raise_on_noconv):
+                        st, _ptr(ws), ws.numel(), _stream(stream))
+    tolerated = (OK,) + (() if raise_on_noconv else (ENOCONV,)) + (() if raise_on_breakdown else (EBREAKDOWN,))
+    if rc not in tolerated:
         raise TmqcdError(rc, "tmqcd_cg")
-    return x, st.as_dict(), rc
+    stats = [s.as_dict() for s in st]
+    return x, (stats if nrhs > 1 else stats[0]), rc
 
 
 def bicgstab_workspace_bytes(prob: Problem, op=MHAT) -> int:
@@ -389,12 +397,21 @@ def _mom(prob: Problem, out, like):
     return out
 
 
-def force(prob: Problem, U_packed, X, Y, recon=RECON18, out=None, scale=1.0, accumulate=False, stream=None):
-    """scale * dS_f/dw^a (float64 device tensor (V, 4, 8)) from packed FP64 full fields X and Y = M X;
-    with accumulate the result is added to `out`."""
+def force_workspace_bytes(prob: Problem) -> int:
+    return lib().tmqcd_force_workspace_bytes(ctypes.byref(prob.c()))
+
+
+def force(prob: Problem, U_packed, X, Y=None, recon=RECON18, out=None, scale=1.0, accumulate=False, ws=None,
+          stream=None):
+    """scale * dS_f/dw^a (float64 device tensor (V, 4, 8)) from packed FP64 full fields X and Y = M X
+    (Y None: computed by the library into ws, allocated when None); with accumulate the result is
+    added to `out`."""
     out = _mom(prob, out, X)
+    if Y is None and ws is None:
+        ws = _bytes(force_workspace_bytes(prob), X.device)
+    nbytes = 0 if ws is None else ws.numel() * ws.element_size()
     _check(lib().tmqcd_force(ctypes.byref(prob.c()), _ptr(U_packed), recon, _ptr(X), _ptr(Y), _ptr(out),
-                             float(scale), int(accumulate), _stream(stream)), "tmqcd_force")
+                             float(scale), int(accumulate), _ptr(ws), nbytes, _stream(stream)), "tmqcd_force")
     return out
 
 
@@ -500,4 +517,16 @@ def dot(prob: Problem, x, y, subset=FULL, ws=None, out=None, stream=None):
     out = _result(2, x) if out is None else out
     _check(lib().tmqcd_dot(ctypes.byref(prob.c()), _ptr(x), _ptr(y), subset, _ptr(out), _ptr(ws), ws.numel(),
                            _stream(stream)), "tmqcd_dot")
+    return out
+
+
+def delta_h(prob: Problem, U0, U1, p0, p1, phi, X0, X1, subset=FULL, beta=0.0, c1=0.0, ws=None, out=None,
+            stream=None):
+    """Device tensor [dH, kinetic, gauge, fermion] between (U0, p0, X0) and (U1, p1, X1), summed site by site
+    in FP64 (packed FP64 RECON18 links, momenta (V, 4, 8), packed FP64 fields phi, X of `subset`)."""
+    ws = aux_workspace(prob) if ws is None else ws
+    out = _result(4, p0) if out is None else out
+    _check(lib().tmqcd_delta_h(ctypes.byref(prob.c()), _ptr(U0), _ptr(U1), _ptr(p0), _ptr(p1), _ptr(phi), _ptr(X0),
+                               _ptr(X1), subset, float(beta), float(c1), _ptr(out), _ptr(ws), ws.numel(),
+                               _stream(stream)), "tmqcd_delta_h")
     return out

@@ -110,6 +110,21 @@ def test_cg_argument_errors(L):
     assert call(ws=None) == T.EWORKSPACE
     assert call(wsb=1024) == T.EWORKSPACE
     assert call(b=(1 << 32) + 4) == T.EALIGN
+    # several right-hand sides: FP64 only, no graph, up to 16; b and x span nrhs fields each
+    assert call(nrhs=17) == T.EINVAL
+    assert call(nrhs=-1) == T.EINVAL
+    gp2 = (ctypes.c_void_p * 3)(1 << 30, 1 << 31, None)
+    o = dict(tol=1e-10, max_iter=100, op=T.MHATDAGMHAT, inner_prec=T.F32, recon=0, reliable_delta=0.0,
+             check_every=0, x_is_zero=1, nrhs=2)
+    assert L.tmqcd_cg(ctypes.byref(prob.c()), ctypes.byref(gp2), 1 << 32, 1 << 34, ctypes.byref(T.CCgOpts(**o)),
+                      ctypes.byref(st), 1 << 36, 1 << 30, None) == T.EINVAL
+    assert call(nrhs=2, use_graph=1) == T.EINVAL
+    fe = T.spinor_bytes(prob, T.F64, T.EVEN)
+    assert call(nrhs=2, x=(1 << 32) + fe) == T.EALIAS          # x overlaps the second column of b
+    need1 = T.workspace_bytes(prob, T.MHATDAGMHAT, 1, 1)
+    need2 = T.workspace_bytes(prob, T.MHATDAGMHAT, 1, 2)
+    assert need2 > need1
+    assert call(nrhs=2, wsb=need2 - 256) == T.EWORKSPACE
 
 
 def test_pack_and_force_argument_errors(L):
@@ -119,9 +134,17 @@ def test_pack_and_force_argument_errors(L):
     assert L.tmqcd_pack_gauge(p, (1 << 30) + 8, 1 << 32, 0, 0, None) == T.EALIGN
     assert L.tmqcd_pack_spinor(p, 1 << 30, 1 << 30, 0, 0, 1, None) == T.EALIAS
     assert L.tmqcd_pack_spinor(p, 1 << 30, 1 << 32, 0, 5, 1, None) == T.EINVAL
-    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, None, 1 << 34, 1.0, 0, None) == T.EINVAL
-    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, 1 << 34, 1.0, 2, None) == T.EINVAL
-    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, 1 << 32, 1.0, 0, None) == T.EALIAS
+    # X and dSdw are required; Y = NULL asks the call to form Y = M X in ws
+    assert L.tmqcd_force(p, 1 << 30, 0, None, 1 << 33, 1 << 34, 1.0, 0, None, 0, None) == T.EINVAL
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, None, 1.0, 0, None, 0, None) == T.EINVAL
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, 1 << 34, 1.0, 2, None, 0, None) == T.EINVAL
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, 1 << 33, 1 << 32, 1.0, 0, None, 0, None) == T.EALIAS
+    fb = T.spinor_bytes(prob, T.F64, T.FULL)
+    assert L.tmqcd_force_workspace_bytes(p) == fb
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, None, 1 << 34, 1.0, 0, None, 0, None) == T.EWORKSPACE
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, None, 1 << 34, 1.0, 0, 1 << 36, fb - 1, None) == T.EWORKSPACE
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, None, 1 << 34, 1.0, 0, (1 << 36) + 16, fb, None) == T.EALIGN
+    assert L.tmqcd_force(p, 1 << 30, 0, 1 << 32, None, 1 << 34, 1.0, 0, 1 << 32, fb, None) == T.EALIAS
     assert L.tmqcd_gauge_force(p, 1 << 30, float("nan"), 1 << 34, 1.0, 0, None) == T.EINVAL
     assert L.tmqcd_gauge_force(p, 1 << 30, 5.0, 1 << 30, 1.0, 0, None) == T.EALIAS
     assert L.tmqcd_update_links(p, 1 << 30, (1 << 34) + 4, 0.1, None) == T.EALIGN
@@ -261,7 +284,7 @@ def test_tune_set_validation_and_roundtrip(L, tmp_path):
     p = ctypes.byref(prob.c())
     assert L.tmqcd_tune_set(p, 0, 0, 4, 1, 128, 1, 0) == T.EINVAL      # no class 4
     assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 192, 1, 0) == T.EINVAL      # block size
-    assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 128, 4, 0) == T.EINVAL      # order
+    assert L.tmqcd_tune_set(p, 0, 0, 0, 1, 128, 6, 0) == T.EINVAL      # order
     assert L.tmqcd_tune_set(p, 5, 0, 0, 1, 128, 1, 0) == T.EINVAL      # precision
     assert L.tmqcd_tune_set(p, 0, 0, 0, 2, 128, 1, 0) == T.EINVAL      # single-RHS class with nrhs 2
     assert L.tmqcd_tune_set(p, 0, 0, 3, 1, 256, 1, 0) == T.EINVAL      # multi-RHS class with nrhs 1

@@ -1,0 +1,139 @@
+"""Several right-hand sides in one CG solve (tmqcd_cg with opts.nrhs > 1) and the force call that
+forms Y = M X itself, through the C interface, against the oracle.
+
+* the 12 spin-colour point sources at 24^3 x 48 (kappa 0.155, mu 0.01, the links of the 24^3 x 48
+  configuration): every column's true residual, recomputed by the C++ FP64 oracle, <= 1e-10;
+* small and ragged lattices (twisted phases): each column equals the single-RHS solve of the same
+  system (1e-12) and the oracle finds its residual <= 1e-10, on M^+M and Mhat^+Mhat;
+* a b = 0 column, a NaN column (its breakdown leaves the others solved), a non-zero start, the
+  iteration cap;
+* tmqcd_force with Y = NULL equals the call with Y = M X given, and the oracle's force.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import BC_AP, BC_TWIST, Fields, dev, host, rel
+from oracle import cref
+from oracle import dirac as D
+from oracle import force as F
+from paper_1209_5942_amd import synth
+from paper_1209_5942_amd import tmqcd as T
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve_cols(f, bs, op, **kw):
+    subset = T.FULL if op == T.MDAGM else T.EVEN
+    n = len(bs)
+    bp = T.pack_spinor(f.prob, dev(np.stack(bs)), T.F64, subset, nrhs=n)
+    recon = kw.pop("recon", T.RECON18)
+    x, st, rc = T.cg(f.prob, {T.F64: f.gauge(T.F64, recon)}, bp, op=op, nrhs=n, recon=recon, **kw)
+    return host(T.unpack_spinor(f.prob, x, T.F64, subset, n)), st, rc
+
+
+@pytest.mark.timeout(600)
+def test_twelve_point_sources_24x24x24x48():
+    dims, kappa, mu = (24, 24, 24, 48), 0.155, 0.01
+    f = Fields(dims, 0.5, 24, kappa, mu, BC_AP)
+    vh = f.prob.volume // 2
+    b = synth.point_sources(vh, 0)
+    print(f"\n12-RHS CG 24^3x48 point sources", flush=True)
+    xs, st, rc = _solve_cols(f, list(b), T.MHATDAGMHAT, tol=1e-10, check_every=16)
+    assert rc == T.OK
+    U = f.U.reshape(-1, 4, 3, 3)
+    for k in range(12):
+        assert st[k]["converged"] == 1
+        res = cref.true_rel_residual("MHATDAGMHAT", U, b[k], xs[k], dims, kappa, mu, BC_AP)
+        print(f"column {k}: {st[k]['iters']} iters, oracle residual {res:.2e}", flush=True)
+        assert res <= 1e-10, (k, res)
+
+
+@pytest.mark.parametrize("dims,bc,op", [((4, 4, 4, 4), BC_AP, T.MHATDAGMHAT), ((4, 4, 4, 4), BC_AP, T.MDAGM),
+                                        ((12, 6, 4, 10), BC_TWIST, T.MHATDAGMHAT), ((6, 4, 2, 8), BC_TWIST, T.MDAGM),
+                                        ((2, 2, 2, 2), BC_TWIST, T.MHATDAGMHAT)])
+@pytest.mark.parametrize("n", [2, 5, 12])
+def test_columns_equal_single_solves(dims, bc, op, n):
+    f = Fields(dims, 0.5, 3100 + n, 0.16, 0.005, bc)
+    subset = T.FULL if op == T.MDAGM else T.EVEN
+    m = f.prob.volume // (1 if subset == T.FULL else 2)
+    bs = [synth.gaussian_spinor(m, 3200 + k) for k in range(n)]
+    xs, st, rc = _solve_cols(f, bs, op, tol=1e-10, check_every=8)
+    assert rc == T.OK
+    A = (lambda v: D.apply_MdagM(f.U, v, dims, f.kappa, f.mu, bc)) if op == T.MDAGM else \
+        (lambda v: D.apply_MhatdagMhat(f.U, v, dims, f.kappa, f.mu, bc))
+    for k in range(n):
+        x1, s1, _ = T.cg(f.prob, {T.F64: f.gauge(T.F64, 0)}, T.pack_spinor(f.prob, dev(bs[k]), T.F64, subset),
+                         op=op, tol=1e-10, check_every=8)
+        x1 = host(T.unpack_spinor(f.prob, x1, T.F64, subset))
+        assert D.true_rel_residual(A, bs[k], xs[k]) <= 1e-10
+        # the same iterations up to the rounding of the reductions (summed per wavefront here, per
+        # block there): the same count, or one more where a residual falls within rounding of the bound
+        assert st[k]["converged"] == 1 and abs(st[k]["iters"] - s1["iters"]) <= 1
+        assert rel(xs[k], x1) < 1e-8
+
+
+def test_zero_and_nan_columns_and_a_start_vector():
+    dims, bc = (4, 4, 2, 6), BC_TWIST
+    f = Fields(dims, 0.5, 3301, 0.16, 0.005, bc)
+    m = f.prob.volume // 2
+    bs = [synth.gaussian_spinor(m, 3302), np.zeros((m, 4, 3), complex), synth.gaussian_spinor(m, 3303)]
+    bad = synth.gaussian_spinor(m, 3304)
+    bad[3, 1, 2] = np.nan
+    bs.insert(2, bad)
+    xs, st, rc = _solve_cols(f, bs, T.MHATDAGMHAT, tol=1e-10, check_every=4, raise_on_breakdown=False)
+    assert rc == T.EBREAKDOWN
+    A = lambda v: D.apply_MhatdagMhat(f.U, v, dims, f.kappa, f.mu, bc)
+    assert st[1]["converged"] == 1 and not np.any(xs[1])
+    assert st[2]["converged"] == 0
+    for k in (0, 3):
+        assert st[k]["converged"] == 1 and D.true_rel_residual(A, bs[k], xs[k]) <= 1e-10
+    # a start vector: the solution itself needs no iteration; a perturbed one converges
+    good = [bs[0], bs[3]]
+    bp = T.pack_spinor(f.prob, dev(np.stack(good)), T.F64, T.EVEN, nrhs=2)
+    x0 = T.pack_spinor(f.prob, dev(np.stack([xs[0], 0.9 * xs[3]])), T.F64, T.EVEN, nrhs=2)
+    x, st2, rc = T.cg(f.prob, {T.F64: f.gauge(T.F64, 0)}, bp, x0, x_is_zero=False, op=T.MHATDAGMHAT, nrhs=2,
+                      tol=1e-10)
+    assert rc == T.OK and st2[0]["iters"] == 0 and st2[1]["iters"] > 0
+    xh = host(T.unpack_spinor(f.prob, x, T.F64, T.EVEN, 2))
+    for k, bk in enumerate(good):
+        assert D.true_rel_residual(A, bk, xh[k]) <= 1e-10
+    # the iteration cap
+    _, st3, rc = _solve_cols(f, good, T.MHATDAGMHAT, tol=1e-14, max_iter=3, raise_on_noconv=False)
+    assert rc == T.ENOCONV and all(s["iters"] == 3 and s["converged"] == 0 for s in st3)
+
+
+@pytest.mark.parametrize("recon", [T.RECON18, T.RECON12, T.RECON8])
+def test_multi_rhs_cg_with_compressed_links(recon):
+    dims, bc = (8, 4, 4, 8), BC_AP
+    f = Fields(dims, 0.4, 3401, 0.16, 0.01, bc)
+    m = f.prob.volume // 2
+    bs = [synth.gaussian_spinor(m, 3402 + k) for k in range(4)]
+    xs, st, rc = _solve_cols(f, bs, T.MHATDAGMHAT, tol=1e-10, recon=recon)
+    assert rc == T.OK
+    from oracle import compress as OC
+    Ur = {T.RECON18: f.U, T.RECON12: OC.rec12_decode(f.U[..., :2, :]),
+          T.RECON8: OC.rec8_decode(OC.rec8_encode(f.U))}[recon]
+    A = lambda v: D.apply_MhatdagMhat(Ur, v, dims, f.kappa, f.mu, bc)
+    for k in range(4):
+        # the system on the links the solver used (the oracle's own reconstruction)
+        assert D.true_rel_residual(A, bs[k], xs[k]) <= 1.02e-10
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), BC_AP), ((6, 4, 2, 8), BC_TWIST)])
+@pytest.mark.parametrize("recon", [T.RECON18, T.RECON12])
+def test_force_forms_y_itself(dims, bc, recon):
+    f = Fields(dims, 0.5, 3501, 0.155, 0.01, bc)
+    x = synth.gaussian_spinor(f.prob.volume, 3502)
+    g = f.gauge(T.F64, recon)
+    Xp = T.pack_spinor(f.prob, dev(x))
+    Yp = T.dslash(f.prob, g, Xp, T.M, recon=recon)
+    given = T.force(f.prob, g, Xp, Yp, recon=recon)
+    formed = T.force(f.prob, g, Xp, None, recon=recon)
+    assert torch.equal(given, formed)
+    want = F.fermion_force(f.U, x, D.apply_M(f.U, x, dims, f.kappa, f.mu, bc), dims, f.kappa, bc)
+    assert rel(host(formed), want) < 1e-12
+    # accumulate with scale into an existing momentum field
+    p = torch.ones_like(formed)
+    T.force(f.prob, g, Xp, None, recon=recon, out=p, scale=-0.25, accumulate=True)
+    assert rel(host(p), 1.0 - 0.25 * want) < 1e-12

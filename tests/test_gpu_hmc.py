@@ -217,3 +217,30 @@ def test_fermion_action_backward_keeps_its_own_links_and_solution(eo):
             X, _ = D.cg(lambda x: D.apply_MdagM(U, x, dims, kappa, mu, BC_AP), phi, 1e-14)
             want = F.fermion_force(U, X, D.apply_M(U, X, dims, kappa, mu, BC_AP), dims, kappa, BC_AP)
         assert rel(host(om.grad), want) < 1e-10
+
+
+@pytest.mark.parametrize("subset,beta,c1", [(T.FULL, 0.0, 0.0), (T.FULL, 5.5, 0.0), (T.EVEN, 3.9, -1.0 / 12.0)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8)])
+def test_delta_h_summed_site_by_site_matches_oracle(subset, beta, c1, dims):
+    """tmqcd_delta_h between two unrelated states (links, momenta, solutions) against the oracle's
+    parts: 1/2 sum (p1^2 - p0^2), the gauge actions' difference (plaquettes and rectangles) and
+    Re phi^+ (X1 - X0)."""
+    from oracle import symanzik as S
+    prob = T.Problem(dims, 0.15, 0.01, BC_AP)
+    v = prob.volume
+    U0 = synth.random_links(dims, 0.4, 261)
+    U1 = synth.random_links(dims, 0.4, 262)
+    p0, p1 = synth.gaussian_momenta(v, 263), synth.gaussian_momenta(v, 264)
+    n = v if subset == T.FULL else v // 2
+    phi, x0, x1 = (synth.gaussian_spinor(n, 265 + k) for k in range(3))
+    pk = lambda a: T.pack_spinor(prob, dev(a), T.F64, subset)
+    d = host(T.delta_h(prob, T.pack_gauge(prob, dev(U0)), T.pack_gauge(prob, dev(U1)), dev(p0), dev(p1), pk(phi),
+                       pk(x0), pk(x1), subset, beta, c1))
+    kin = 0.5 * (np.sum(p1 ** 2) - np.sum(p0 ** 2))
+    gauge = 0.0
+    if beta != 0.0:
+        gauge = beta / 3.0 * ((1 - 8 * c1) * (S.plaquette_sum(U0, dims) - S.plaquette_sum(U1, dims))
+                              + c1 * (S.rectangle_sum(U0, dims) - S.rectangle_sum(U1, dims)))
+    ferm = float(np.vdot(phi, x1 - x0).real)
+    for got, want in ((d[1], kin), (d[2], gauge), (d[3], ferm), (d[0], kin + gauge + ferm)):
+        assert abs(got - want) <= 1e-12 * max(1.0, abs(kin) + abs(gauge) + abs(ferm)), (got, want)

@@ -25,8 +25,8 @@ def test_tune_admits_bitwise_equal_shapes_and_keeps_results(tmp_path, prec, reco
     res = T.tune(f.prob, g, prec, recon)
     assert [r["kernel_class"] for r in res] == [0, 1, 2]
     for r in res:
-        assert r["candidates"] == 8 and r["rejected"] == 0
-        assert r["block"] in (128, 256) and r["order"] in (0, 1, 2, 3) and 0 < r["us"] <= r["default_us"] * 1.0001
+        assert r["candidates"] == 12 and r["rejected"] == 0
+        assert r["block"] in (128, 256) and r["order"] in range(6) and 0 < r["us"] <= r["default_us"] * 1.0001
     after = host(T.unpack_spinor(f.prob, T.dslash(f.prob, g, inp, T.MHATDAGMHAT, prec, recon), prec, T.EVEN))
     assert np.array_equal(before, after)
     path = tmp_path / "tune.jsonl"
@@ -55,7 +55,7 @@ def test_tuned_cg_matches_untuned():
     assert np.linalg.norm(a1 - a0) <= 1e-12 * np.linalg.norm(a0)
 
 
-SHAPES = [(b, o) for b in (128, 256) for o in (0, 1, 2, 3)]
+SHAPES = [(b, o) for b in (128, 256) for o in range(6)]
 
 
 @pytest.mark.parametrize("block,order", SHAPES)
@@ -89,7 +89,7 @@ def test_pinned_shapes_match_oracle(block, order, dims, bc):
         T.tune_clear()
 
 
-@pytest.mark.parametrize("order,group", [(0, 0), (1, 0), (2, 0), (3, 0), (2, 5), (3, 4)])
+@pytest.mark.parametrize("order,group", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (2, 5), (3, 4), (4, 5)])
 @pytest.mark.parametrize("dims,bc", [((12, 6, 4, 10), BC_TWIST), ((4, 4, 8, 8), BC_AP)])
 def test_pinned_multi_rhs_orders_match_oracle(order, group, dims, bc):
     """The multi-RHS kernel in every block order and with rhs groups (5 per block: 5 + 5 + 2): 12 Gaussian
@@ -125,8 +125,8 @@ def test_tune_mrhs_admits_equal_orders_and_keeps_results():
         before = host(T.unpack_spinor(f.prob, T.dslash(f.prob, g, inp, T.MHATDAGMHAT, nrhs=12), T.F64, T.EVEN,
                                       nrhs=12))
         r = T.tune_mrhs(f.prob, g, 12)
-        assert r["kernel_class"] == 3 and r["candidates"] == 12 and r["rejected"] == 0
-        assert r["block"] == 256 and r["order"] in (0, 1, 2, 3) and r["group"] in (0, 6, 4)
+        assert r["kernel_class"] == 3 and r["candidates"] == 18 and r["rejected"] == 0
+        assert r["block"] == 256 and r["order"] in range(6) and r["group"] in (0, 6, 4)
         assert 0 < r["us"] <= r["default_us"] * 1.0001
         after = host(T.unpack_spinor(f.prob, T.dslash(f.prob, g, inp, T.MHATDAGMHAT, nrhs=12), T.F64, T.EVEN,
                                      nrhs=12))
