@@ -102,9 +102,12 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle residual check and CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 32^3 x 64 FP64-vs-mixed comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-RHS, batch and HMC measurements")
-    ap.add_argument("--kernel-only", nargs="?", const="hop", choices=("hop", "mrhs"),
-                    help="only a 1 GiB copy (counter calibration), the tuner and 10 launches of one kernel at 24^3x48: "
-                         "the FP64 hop (default) or the 12-RHS hop in FP64 and FP32, for rocprofv3 --pmc")
+    ap.add_argument("--kernel-only", nargs="?", const="hop",
+                    choices=("hop", "mrhs", "force24", "force32", "heatbath24", "tlsym16"),
+                    help="only a 1 GiB copy (counter calibration) and 10 launches of one kernel, for rocprofv3 --pmc: "
+                         "the tuned FP64 hop (default) or the tuned 12-RHS hop in FP64 and FP32 at 24^3x48, the "
+                         "FP64 fermion force at 24^3x48 or 32^3x64, 10 FP64 heatbath sweeps at 24^3x48 (8 launches "
+                         "each), or 10 tree-level Symanzik gauge forces at 16^3x32 (2 launches each)")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
                     help="write the hop's measured HBM traffic from two --pmc runs of --kernel-only, then exit")
     ap.add_argument("--durations-from", nargs=3, metavar=("KERNEL_TRACE_CSV", "NAME_SUBSTRING", "LAST_N"),
@@ -121,6 +124,9 @@ def main():
         return
     if args.counters_from:
         counters_from(*args.counters_from)
+        return
+    if args.kernel_only in ("force24", "force32", "heatbath24", "tlsym16") and args.gpus == 1:
+        kernel_only_force(args.kernel_only)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and the library has no "
@@ -543,6 +549,52 @@ def kernel_only_mrhs(T, prob, gauges, dev):
     print(json.dumps(info), flush=True)
 
 
+def kernel_only_force(which):
+    """Calibration copy (1 GiB), then 10 FP64 fermion-force launches (RECON18) at 24^3x48 or 32^3x64 on
+    random fields (values do not change the kernel's memory traffic); or 10 FP64 heatbath sweeps at 24^3x48
+    (SU(3) links, beta 5.7); or 10 tree-level Symanzik forces (c1 = -1/12) at 16^3x32."""
+    import torch
+
+    from paper_1209_5942_amd import synth
+    from paper_1209_5942_amd import tmqcd as T
+    dev = torch.device("cuda:0")
+    a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    del a, c
+    if which in ("heatbath24", "tlsym16"):
+        dims = (24, 24, 24, 48) if which == "heatbath24" else (16, 16, 16, 32)
+        prob = T.Problem(dims, 0.15, 0.0, (1, 1, 1, -1))
+        g = T.pack_gauge(prob, torch.from_numpy(synth.random_links(dims, 0.4, 91)).to(dev))
+        if which == "heatbath24":
+            for k in range(10):
+                T.heatbath(prob, g, 5.7, 92, k)
+            info = {"sweeps": 10, "launches_per_sweep": 8, "sweep_algorithmic_bytes": 5184 * prob.volume}
+        else:
+            ws = T._bytes(T.gauge_force_tlsym_workspace_bytes(prob), dev)
+            G = torch.empty((prob.volume, 4, 8), dtype=torch.float64, device=dev)
+            for _ in range(10):
+                T.gauge_force_tlsym(prob, g, 3.9, -1.0 / 12.0, out=G, ws=ws)
+            info = {"forces": 10, "staple_field_bytes": 3456 * prob.volume}
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "dims": list(dims), **info}), flush=True)
+        return
+    dims = (24, 24, 24, 48) if which == "force24" else (32, 32, 32, 64)
+    prob = T.Problem(dims, 0.155, 0.01, (1, 1, 1, -1))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    g = T.pack_gauge(prob, torch.randn((prob.volume, 4, 3, 3), dtype=torch.complex128, device=dev, generator=gen))
+    X = T.pack_spinor(prob, torch.randn((prob.volume, 4, 3), dtype=torch.complex128, device=dev, generator=gen))
+    Y = T.pack_spinor(prob, torch.randn((prob.volume, 4, 3), dtype=torch.complex128, device=dev, generator=gen))
+    G = torch.empty((prob.volume, 4, 8), dtype=torch.float64, device=dev)
+    for _ in range(10):
+        T.force(prob, g, X, Y, out=G)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 1 << 30, "launches": 10, "dims": list(dims),
+                      "force_algorithmic_bytes": prob.volume * 1216}), flush=True)
+
+
 def traffic_from_counters(fetch_csv, write_csv, kernel_log):
     """Write the per-launch HBM traffic of the FP64 hop from two rocprofv3 --pmc runs of --kernel-only.
 
@@ -956,15 +1008,19 @@ def bench_hmc(T, synth, dev):
     Xe = T.pack_spinor(prob, torch.from_numpy(synth.gaussian_spinor(prob.volume // 2, 83)).to(dev), T.F64, T.EVEN)
     ws_eo = T._bytes(T.force_eo_workspace_bytes(prob), dev)
     t_force_eo = _events_time(lambda: T.force_eo(prob, h.U, Xe, out=G, ws=ws_eo), 20)
-    # gauge forces: Wilson plaquettes and the tree-level Symanzik action (c1 = -1/12); flops counted as
-    # 198 per 3x3 complex product (27 complex multiply-adds) over the products that walking one link's
-    # loops takes (the kernel needs fewer: it builds rectangle staples from stored plaquette staples)
+    # gauge forces: Wilson plaquettes and the tree-level Symanzik action (c1 = -1/12).  Two flop counts:
+    # the paper's Table 2 per site and direction (plaquette force 2717, rectangle force 14813), and the
+    # products these kernels execute at 198 flops per 3x3 complex product: Wilson 13 per link (6
+    # staples of 2 products, U V); Symanzik 2 per stored staple (24 per site) plus, per link, 12
+    # plaquette-staple additions, 18 rectangle staples of 2 products and U V (37 products)
     t_gauge_w = _events_time(lambda: T.gauge_force(prob, h.U, 3.9, out=G), 20)
     ws_sym = T._bytes(T.gauge_force_tlsym_workspace_bytes(prob), dev)
     t_gauge_s = _events_time(lambda: T.gauge_force_tlsym(prob, h.U, 3.9, -1.0 / 12.0, out=G, ws=ws_sym), 20)
     del ws_sym
-    flops_w = 4 * prob.volume * 198 * (6 * 2 + 1)
-    flops_s = 4 * prob.volume * 198 * (6 * 2 + 18 * 4 + 1)
+    paper_w = 4 * prob.volume * 2717
+    paper_s = 4 * prob.volume * (2717 + 14813)
+    exec_w = 4 * prob.volume * 198 * 13
+    exec_s = prob.volume * 198 * (24 * 2 + 4 * 37)
 
     def run(hmc, n_steps, integrator="leapfrog", n_inner=1):
         dh, acc = [], 0
@@ -1022,10 +1078,14 @@ def bench_hmc(T, synth, dev):
             "creutz_4x4x4x4": creutz,
             "force_eo_us": round(t_force_eo * 1e6, 1),
             "gauge_force_wilson_us": round(t_gauge_w * 1e6, 1),
-            "gauge_force_wilson_TFLOP_s": round(flops_w / t_gauge_w / 1e12, 2),
+            "gauge_force_wilson_TFLOP_s_paper_count": round(paper_w / t_gauge_w / 1e12, 2),
+            "gauge_force_wilson_TFLOP_s_executed": round(exec_w / t_gauge_w / 1e12, 2),
             "gauge_force_tlsym_us": round(t_gauge_s * 1e6, 1),
-            "gauge_force_tlsym_TFLOP_s": round(flops_s / t_gauge_s / 1e12, 2),
-            "gauge_force_tlsym_frac_of_fp64_peak": round(flops_s / t_gauge_s / 78.6e12, 4),
+            "gauge_force_tlsym_TFLOP_s_paper_count": round(paper_s / t_gauge_s / 1e12, 2),
+            "gauge_force_tlsym_TFLOP_s_executed": round(exec_s / t_gauge_s / 1e12, 2),
+            "gauge_force_tlsym_executed_frac_of_fp64_peak": round(exec_s / t_gauge_s / 78.6e12, 4),
+            "gauge_force_flop_counts": "paper: Table 2 per site and direction (2717 plaquette, 14813 rectangles); "
+                                       "executed: 198 flops per 3x3 complex product the kernels perform",
             "eo_2mn_tlsym_beta3.9": {"trajectory_s": round(t_prod, 3), "acceptance": acc_prod,
                                      "mean_abs_dH": round(float(np.mean(np.abs(dh_prod))), 4),
                                      "cg_iters_per_solve": round(hprod.cg_iters / max(1, hprod.solves), 1),

@@ -137,3 +137,14 @@ def test_force_forms_y_itself(dims, bc, recon):
     p = torch.ones_like(formed)
     T.force(f.prob, g, Xp, None, recon=recon, out=p, scale=-0.25, accumulate=True)
     assert rel(host(p), 1.0 - 0.25 * want) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(24, 24, 24, 4), (32, 32, 32, 2), (16, 8, 16, 4)])
+def test_force_on_wide_slices(dims):
+    """Lattices whose t-slices are wide and short in t (one block range per XCD spans several
+    z-planes); every link's gradient against the oracle."""
+    f = Fields(dims, 0.5, 3601, 0.155, 0.01, BC_TWIST)
+    x = synth.gaussian_spinor(f.prob.volume, 3602)
+    y = synth.gaussian_spinor(f.prob.volume, 3603)
+    got = host(T.force(f.prob, f.gauge(T.F64, T.RECON18), T.pack_spinor(f.prob, dev(x)), T.pack_spinor(f.prob, dev(y))))
+    assert rel(got, F.fermion_force(f.U, x, y, dims, f.kappa, f.bc)) < 1e-12
