@@ -82,8 +82,9 @@ def hop_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(vh: int):
-    """HBM bytes per hop launch measured with rocprofv3 counters, if taken on the current kernel source."""
+def traffic_from_profile(vh: int, block: int, order: int):
+    """HBM bytes per hop launch in the given launch shape, measured with rocprofv3 counters, if taken on
+    the current kernel source."""
     path = os.path.join(ROOT, "profiles", "hop_f64_24x24x24x48_traffic.json")
     if not os.path.exists(path):
         return None
@@ -91,7 +92,7 @@ def traffic_from_profile(vh: int):
         rec = json.load(fh)
     if rec.get("source_sha") != hop_source_hash() or rec.get("vh") != vh:
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("shapes", {}).get(f"{block}/{order}", {}).get("bytes_per_launch")
 
 
 def main():
@@ -233,7 +234,7 @@ def main():
     copy_gbs = 2 * a.numel() / _events_time(lambda: c.copy_(a), 5) / 1e9
     del a, c
 
-    traffic = traffic_from_profile(vh)
+    traffic = traffic_from_profile(vh, tuning["class0"]["block"], tuning["class0"]["order"])
     cg_gbs = st0["iters"] * vh * CG_ITER_BYTES_PER_SITE / (elapsed / args.steps) / 1e9
     result = {
         "metric": "Dslash GB/s (% HBM peak); CG time to 1e-10 residual, FP64 vs mixed",
@@ -262,7 +263,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs_hop, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(gbs_hop / PEAK_HBM_GBPS, 4), "traffic": traffic,
                      "kernel": f"hop_kernel<F64,RECON18,dag=0,own=0,store> block {tuning['class0']['block']} "
-                               "(DSLASH_OE / first Schur hop)",
+                               f"order {tuning['class0']['order']} (DSLASH_OE / first Schur hop)",
                      "bytes_per_launch": vh * BYTES_PER_SITE[(0, 0)], "us_per_launch": round(t_hop * 1e6, 2),
                      "gflops": round(gflops_hop, 1), "measured_read_peak_GB_s": round(read_gbs, 1),
                      "measured_copy_peak_GB_s": round(max(copy_gbs, probe_copy_gbs), 1),
@@ -508,7 +509,8 @@ def bench_mixed(T, synth, dev, check):
 
 
 def kernel_only(T, prob, gauges, b, dev):
-    """Calibration copy of known size, then the FP64 hop kernel in its tuned launch shape; for counter runs."""
+    """Calibration copy of known size, then the tuner and 10 FP64 hops in each of the 12 launch shapes
+    (block size x block order, pinned one after the other); for counter runs."""
     import torch
     a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
     c = torch.empty_like(a)
@@ -517,10 +519,14 @@ def kernel_only(T, prob, gauges, b, dev):
     tuned = T.tune(prob, gauges[(0, 0)], T.F64, T.RECON18)[0]
     src = T.pack_spinor(prob, torch.from_numpy(b).to(dev), T.F64, T.EVEN)
     out = torch.empty(T.spinor_bytes(prob, T.F64, T.ODD), dtype=torch.uint8, device=dev)
-    for _ in range(10):
-        T.dslash(prob, gauges[(0, 0)], src, T.DSLASH_OE, out=out)
+    shapes = [(block, order) for block in (128, 256) for order in range(6)]
+    for block, order in shapes:
+        T.tune_set(prob, T.F64, T.RECON18, 0, block, order)
+        for _ in range(10):
+            T.dslash(prob, gauges[(0, 0)], src, T.DSLASH_OE, out=out)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": a.numel(), "hop_launches": 10, "hop_block": tuned["block"],
+    T.tune_clear()
+    print(json.dumps({"copy_bytes": a.numel(), "hop_launches": 10, "shapes": shapes, "hop_block": tuned["block"],
                       "hop_order": tuned["order"], "hop_algorithmic_bytes": prob.volume // 2 * 1536,
                       "hop_source_sha": hop_source_hash()}), flush=True)
 
@@ -596,10 +602,12 @@ def kernel_only_force(which):
 
 
 def traffic_from_counters(fetch_csv, write_csv, kernel_log):
-    """Write the per-launch HBM traffic of the FP64 hop from two rocprofv3 --pmc runs of --kernel-only.
+    """Write the per-launch HBM traffic of the FP64 hop in each launch shape from two rocprofv3 --pmc runs
+    of --kernel-only.
 
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
-    counters read for the calibration copy of known size in the same run.
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same counters read for the
+    calibration copy of known size in the same run; the last 12 x 10 hop dispatches are the 12 pinned
+    shapes in the order the run printed.
     """
     import csv
     with open(kernel_log) as fh:
@@ -613,22 +621,27 @@ def traffic_from_counters(fetch_csv, write_csv, kernel_log):
                     out.append(r)
         return sorted(out, key=lambda r: int(r["Dispatch_Id"]))
 
-    res = {}
+    n, shapes = info["hop_launches"], [tuple(x) for x in info["shapes"]]
+    per_shape = {f"{b}/{o}": {} for b, o in shapes}
+    factors = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rs = rows(path, counter)
         copy = [float(r["Counter_Value"]) for r in rs if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer")][:1]
-        hop = [float(r["Counter_Value"]) for r in rs
-               if "hop_kernel<0, 0, false, false, 0, 0," in r["Kernel_Name"]
-               and int(r["Workgroup_Size"]) == info["hop_block"]][-info["hop_launches"]:]
-        assert len(copy) == 1 and len(hop) == info["hop_launches"], (counter, len(copy), len(hop))
+        hop = [r for r in rs if "hop_kernel<0, 0, false, false, 0, 0," in r["Kernel_Name"]][-n * len(shapes):]
+        assert len(copy) == 1 and len(hop) == n * len(shapes), (counter, len(copy), len(hop))
         factor = info["copy_bytes"] / 1024.0 / copy[0]
-        res[counter] = {"copy_kib": copy[0], "factor": round(factor, 4), "hop_kib_mean": sum(hop) / len(hop),
-                        "hop_bytes": sum(hop) / len(hop) * 1024.0 * factor}
-    total = res["FETCH_SIZE"]["hop_bytes"] + res["WRITE_SIZE"]["hop_bytes"]
-    rec = {"source_sha": info["hop_source_sha"], "vh": info["hop_algorithmic_bytes"] // 1536,
-           "hop_block": info["hop_block"], "hop_order": info["hop_order"],
-           "bytes_per_launch": round(total), "algorithmic_bytes_per_launch": info["hop_algorithmic_bytes"],
-           "ratio_to_algorithmic": round(total / info["hop_algorithmic_bytes"], 4), "counters": res}
+        factors[counter] = {"copy_kib": copy[0], "factor": round(factor, 4)}
+        for i, (block, order) in enumerate(shapes):
+            grp = hop[i * n:(i + 1) * n]
+            assert all(int(r["Workgroup_Size"]) == block for r in grp), (counter, block, order)
+            kib = sum(float(r["Counter_Value"]) for r in grp) / n
+            per_shape[f"{block}/{order}"][counter] = round(kib * 1024.0 * factor)
+    alg = info["hop_algorithmic_bytes"]
+    for v in per_shape.values():
+        v["bytes_per_launch"] = v["FETCH_SIZE"] + v["WRITE_SIZE"]
+        v["ratio_to_algorithmic"] = round(v["bytes_per_launch"] / alg, 4)
+    rec = {"source_sha": info["hop_source_sha"], "vh": alg // 1536, "algorithmic_bytes_per_launch": alg,
+           "launches_per_shape": n, "calibration": factors, "shapes": per_shape}
     path = os.path.join(ROOT, "profiles", "hop_f64_24x24x24x48_traffic.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)

@@ -126,6 +126,11 @@ __global__ __launch_bounds__(kBlock) void xpay_fused_kernel(VecK v, char* p, int
     sum_partials<1>(partials, n, tot);
     const double beta_d = tot[0] / st->rr;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->beta_pending = 1;
+    // The pending finish will stop the recursion here (the stop tests of
+    // cg_finish_update, on the same total): p keeps the last search direction,
+    // from which a reliable update restarts, as when the finish precedes p.
+    const int it = st->iter + 1;
+    if (!isfinite(tot[0]) || tot[0] <= st->stop_rr || it >= st->cycle_end || it >= st->max_iter) return;
     int half, h;
     if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
     using T = typename Prec<PP>::T;

@@ -43,17 +43,52 @@ def test_traffic_reported_only_for_the_measured_source(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
     vh = 331_776
-    rec = {"source_sha": bench.hop_source_hash(), "vh": vh, "bytes_per_launch": 123}
+    rec = {"source_sha": bench.hop_source_hash(), "vh": vh,
+           "shapes": {"128/2": {"bytes_per_launch": 123}, "256/4": {"bytes_per_launch": 456}}}
     (prof / "hop_f64_24x24x24x48_traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     # the hash reads the sources under ROOT: point it back at the repository's
     sha = rec["source_sha"]
     monkeypatch.setattr(bench, "hop_source_hash", lambda: sha)
-    assert bench.traffic_from_profile(vh) == 123
-    assert bench.traffic_from_profile(vh + 1) is None            # another lattice
+    assert bench.traffic_from_profile(vh, 128, 2) == 123
+    assert bench.traffic_from_profile(vh, 256, 4) == 456          # the launch shape the bench tuned
+    assert bench.traffic_from_profile(vh, 128, 4) is None         # a shape without counters
+    assert bench.traffic_from_profile(vh + 1, 128, 2) is None     # another lattice
     rec["source_sha"] = "0" * 16
     (prof / "hop_f64_24x24x24x48_traffic.json").write_text(json.dumps(rec))
-    assert bench.traffic_from_profile(vh) is None                # another kernel source
+    assert bench.traffic_from_profile(vh, 128, 2) is None         # another kernel source
+
+
+def test_traffic_from_counters_groups_the_pinned_shapes(tmp_path, monkeypatch):
+    """The counter rows of the 12 x 10 pinned hop launches are attributed to their shapes in order."""
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    shapes = [[b, o] for b in (128, 256) for o in range(6)]
+    info = {"copy_bytes": 1 << 30, "hop_launches": 10, "shapes": shapes, "hop_block": 128, "hop_order": 2,
+            "hop_algorithmic_bytes": 331_776 * 1536, "hop_source_sha": "abc"}
+    log = tmp_path / "k.log"
+    log.write_text("rocprofv3 noise\n" + json.dumps(info) + "\n")
+    hop = "void tmqcd::(anonymous namespace)::hop_kernel<0, 0, false, false, 0, 0, {}>(tmqcd::stencil::HopK)"
+    for counter, copy_kib, per in (("FETCH_SIZE", 524288.0, 1.0), ("WRITE_SIZE", 1048576.0, 0.5)):
+        lines = ["Dispatch_Id,Kernel_Name,Workgroup_Size,Counter_Name,Counter_Value",
+                 f"1,__amd_rocclr_copyBuffer,256,{counter},{copy_kib}"]
+        d = 2
+        for k in range(7):   # tuner launches before the pinned ones are ignored
+            lines.append(f'{d},"{hop.format(128)}",128,{counter},9999')
+            d += 1
+        for i, (b, o) in enumerate(shapes):
+            for _ in range(10):
+                lines.append(f'{d},"{hop.format(b)}",{b},{counter},{(1000 + i) * per}')
+                d += 1
+        (tmp_path / f"{counter}.csv").write_text("\n".join(lines) + "\n")
+    bench.traffic_from_counters(str(tmp_path / "FETCH_SIZE.csv"), str(tmp_path / "WRITE_SIZE.csv"), str(log))
+    rec = json.loads((tmp_path / "profiles" / "hop_f64_24x24x24x48_traffic.json").read_text())
+    assert rec["calibration"]["FETCH_SIZE"]["factor"] == 2.0 and rec["calibration"]["WRITE_SIZE"]["factor"] == 1.0
+    for i, (b, o) in enumerate(shapes):
+        r = rec["shapes"][f"{b}/{o}"]
+        assert r["FETCH_SIZE"] == round((1000 + i) * 1024 * 2.0)
+        assert r["WRITE_SIZE"] == round((1000 + i) * 0.5 * 1024)
+        assert r["bytes_per_launch"] == r["FETCH_SIZE"] + r["WRITE_SIZE"]
 
 
 def test_hop_source_hash_is_stable():

@@ -60,6 +60,22 @@ def test_cg_mixed_reaches_fp64_residual(inner, recon):
     assert st["reliable_updates"] >= 2
 
 
+@pytest.mark.parametrize("inner", [T.F32, T.F16])
+def test_cg_mixed_iterations_track_fp64(inner):
+    """A reliable update restarts the recursion from the FP64 residual along the last search
+    direction, so the mixed solver needs about as many iterations as FP64 CG (8^3 x 16: 48 each
+    way).  Restarting along a direction that had already been advanced past the stop cost 8
+    (FP32-inner) and 13 (FP16-inner) extra iterations here."""
+    f = Fields((8, 8, 8, 16), 0.5, 111, 0.162, 0.003, BC_AP)
+    b = synth.gaussian_spinor(f.prob.volume // 2, 112)
+    _, s64, rc = _solve(f, T.MHATDAGMHAT, b, tol=1e-10)
+    assert rc == T.OK
+    x, sq, rc = _solve(f, T.MHATDAGMHAT, b, inner=inner, tol=1e-10)
+    assert rc == T.OK and sq["reliable_updates"] >= 3
+    assert sq["iters"] <= s64["iters"] + 2, (sq["iters"], s64["iters"])
+    assert D.true_rel_residual(_oracle_A(f, T.MHATDAGMHAT), b, x) <= 1e-10
+
+
 def test_cg_mixed_full_operator():
     f = Fields((4, 4, 4, 8), 0.4, 121, 0.155, 0.01, BC_TWIST)
     b = synth.gaussian_spinor(f.prob.volume, 122)
