@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle residual check and CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 32^3 x 64 FP64-vs-mixed comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-RHS, batch and HMC measurements")
+    ap.add_argument("--normal-exit", action="store_true",
+                    help="end through the interpreter's normal shutdown instead of leaving at once after the JSON "
+                         "line (needed under rocprofv3, which writes its results at exit)")
     ap.add_argument("--kernel-only", nargs="?", const="hop",
                     choices=("hop", "mrhs", "force24", "force32", "heatbath24", "tlsym16"),
                     help="only a 1 GiB copy (counter calibration) and 10 launches of one kernel, for rocprofv3 --pmc: "
@@ -111,6 +114,8 @@ def main():
                          "each), or 10 tree-level Symanzik gauge forces at 16^3x32 (2 launches each)")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
                     help="write the hop's measured HBM traffic from two --pmc runs of --kernel-only, then exit")
+    ap.add_argument("--mrhs-shapes-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL_ONLY_LOG"),
+                    help="print the FP64 12-RHS hop's counters in each pinned shape of --kernel-only mrhs, then exit")
     ap.add_argument("--durations-from", nargs=3, metavar=("KERNEL_TRACE_CSV", "NAME_SUBSTRING", "LAST_N"),
                     help="mean/min/max duration of the last N dispatches of a kernel in a rocprofv3 kernel trace")
     ap.add_argument("--counters-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "NAME_SUBSTRING", "LAST_N"),
@@ -122,6 +127,9 @@ def main():
         return
     if args.durations_from:
         durations_from_trace(*args.durations_from)
+        return
+    if args.mrhs_shapes_from:
+        mrhs_shapes_from_counters(*args.mrhs_shapes_from)
         return
     if args.counters_from:
         counters_from(*args.counters_from)
@@ -337,6 +345,8 @@ def main():
             result["bicgstab_24x24x24x48"][f"{name}_rel_error_vs_oracle_solution"] = e["rel_error_vs_oracle_solution"]
         result["cpu_baseline"] = cpu_baseline(T, synth, U64, b, ost, cg_seconds=elapsed / args.steps)
     print(json.dumps(result), flush=True)
+    if args.normal_exit:
+        return
     # leave at once: nothing below needs the interpreter's teardown (GPU buffers, thread pools)
     sys.stdout.flush()
     sys.stderr.flush()
@@ -552,6 +562,17 @@ def kernel_only_mrhs(T, prob, gauges, dev):
             T.dslash(prob, g, s, T.DSLASH_OE, p, 0, nrhs=12, out=o)
         torch.cuda.synchronize()
         info[name] = {"order": tuned["order"], "group": tuned["group"]}
+        if p == T.F64:
+            # then 3 launches in each pinned shape: block order x right-hand sides per sweep
+            shapes = [(order, group) for order in range(6) for group in (0, 6, 4)]
+            for order, group in shapes:
+                T.tune_set(prob, p, 0, 3, 256, order, nrhs=12, group=group)
+                for _ in range(3):
+                    T.dslash(prob, g, s, T.DSLASH_OE, p, 0, nrhs=12, out=o)
+            torch.cuda.synchronize()
+            T.tune_clear()
+            info["f64_shapes"] = shapes
+            info["f64_shape_launches"] = 3
     print(json.dumps(info), flush=True)
 
 
@@ -750,6 +771,32 @@ def counters_from(fetch_csv, write_csv, name, last_n):
         out[counter] = {"factor": round(factor, 4), "dispatches": len(v),
                         "bytes_mean": round(sum(v) / len(v) * 1024.0 * factor)}
     print(json.dumps(out))
+
+
+def mrhs_shapes_from_counters(fetch_csv, write_csv, kernel_log):
+    """FETCH_SIZE / WRITE_SIZE bytes of the FP64 12-RHS hop in each pinned shape of --kernel-only mrhs
+    (the calibration copy's factor applied), with the links' and spinors' share of the fetch."""
+    import csv
+    with open(kernel_log) as fh:
+        info = [json.loads(l) for l in fh if l.startswith("{")][-1]
+    shapes, n = [tuple(x) for x in info["f64_shapes"]], info["f64_shape_launches"]
+    links, spinors = 382.2e6, 12 * 63.7e6          # 24^3 x 48: FP64 RECON18 links, 12 half spinors
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        with open(path) as fh:
+            rs = sorted((r for r in csv.DictReader(fh) if r["Counter_Name"] == counter),
+                        key=lambda r: int(r["Dispatch_Id"]))
+        copy = [float(r["Counter_Value"]) for r in rs if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer")][0]
+        factor = (1 << 30) / 1024.0 / copy
+        v = [float(r["Counter_Value"]) * 1024.0 * factor for r in rs
+             if "hop_mrhs_kernel<0, 0, false, false, 0>" in r["Kernel_Name"]][-n * len(shapes):]
+        assert len(v) == n * len(shapes), (counter, len(v))
+        for i, (order, group) in enumerate(shapes):
+            out.setdefault(f"{order}/{group}", {})[counter] = round(sum(v[i * n:(i + 1) * n]) / n)
+    for key, r in out.items():
+        sweeps = 1 if key.endswith("/0") else 12 // int(key.split("/")[1])
+        r["spinor_fetch_ratio"] = round((r["FETCH_SIZE"] - sweeps * links) / spinors, 2)
+        print(json.dumps({"shape": key, **r}))
 
 
 def durations_from_trace(path, name, last_n):
@@ -1073,6 +1120,7 @@ def bench_hmc(T, synth, dev):
     hprod = HMC(prob, U, beta=3.9, tol=1e-12, md_tol=1e-10, eo=True, inner_prec=T.F32, guess=True, c1=-1.0 / 12.0)
     dh_prod, acc_prod, t_prod = run(hprod, 10, "2mn", n_inner=2)
     creutz = creutz_4x4x4x4(T, synth, dev)
+    chain = thermalised_chain(T, synth, dev, prob, U)
     e = np.exp(-np.clip(np.array(dh20), -700, 700))
     ratio = float(np.mean(np.abs(dh20)) / np.mean(np.abs(dh40)))
     return {"force_us": round(t_force * 1e6, 1), "force_GB_s": round(force_bytes / t_force / 1e9, 1),
@@ -1115,11 +1163,57 @@ def bench_hmc(T, synth, dev):
                        "dH_fp32_inner_guess_max_abs_diff": float(np.max(np.abs(np.array(dh_eo32g) - np.array(dh_eo)))),
                        "cg_iters_per_solve_fp32_inner_guess": round(heo32g.cg_iters / max(1, heo32g.solves), 1),
                        "creutz_4x4x4x4": creutz_4x4x4x4(T, synth, dev, eo=True)},
+            "thermalised_chain_eo_2mn_tlsym_beta3.9": chain,
             "leapfrog_mean_abs_dH": round(float(np.mean(np.abs(dh20))), 6),
             "setup": "two-flavour twisted-mass pseudofermion action (beta = 0), tau = 1 leapfrog with 20 steps "
                      "(and 40: second-order integrator, mean |dH| ratio near 4) from the eps 0.4 start, force solves "
                      "1e-10, acceptance solves 1e-12; eo_2mn: the even-odd action and the two-level 2MN "
                      "integrator with 10 outer steps (and 20), the same solver tolerances"}
+
+
+def thermalised_chain(T, synth, dev, prob, U, n_traj=24, burn_in=4):
+    """A Markov chain at 16^3x32 from a thermalised start: 40 heatbath + overrelaxation sweeps of the Wilson
+    action at beta 5.9 from the eps 0.4 links, then the production setting (even-odd action, tree-level
+    Symanzik gauge action beta 3.9, c1 = -1/12; 20 outer 2MN steps of 2 inner steps, tau 1; FP32-inner
+    solves from the previous solution).  <exp(-dH)> over the trajectories after the burn-in."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1209_5942_amd.hmc import HMC
+    g = T.pack_gauge(prob, U)
+    for sw in range(40):
+        T.heatbath(prob, g, 5.9, 7, sw)
+        T.overrelax(prob, g)
+    per_plaq = 6 * prob.volume * 3.0
+    plaq0 = float(T.plaquette(prob, g)[0]) / per_plaq
+    Uth = T.unpack_gauge(prob, g).contiguous()
+    del g
+    h = HMC(prob, Uth, beta=3.9, tol=1e-12, md_tol=1e-10, eo=True, inner_prec=T.F32, guess=True, c1=-1.0 / 12.0)
+    dh, acc = [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_traj):
+        p = torch.from_numpy(synth.gaussian_momenta(prob.volume, 5000 + k)).to(dev)
+        eta = torch.from_numpy(synth.gaussian_spinor(prob.volume // 2, 6000 + k)).to(dev)
+        u = float(np.random.default_rng(7000 + k).random())
+        out = h.trajectory(p, eta, u, 20, 1.0 / 20, integrator="2mn", n_inner=2)
+        dh.append(out["dH"])
+        acc += int(out["accepted"])
+    torch.cuda.synchronize()
+    t_traj = (time.perf_counter() - t0) / n_traj
+    e = np.exp(-np.array(dh[burn_in:]))
+    return {"trajectory_s": round(t_traj, 3), "trajectories": n_traj, "burn_in": burn_in,
+            "acceptance": round(acc / n_traj, 3), "dH": [round(x, 5) for x in dh],
+            "exp_minus_dH_mean": round(float(e.mean()), 4),
+            "exp_minus_dH_stderr": round(float(e.std(ddof=1) / math.sqrt(len(e))), 4),
+            "plaquette_start": round(plaq0, 5),
+            "plaquette_end": round(float(T.plaquette(prob, h.U)[0]) / per_plaq, 5),
+            "cg_iters_per_solve": round(h.cg_iters / max(1, h.solves), 1),
+            "setup": "40 heatbath + overrelaxation sweeps (Wilson beta 5.9) from the eps 0.4 links, then a chain "
+                     "of even-odd 2MN trajectories (tree-level Symanzik beta 3.9, c1 = -1/12, kappa 0.155, "
+                     "mu 0.01, 20 outer x 2 inner steps, tau 1, FP32-inner solves from the previous solution)"}
 
 
 if __name__ == "__main__":

@@ -88,3 +88,19 @@ def test_thread_count_does_not_change_the_operator():
     finally:
         R.set_threads(n0)
     assert np.array_equal(one, many)
+
+
+def test_mismatched_sizes_are_rejected_before_the_loops():
+    """The C++ loops trust the sizes they are given; the wrapper refuses fields of the wrong size."""
+    dims = (4, 4, 4, 4)
+    v = int(np.prod(dims))
+    U = synth.random_links(dims, 0.5, 41).reshape(v, 4, 3, 3)
+    full, half = synth.gaussian_spinor(v, 42), synth.gaussian_spinor(v // 2, 43)
+    with pytest.raises(ValueError):
+        R.apply("MHAT", U, full, dims, 0.16, 0.01, BC_AP)          # a full field for an even-odd operator
+    with pytest.raises(ValueError):
+        R.apply("M", U, half, dims, 0.16, 0.01, BC_AP)             # a half field for a full operator
+    with pytest.raises(ValueError):
+        R.apply("M", U[: v // 2], full, dims, 0.16, 0.01, BC_AP)   # links of another lattice
+    with pytest.raises(ValueError):
+        R.true_rel_residual("MHATDAGMHAT", U, half, full, dims, 0.16, 0.01, BC_AP)
