@@ -226,11 +226,17 @@ struct LinkIO64 {
         }
         if constexpr (R == TMQCD_RECON12) rebuild_third_row(u);
     }
+    // NT: nontemporal stores, for links the launch does not read back
+    template <bool NT = false>
     __device__ __forceinline__ static void store(char* base, int64_t gstride, int par, int mu, int64_t h,
                                                  const Su3<double>& u) {
         double2* p = reinterpret_cast<double2*>(base) + (int64_t)((par * 4 + mu) * kUnits) * gstride + h;
 #pragma unroll
-        for (int k = 0; k < kUnits; ++k) p[k * gstride] = make_double2(u.m[k / 3][k % 3].re, u.m[k / 3][k % 3].im);
+        for (int k = 0; k < kUnits; ++k) {
+            const double2 w = make_double2(u.m[k / 3][k % 3].re, u.m[k / 3][k % 3].im);
+            if constexpr (NT) st_stream(p + k * gstride, w);
+            else p[k * gstride] = w;
+        }
     }
 };
 template <>

@@ -164,7 +164,10 @@ __global__ __launch_bounds__(kBlock) void su3_update_kernel(LatK k, stencil::Hop
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) ud.m[i][j] = {(double)u.m[i][j].re, (double)u.m[i][j].im};
-    LinkIO<P, TMQCD_RECON18>::store(gauge, k.gstride, par, mu, h, ud);
+    // FP64: nontemporal (no thread of the launch reads a link of this direction and parity
+    // but its own; 1025 -> 1007 us per heatbath sweep at 24^3 x 48)
+    if constexpr (P == TMQCD_F64) LinkIO<P, TMQCD_RECON18>::template store<true>(gauge, k.gstride, par, mu, h, ud);
+    else LinkIO<P, TMQCD_RECON18>::store(gauge, k.gstride, par, mu, h, ud);
 }
 
 }  // namespace
