@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const Mr
         if constexpr (EPI == kEpiStore) {
             SpinorIO<P>::template store<true>(a.out + r * m.out_fstride + hoff, a.stride, h, acc);
         } else if constexpr (EPI == kEpiStoreNorm) {
-            SpinorIO<P>::store(a.out + r * m.out_fstride + hoff, a.stride, h, acc);   // read by the next stage
+            SpinorIO<P>::template store<true>(a.out + r * m.out_fstride + hoff, a.stride, h, acc);   // not read by this launch
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
