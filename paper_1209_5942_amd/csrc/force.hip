@@ -87,7 +87,9 @@ struct ForceK {
 // bitwise the same output; giving each XCD one contiguous eighth of the lattice
 // instead lost on 32^3 x 64, whose t-slice of X and Y no longer fits in L2.  So did
 // cutting each range along y into chunks walked through t one after the other
-// (32^3 x 64: 17 % less fetched from HBM, 15 % slower).
+// (32^3 x 64: 17 % less fetched from HBM, 15 % slower), and giving each XCD one of 4
+// (or 2) z-ranges of the slices of one of 2 (or 4) t-ranges (16^3 x 32: 2 % faster,
+// 24^3 x 48: the same, 32^3 x 64: 2.5 % slower).
 __device__ __forceinline__ bool force_block_site(const ForceK& a, int bid, int lane, int& par, int& h) {
     const int x = bid & (kNumXcd - 1), k = bid / kNumXcd;
     const int t = k / (2 * a.tq), rem = k - t * 2 * a.tq;
@@ -176,7 +178,9 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
 // each outer product to Q at once keeps the kernel within 168 registers (three
 // waves per SIMD; 242-256 registers and two waves when the four spinors were
 // held whole).  Holding all four directions per thread needed 260 registers,
-// one wave per SIMD, and ran 14 % slower.
+// one wave per SIMD, and ran 14 % slower; putting the two terms of Q on separate
+// waves (eight per block, four waves per SIMD with 36 registers spilled) ran 45 %
+// slower.
 template <int R>
 __global__ __launch_bounds__(kBlock, FORCE_WAVES) void force_dir_kernel(const ForceK a) {
     // the block's 64 output records (32 doubles each, +1 against bank conflicts) and their sites
