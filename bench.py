@@ -573,6 +573,7 @@ def kernel_only_mrhs(T, prob, gauges, dev):
             T.tune_clear()
             info["f64_shapes"] = shapes
             info["f64_shape_launches"] = 3
+            info["vh"] = prob.volume // 2
     print(json.dumps(info), flush=True)
 
 
@@ -780,7 +781,7 @@ def mrhs_shapes_from_counters(fetch_csv, write_csv, kernel_log):
     with open(kernel_log) as fh:
         info = [json.loads(l) for l in fh if l.startswith("{")][-1]
     shapes, n = [tuple(x) for x in info["f64_shapes"]], info["f64_shape_launches"]
-    links, spinors = 382.2e6, 12 * 63.7e6          # 24^3 x 48: FP64 RECON18 links, 12 half spinors
+    links, spinors = info["vh"] * 1152, 12 * info["vh"] * 192   # FP64 RECON18 links (8 per output site), 12 half spinors
     out = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         with open(path) as fh:
