@@ -376,7 +376,7 @@ def tune_clear():
 
 
 def tune_set(prob: Problem, prec, recon, kernel_class, block, order, nrhs=1, group=0):
-    """Pin the launch shape (block 128/256, order 0..3; class 3: multi-RHS with nrhs and group) for this problem."""
+    """Pin the launch shape (block 128/256, order 0..5; class 3: multi-RHS with nrhs and group) for this problem."""
     _check(lib().tmqcd_tune_set(ctypes.byref(prob.c()), prec, recon, kernel_class, nrhs, block, order, group),
            "tmqcd_tune_set")
 
