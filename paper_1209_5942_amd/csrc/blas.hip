@@ -113,30 +113,41 @@ __global__ __launch_bounds__(kBlock) void xpay_kernel(VecK v, char* p, int64_t p
     SpinorIO<PP>::store(p + half * pbytes, v.stride, h, pv);
 }
 
-// p = r + beta p inside the CG iteration: beta = rr_new / rr with rr_new the sum of
-// the update hop's partials, formed by every block in the same fixed order (so all
-// blocks use the same beta) while st->rr still holds the previous |r|^2; the state
-// itself is updated by the next launch that finishes the pending beta.
+// x += alpha p and p = r + beta p inside the CG iteration: beta = rr_new / rr with
+// rr_new the sum of the update hop's partials, formed by every block in the same fixed
+// order (so all blocks use the same beta) while st->rr still holds the previous |r|^2;
+// the state itself is updated by the next launch that finishes the pending beta.
+// x (precision PR, as r) is updated here from the p this launch reads anyway, not in
+// the update hop.
 template <int PP, int PR>
 __global__ __launch_bounds__(kBlock) void xpay_fused_kernel(VecK v, char* p, int64_t pbytes, const char* r,
-                                                            int64_t rbytes, CgState* st, const double* partials,
-                                                            int n) {
+                                                            int64_t rbytes, char* x, CgState* st,
+                                                            const double* partials, int n) {
     if (block_stopped(st)) return;
     double tot[1];
     sum_partials<1>(partials, n, tot);
     const double beta_d = tot[0] / st->rr;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->beta_pending = 1;
     // The pending finish will stop the recursion here (the stop tests of
-    // cg_finish_update, on the same total): p keeps the last search direction,
-    // from which a reliable update restarts, as when the finish precedes p.
+    // cg_finish_update, on the same total): x takes this iteration's step, and p keeps
+    // the last search direction, from which a reliable update restarts, as when the
+    // finish precedes p.
     const int it = st->iter + 1;
-    if (!isfinite(tot[0]) || tot[0] <= st->stop_rr || it >= st->cycle_end || it >= st->max_iter) return;
+    const bool stops = !isfinite(tot[0]) || tot[0] <= st->stop_rr || it >= st->cycle_end || it >= st->max_iter;
     int half, h;
     if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
     using T = typename Prec<PP>::T;
-    const T beta = (T)beta_d;
-    Spinor<T> pv, rv;
+    const T alpha = (T)st->alpha, beta = (T)beta_d;
+    Spinor<T> pv, xv;
     SpinorIO<PP>::load(pv, p + half * pbytes, v.stride, h);
+    SpinorIO<PR>::load(xv, x + half * rbytes, v.stride, h);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
+    SpinorIO<PR>::store(x + half * rbytes, v.stride, h, xv);
+    if (stops) return;
+    Spinor<T> rv;
     SpinorIO<PR>::load(rv, r + half * rbytes, v.stride, h);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -405,21 +416,22 @@ hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr,
     return hipGetLastError();
 }
 
-hipError_t launch_xpay_fused(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st,
+hipError_t launch_xpay_fused(const VecSpec& v, void* p, int pp, const void* r, int pr, void* x, CgState* st,
                              const double* partials, int n, hipStream_t s) {
     const VecK k = make_veck(v);
     char* pc = static_cast<char*>(p);
     const char* rc = static_cast<const char*>(r);
+    char* xc = static_cast<char*>(x);
     const int64_t pb = half_field_bytes(*v.g, pp), rb = half_field_bytes(*v.g, pr);
     if (pp == TMQCD_F64 && pr == TMQCD_F64)
         hipLaunchKernelGGL((xpay_fused_kernel<TMQCD_F64, TMQCD_F64>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb,
-                           rc, rb, st, partials, n);
+                           rc, rb, xc, st, partials, n);
     else if (pp == TMQCD_F32 && pr == TMQCD_F32)
         hipLaunchKernelGGL((xpay_fused_kernel<TMQCD_F32, TMQCD_F32>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb,
-                           rc, rb, st, partials, n);
+                           rc, rb, xc, st, partials, n);
     else if (pp == TMQCD_F16 && pr == TMQCD_F32)
         hipLaunchKernelGGL((xpay_fused_kernel<TMQCD_F16, TMQCD_F32>), dim3(k.nblocks), dim3(kBlock), 0, s, k, pc, pb,
-                           rc, rb, st, partials, n);
+                           rc, rb, xc, st, partials, n);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

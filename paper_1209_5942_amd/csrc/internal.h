@@ -128,7 +128,7 @@ hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr,
                        hipStream_t s);
 // p = r + beta p with beta = (sum of the n partials) / st->rr formed by every block in a fixed order
 // (the partials of the update hop's |r|^2); sets st->beta_pending; nothing once st->done
-hipError_t launch_xpay_fused(const VecSpec& v, void* p, int pp, const void* r, int pr, CgState* st,
+hipError_t launch_xpay_fused(const VecSpec& v, void* p, int pp, const void* r, int pr, void* x, CgState* st,
                              const double* partials, int n, hipStream_t s);
 // p = r + beta p for n <= 8 lattices (FP64 even fields), skipping lattices whose solve has stopped
 hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* const* r, CgState* const* st, int n,

@@ -14,11 +14,13 @@
 //   t2 = A p - kappa^2 H_eo t1                 and per-block sums of |t2|^2
 //   t3 = A(-mu)^{-1} H^+_oe t2                 its block 0 first finishes
 //                                               p^+ A p = |t2|^2 and alpha
-//   (A p) = A(-mu) t2 - kappa^2 H^+_eo t3      fused with x += alpha p,
-//                                               r -= alpha A p, per-block |r|^2
-//   p = r + beta p                             every block forms beta itself
+//   (A p) = A(-mu) t2 - kappa^2 H^+_eo t3      fused with r -= alpha A p and
+//                                               per-block |r|^2
+//   x += alpha p, p = r + beta p               every block forms beta itself
 //                                               from those partials (the same
-//                                               fixed order in every block)
+//                                               fixed order in every block);
+//                                               x here, not in the update hop,
+//                                               saves one read of p
 // and the host reads the state after a one-block finish of the last beta.
 // The reductions finish in a later launch: a last-block-done scheme would
 // need a device-wide release in every block, which on this chip writes back
@@ -340,8 +342,8 @@ hipError_t queue_iteration(const OpCtx& c, bool full, const Fields& f, CgState* 
         e = launch_hop(k1, c.s, &nb);
         if (e == hipSuccess) e = launch_cg_finish(st, partials_a, nb, kFinishAlpha, c.s);
         if (e == hipSuccess)
-            e = launch_hop(hp_full(c, f.t1, nullptr, true, kEpiCgUpdate, st, partials_b, f.x, f.r, f.p, kOne), c.s,
-                           &nb_update);
+            e = launch_hop(hp_full(c, f.t1, nullptr, true, kEpiCgUpdate, st, partials_b, nullptr, f.r, nullptr, kOne),
+                           c.s, &nb_update);
     } else {
         HopParams k1 = hp_schur_first(c, f.p, f.t1, false, kOne);
         HopParams k3 = hp_schur_first(c, f.t2, f.t3, true, kOne);
@@ -360,13 +362,13 @@ hipError_t queue_iteration(const OpCtx& c, bool full, const Fields& f, CgState* 
         k3.fin_kind = kFinishAlpha;
         if (e == hipSuccess) e = launch_hop(k3, c.s);
         if (e == hipSuccess)
-            e = launch_hop(hp_schur_second(c, f.t3, f.t2, nullptr, true, kEpiCgUpdate, st, partials_b, f.x, f.r, f.p,
-                                           kOne),
+            e = launch_hop(hp_schur_second(c, f.t3, f.t2, nullptr, true, kEpiCgUpdate, st, partials_b, nullptr, f.r,
+                                           nullptr, kOne),
                            c.s, &nb_update);
     }
     if (e != hipSuccess) return e;
-    // p = r + beta p with beta formed from the update's partials; the state's beta finish is pending
-    return launch_xpay_fused(vs, f.p, c.prec, f.r, pv, st, partials_b, nb_update, c.s);
+    // x += alpha p and p = r + beta p, beta formed from the update's partials; the state's beta finish is pending
+    return launch_xpay_fused(vs, f.p, c.prec, f.r, pv, f.x, st, partials_b, nb_update, c.s);
 }
 
 // The pending beta finish of the last iteration queued (before the host reads the state).

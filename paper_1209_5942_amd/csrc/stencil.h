@@ -294,21 +294,26 @@ __device__ __forceinline__ double hop_site(const HopK& a, int par, int h) {
                 for (int c = 0; c < 3; ++c) red += (double)norm2(acc.s[s][c]);
         }
     } else {
-        // x += alpha p, r -= alpha (A p)
+        // r -= alpha (A p), and x += alpha p unless x is null (the single-lattice CG
+        // updates x in its p = r + beta p launch, which reads p anyway)
         const T alpha = (T)a.st->alpha;
         const int64_t voff = two ? (int64_t)par * a.vhbytes : 0;
-        Spinor<T> pv, xv, rv;
-        SpinorIO<P>::load(pv, a.p + hoff, a.stride, h);
-        SpinorIO<PV>::load(xv, a.x + voff, a.stride, h);
+        Spinor<T> rv;
         SpinorIO<PV>::load(rv, a.r + voff, a.stride, h);
+        if (a.x != nullptr) {
+            Spinor<T> pv, xv;
+            SpinorIO<P>::load(pv, a.p + hoff, a.stride, h);
+            SpinorIO<PV>::load(xv, a.x + voff, a.stride, h);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
+            SpinorIO<PV>::store(a.x + voff, a.stride, h, xv);
+        }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
-                rv.s[s][c] = rv.s[s][c] - scale(alpha, acc.s[s][c]);
-            }
-        SpinorIO<PV>::store(a.x + voff, a.stride, h, xv);
+            for (int c = 0; c < 3; ++c) rv.s[s][c] = rv.s[s][c] - scale(alpha, acc.s[s][c]);
         SpinorIO<PV>::store(a.r + voff, a.stride, h, rv);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
