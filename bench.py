@@ -37,9 +37,9 @@ BYTES_PER_SITE = {(p, r): 8 * _LINK[p][r] + 2 * _SPINOR[p] for p in range(3) for
 FLOPS_PER_SITE = 1320           # Wilson hop, per output site
 # one FP64 iteration of CG on Mhat^dag Mhat per even site (algorithmic, REC18 links): the operator's four
 # hops -- two plain stores (1536 B each), the one that adds A p and sums |Mhat p|^2 (also reads p: 1728 B),
-# the one that adds A^dag t, updates x and r and sums |r|^2 (reads t and p, reads and writes x and r:
-# 2496 B) -- and p = r + beta p (576 B)
-CG_ITER_BYTES_PER_SITE = 1536 + 1728 + 1536 + 2496 + 576
+# the one that adds A^dag t, updates r and sums |r|^2 (reads t, reads and writes r: 1920 B) -- and
+# x += alpha p, p = r + beta p (reads p, r, x; writes p, x: 960 B)
+CG_ITER_BYTES_PER_SITE = 1536 + 1728 + 1536 + 1920 + 960
 WORKLOAD = dict(dims=(24, 24, 24, 48), eps=0.5, kappa=0.16, mu=0.005, seed=24, src_seed=26)
 MIXED = dict(dims=(32, 32, 32, 64), eps=0.5, kappa=0.162, mu=0.003, seed=32, src_seed=34)
 HOP_SOURCES = ("hop.hip", "stencil.h", "device.h", "layout.h")
