@@ -84,8 +84,9 @@ __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const Mr
 #define TMQCD_TERMS(MU)                                                                                     \
     {                                                                                                       \
         const C<T> ph = cvt<T>(a.bc[MU]);                                                                   \
-        hop_term_at<P, R, MU, true, DAG, false>(acc, in, a.stride, n.f[MU], lt, 64, 0, lane, n.cf[MU], ph);       \
-        hop_term_at<P, R, MU, false, DAG, false>(acc, in, a.stride, n.b[MU], lt, 64, 1, lane, n.cb[MU], conj(ph)); \
+        hop_term_at<P, R, MU, true, DAG, false, true>(acc, in, a.stride, n.f[MU], lt, 64, 0, lane, n.cf[MU], ph);  \
+        hop_term_at<P, R, MU, false, DAG, false, true>(acc, in, a.stride, n.b[MU], lt, 64, 1, lane, n.cb[MU],      \
+                                                       conj(ph));                                                  \
     }
         TMQCD_TERMS(0)
         TMQCD_TERMS(1)

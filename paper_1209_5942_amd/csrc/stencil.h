@@ -136,8 +136,12 @@ __device__ __forceinline__ bool block_site(const HopK& a, int b, int lane, int& 
 // One of the eight terms: FWD: b+ (1 -+ gamma_mu) U_mu(x) psi(x+mu);
 // backward: b- (1 +- gamma_mu) U_mu(x-mu)^+ psi(x-mu) (signs flip for H^+).
 // The link is read from `lbase` in the packed link layout with stride
-// `lstride` (global memory, or a block's link tile in LDS).
-template <int P, int R, int MU, bool FWD, bool DAG, bool STREAM, typename T>
+// `lstride` (global memory, or a block's link tile in LDS).  A hop across the
+// boundary (`cross`) takes the boundary phase.  BRANCHLESS selects the factor
+// (1 or the phase) and always multiplies: the term is then branch-free, and
+// the compiler can issue the next term's spinor loads before this term's
+// arithmetic instead of waiting for each term's loads in turn.
+template <int P, int R, int MU, bool FWD, bool DAG, bool STREAM, bool BRANCHLESS = false, typename T>
 __device__ __forceinline__ void hop_term_at(Spinor<T>& acc, const char* in, int64_t stride, int nh, const char* lbase,
                                             int64_t lstride, int lpar, int lh, bool cross, C<T> phase) {
     constexpr int EPS = FWD ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
@@ -149,7 +153,13 @@ __device__ __forceinline__ void hop_term_at(Spinor<T>& acc, const char* in, int6
     project_row<MU, EPS, 0>(hs, v);
     project_row<MU, EPS, 1>(hs, v);
     su3_mul<!FWD>(g, u, hs);
-    if (cross) {
+    if constexpr (BRANCHLESS) {
+        const C<T> f = cross ? phase : C<T>{T(1), T(0)};
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g.s[r][c] = g.s[r][c] * f;
+    } else if (cross) {
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
