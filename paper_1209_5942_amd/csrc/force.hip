@@ -14,10 +14,6 @@
 #include "device.h"
 #include "internal.h"
 
-// waves per SIMD the force kernel is compiled for (launch bounds)
-#ifndef FORCE_WAVES
-#define FORCE_WAVES 3
-#endif
 
 namespace tmqcd {
 namespace {
@@ -175,14 +171,16 @@ __device__ __forceinline__ void force_dir(const ForceK& a, int par, int h, int n
 // branch), so each thread holds one direction's operands; the four waves read
 // the same X(x), Y(x) (cache hits after the first; staging them in LDS once per
 // block measured 3 % slower).  Projecting every spinor as it arrives and adding
-// each outer product to Q at once keeps the kernel within 168 registers (three
-// waves per SIMD; 242-256 registers and two waves when the four spinors were
-// held whole).  Holding all four directions per thread needed 260 registers,
-// one wave per SIMD, and ran 14 % slower; putting the two terms of Q on separate
-// waves (eight per block, four waves per SIMD with 36 registers spilled) ran 45 %
-// slower.
+// each outer product to Q at once would fit 168 registers (three waves per SIMD),
+// but at that budget the compiler waits for each spinor's loads before issuing
+// the next one's.  Compiled for at most two waves per SIMD (about 205 registers)
+// it issues them together: 39 -> 35 us at 16^3 x 32, 191 -> 185 us at 24^3 x 48
+// and 612 -> 559 us at 32^3 x 64, bitwise the same output.  Holding all four
+// directions per thread needed 260 registers, one wave per SIMD, and ran 14 %
+// slower; putting the two terms of Q on separate waves (eight per block, four
+// waves per SIMD with 36 registers spilled) ran 45 % slower.
 template <int R>
-__global__ __launch_bounds__(kBlock, FORCE_WAVES) void force_dir_kernel(const ForceK a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void force_dir_kernel(const ForceK a) {
     // the block's 64 output records (32 doubles each, +1 against bank conflicts) and their sites
     __shared__ double otile[64][33];
     __shared__ int64_t srec[64];
