@@ -95,6 +95,21 @@ def test_batch_of_one_and_of_eight():
         assert D.true_rel_residual(A, bs[k], xs[k]) <= 1e-10
 
 
+@pytest.mark.timeout(300)
+def test_batch_of_thermal_lattices():
+    """Four lattices of short time extent (16^3 x 4, 6, 8 and 20^3 x 4, the bench's thermal batch),
+    graph and eager: every member against the oracle, the two bitwise equal."""
+    specs = [((16, 16, 16, 4), BC_AP), ((16, 16, 16, 6), BC_AP), ((16, 16, 16, 8), BC_AP), ((20, 20, 20, 4), BC_AP)]
+    fs, bs = _setup(specs)
+    xg, sg, rcg = _batch(fs, bs, True)
+    xe, se, rce = _batch(fs, bs, False)
+    assert rcg == T.OK and rce == T.OK
+    for k, f in enumerate(fs):
+        assert sg[k]["converged"] == 1 and np.array_equal(xg[k], xe[k]), k
+        A = lambda v, f=f: D.apply_MhatdagMhat(f.U, v, f.dims, f.kappa, f.mu, f.bc)
+        assert D.true_rel_residual(A, bs[k], xg[k]) <= 1e-10
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_batch_member_breakdown_leaves_the_others_solved(use_graph):
     """One lattice's links hold a NaN, so its first p^+ A p is not finite and its solve
