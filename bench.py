@@ -325,6 +325,7 @@ def main():
         result["batch_cg"] = bench_batch(T, synth, dev, not args.no_oracle)
         result["batch_cg_thermal"] = bench_batch(T, synth, dev, not args.no_oracle, BATCH_THERMAL)
         result["hmc_16x16x16x32"] = bench_hmc(T, synth, dev)
+        result["force_f64_large"] = bench_force_large(T, dev, read_gbs)
         result["heatbath"] = bench_heatbath(T, synth, dev)
 
     # ------------------------------------- oracle check and CPU baseline ---
@@ -777,11 +778,13 @@ def counters_from(fetch_csv, write_csv, name, last_n):
 
 def mrhs_shapes_from_counters(fetch_csv, write_csv, kernel_log):
     """FETCH_SIZE / WRITE_SIZE bytes of the FP64 12-RHS hop in each pinned shape of --kernel-only mrhs
-    (the calibration copy's factor applied), with the links' and spinors' share of the fetch."""
+    (the calibration copy's factor applied), with the links' and spinors' share of the fetch; then the
+    same for the launches in the shape the tuner chose (the ones before the pinned shapes)."""
     import csv
     with open(kernel_log) as fh:
         info = [json.loads(l) for l in fh if l.startswith("{")][-1]
     shapes, n = [tuple(x) for x in info["f64_shapes"]], info["f64_shape_launches"]
+    pinned, tuned = n * len(shapes), info["launches"]
     links, spinors = info["vh"] * 1152, 12 * info["vh"] * 192   # FP64 RECON18 links (8 per output site), 12 half spinors
     out = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
@@ -791,14 +794,19 @@ def mrhs_shapes_from_counters(fetch_csv, write_csv, kernel_log):
         copy = [float(r["Counter_Value"]) for r in rs if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer")][0]
         factor = (1 << 30) / 1024.0 / copy
         v = [float(r["Counter_Value"]) * 1024.0 * factor for r in rs
-             if "hop_mrhs_kernel<0, 0, false, false, 0>" in r["Kernel_Name"]][-n * len(shapes):]
-        assert len(v) == n * len(shapes), (counter, len(v))
+             if "hop_mrhs_kernel<0, 0, false, false, 0>" in r["Kernel_Name"]][-(pinned + tuned):]
+        assert len(v) == pinned + tuned, (counter, len(v))
+        out.setdefault("tuned", {})[counter] = round(sum(v[:tuned]) / tuned)
+        v = v[tuned:]
         for i, (order, group) in enumerate(shapes):
             out.setdefault(f"{order}/{group}", {})[counter] = round(sum(v[i * n:(i + 1) * n]) / n)
-    for key, r in out.items():
-        sweeps = 1 if key.endswith("/0") else 12 // int(key.split("/")[1])
+    tuned_shape = f'{info["f64"]["order"]}/{info["f64"]["group"]}'
+    for key in [f"{o}/{g}" for o, g in shapes] + ["tuned"]:
+        r = out[key]
+        shape = tuned_shape if key == "tuned" else key
+        sweeps = 1 if shape.endswith("/0") else 12 // int(shape.split("/")[1])
         r["spinor_fetch_ratio"] = round((r["FETCH_SIZE"] - sweeps * links) / spinors, 2)
-        print(json.dumps({"shape": key, **r}))
+        print(json.dumps({"shape": key if key != "tuned" else "tuned " + tuned_shape, **r}))
 
 
 def durations_from_trace(path, name, last_n):
@@ -1052,6 +1060,33 @@ def bench_batch(T, synth, dev, check=True, dims_list=BATCH_MIXED):
     res["speedup_graph_vs_separate"] = round(res["separate_solves_ms"] / res["graph_batch_ms"], 3)
     res["speedup_eager_vs_separate"] = round(res["separate_solves_ms"] / res["eager_batch_ms"], 3)
     return res
+
+
+def bench_force_large(T, dev, read_gbs):
+    """The fermion force kernel (FP64 RECON18) at 24^3x48 and 32^3x64 on random links and spinors (the
+    values do not change the memory traffic): time per launch from HIP events, the compulsory bytes per
+    site (4 links, X and Y once each, the 4 x 8 outputs: 1216 B) over it, against the 8 TB/s peak and the
+    read rate measured in the same run."""
+    import torch
+    log("force kernel at 24^3x48 and 32^3x64")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    out = {}
+    for dims in ((24, 24, 24, 48), (32, 32, 32, 64)):
+        prob = T.Problem(dims, 0.155, 0.01, (1, 1, 1, -1))
+        v = prob.volume
+        g = T.pack_gauge(prob, torch.randn((v, 4, 3, 3), dtype=torch.complex128, device=dev, generator=gen))
+        X = T.pack_spinor(prob, torch.randn((v, 4, 3), dtype=torch.complex128, device=dev, generator=gen))
+        Y = T.pack_spinor(prob, torch.randn((v, 4, 3), dtype=torch.complex128, device=dev, generator=gen))
+        G = torch.empty((v, 4, 8), dtype=torch.float64, device=dev)
+        t = _events_time(lambda: T.force(prob, g, X, Y, out=G), 20)
+        gbs = v * (4 * 144 + 2 * 192 + 256) / t / 1e9
+        out["x".join(map(str, dims))] = {"us": round(t * 1e6, 1), "GB_s": round(gbs, 1),
+                                         "frac_of_8TB_s": round(gbs / PEAK_HBM_GBPS, 4),
+                                         "frac_of_measured_read": round(gbs / read_gbs, 4)}
+        del g, X, Y, G
+    out["bytes_per_site"] = 1216
+    return out
 
 
 def bench_hmc(T, synth, dev):

@@ -97,11 +97,13 @@ def test_hop_source_hash_is_stable():
 
 
 def test_mrhs_shapes_from_counters_attributes_launches(tmp_path, capsys):
-    """The 18 x 3 pinned 12-RHS launches are attributed to their shapes in order, and the spinors'
-    share of the fetch is what remains after the link reads of each sweep."""
+    """The 18 x 3 pinned 12-RHS launches are attributed to their shapes in order, the 10 before them to
+    the tuned shape, and the spinors' share of the fetch is what remains after the link reads of each
+    sweep."""
     vh = 1000
     shapes = [[o, g] for o in range(6) for g in (0, 6, 4)]
-    info = {"copy_bytes": 1 << 30, "launches": 10, "f64_shapes": shapes, "f64_shape_launches": 3, "vh": vh}
+    info = {"copy_bytes": 1 << 30, "launches": 10, "f64_shapes": shapes, "f64_shape_launches": 3, "vh": vh,
+            "f64": {"order": 3, "group": 6}}
     log = tmp_path / "k.log"
     log.write_text(json.dumps(info) + "\n")
     name = "void tmqcd::stencil::(anonymous namespace)::hop_mrhs_kernel<0, 0, false, false, 0>(tmqcd::stencil::HopK)"
@@ -109,8 +111,12 @@ def test_mrhs_shapes_from_counters_attributes_launches(tmp_path, capsys):
     for counter, copy_kib in (("FETCH_SIZE", 524288.0), ("WRITE_SIZE", 1048576.0)):
         lines = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value", f"1,__amd_rocclr_copyBuffer,{counter},{copy_kib}"]
         d = 2
-        for _ in range(10):   # the tuned launches before the pinned ones
-            lines.append(f'{d},"{name}",{counter},1')
+        for _ in range(4):    # the tuner's own trial launches
+            lines.append(f'{d},"{name}",{counter},77')
+            d += 1
+        for _ in range(10):   # the tuned launches before the pinned ones: shape 3/6, two sweeps
+            kib = (2 * links + 2.0 * spinors) / 1024.0 / 2.0 if counter == "FETCH_SIZE" else 12 * vh * 192 / 1024.0
+            lines.append(f'{d},"{name}",{counter},{kib}')
             d += 1
         for i, (o, g) in enumerate(shapes):
             sweeps = 1 if g == 0 else 12 // g
@@ -122,7 +128,8 @@ def test_mrhs_shapes_from_counters_attributes_launches(tmp_path, capsys):
         (tmp_path / f"{counter}.csv").write_text("\n".join(lines) + "\n")
     bench.mrhs_shapes_from_counters(str(tmp_path / "FETCH_SIZE.csv"), str(tmp_path / "WRITE_SIZE.csv"), str(log))
     out = [json.loads(l) for l in capsys.readouterr().out.splitlines()]
-    assert [r["shape"] for r in out] == [f"{o}/{g}" for o, g in shapes]
-    for i, r in enumerate(out):
+    assert [r["shape"] for r in out] == [f"{o}/{g}" for o, g in shapes] + ["tuned 3/6"]
+    for i, r in enumerate(out[:-1]):
         assert r["spinor_fetch_ratio"] == round(1.5 + 0.1 * i, 2)
         assert r["WRITE_SIZE"] == 12 * vh * 192
+    assert out[-1]["spinor_fetch_ratio"] == 2.0 and out[-1]["WRITE_SIZE"] == 12 * vh * 192
