@@ -259,9 +259,10 @@ __global__ void set_state_kernel(CgState* st, StateInit v) {
     if (v.set_iter) st->iter = v.iter;
     if (v.set_max_iter) st->max_iter = v.max_iter;
     if (v.set_cycle_end) st->cycle_end = v.cycle_end;
-    if (v.set_done) {   // a solve (re)starts or stops here: no beta finish is pending
+    if (v.set_done) {   // a solve (re)starts or stops here: no beta finish or x update is pending
         st->done = v.done;
         st->beta_pending = 0;
+        st->x_pending = 0;
     }
 }
 
@@ -301,18 +302,33 @@ __global__ __launch_bounds__(kBlock) void cg_finish_cols_kernel(CgState* st, con
 }
 
 // p_c = r_c + beta_c p_c for every column c = blockIdx.y whose solve runs (FP64 fields fstride apart).
-__global__ __launch_bounds__(kBlock) void xpay_cols_kernel(VecK v, char* p, const char* r, int64_t hbytes,
+__global__ __launch_bounds__(kBlock) void xpay_cols_kernel(VecK v, char* p, const char* r, char* x, int64_t hbytes,
                                                            int64_t fstride, const CgState* st) {
     const int c = blockIdx.y;
-    if (st[c].done) return;
+    // x += alpha p for a column whose r update ran in this iteration (also the one that stopped
+    // it), then p = r + beta p while the column runs
+    const bool upd_x = st[c].x_pending != 0, upd_p = st[c].done == 0;
+    if (!upd_x && !upd_p) return;
     int half, h;
     if (!site_of(v, blockIdx.x * kBlock + threadIdx.x, half, h)) return;
-    const double beta = st[c].beta;
     char* pc = p + c * fstride + half * hbytes;
-    const char* rc = r + c * fstride + half * hbytes;
-    Spinor<double> pv, rv;
+    Spinor<double> pv;
     SpinorIO<TMQCD_F64>::load(pv, pc, v.stride, h);
-    SpinorIO<TMQCD_F64>::load(rv, rc, v.stride, h);
+    if (upd_x) {
+        const double alpha = st[c].alpha;
+        char* xc = x + c * fstride + half * hbytes;
+        Spinor<double> xv;
+        SpinorIO<TMQCD_F64>::load(xv, xc, v.stride, h);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) xv.s[s][k] = xv.s[s][k] + scale(alpha, pv.s[s][k]);
+        SpinorIO<TMQCD_F64>::store(xc, v.stride, h, xv);
+    }
+    if (!upd_p) return;
+    const double beta = st[c].beta;
+    Spinor<double> rv;
+    SpinorIO<TMQCD_F64>::load(rv, r + c * fstride + half * hbytes, v.stride, h);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -479,12 +495,13 @@ hipError_t launch_cg_finish_cols(CgState* st, const double* partials, int tiles,
     return hipGetLastError();
 }
 
-hipError_t launch_xpay_cols(const VecSpec& v, void* p, const void* r, int64_t fstride, int ncol, const CgState* st,
-                            hipStream_t s) {
+hipError_t launch_xpay_cols(const VecSpec& v, void* p, const void* r, void* x, int64_t fstride, int ncol,
+                            const CgState* st, hipStream_t s) {
     const VecK k = make_veck(v);
     if (ncol < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(xpay_cols_kernel, dim3(k.nblocks, ncol), dim3(kBlock), 0, s, k, static_cast<char*>(p),
-                       static_cast<const char*>(r), half_field_bytes(*v.g, TMQCD_F64), fstride, st);
+                       static_cast<const char*>(r), static_cast<char*>(x), half_field_bytes(*v.g, TMQCD_F64), fstride,
+                       st);
     return hipGetLastError();
 }
 

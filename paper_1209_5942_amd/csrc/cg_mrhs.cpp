@@ -170,7 +170,8 @@ int run_cg_mrhs(const tmqcd_problem& prob, const void* gauge, const void* b, voi
     if (full) {
         k1 = hp_full(c, w.p, w.t1, false, kEpiStoreNorm, states, w.partials, nullptr, nullptr, nullptr,
                      Rhs{n, fs, fs, 2 * hb});
-        k2 = hp_full(c, w.t1, nullptr, true, kEpiCgUpdate, states, w.partials, x, w.r, w.p, Rhs{n, 2 * hb, 2 * hb, 0});
+        k2 = hp_full(c, w.t1, nullptr, true, kEpiCgUpdate, states, w.partials, nullptr, w.r, nullptr,
+                     Rhs{n, 2 * hb, 2 * hb, 0});
         k2.v_fstride = fs;
     } else {
         k1 = hp_schur_first(c, w.p, w.t1, false, one_half);
@@ -179,7 +180,7 @@ int run_cg_mrhs(const tmqcd_problem& prob, const void* gauge, const void* b, voi
                              Rhs{n, hb, fs, hb});
         k3 = hp_schur_first(c, w.t2, w.t1, true, one_half);
         k3.st = states;
-        k4 = hp_schur_second(c, w.t1, w.t2, nullptr, true, kEpiCgUpdate, states, w.partials, x, w.r, w.p,
+        k4 = hp_schur_second(c, w.t1, w.t2, nullptr, true, kEpiCgUpdate, states, w.partials, nullptr, w.r, nullptr,
                              Rhs{n, hb, hb, 0});
         k4.v_fstride = fs;
     }
@@ -201,7 +202,7 @@ int run_cg_mrhs(const tmqcd_problem& prob, const void* gauge, const void* b, voi
             hop_launches += 4;
         }
         if (e == hipSuccess) e = launch_cg_finish_cols(states, w.partials, tiles, n, kFinishBeta, s);
-        if (e == hipSuccess) e = launch_xpay_cols(vs, w.p, w.r, fs, n, states, s);
+        if (e == hipSuccess) e = launch_xpay_cols(vs, w.p, w.r, x, fs, n, states, s);
         return e;
     };
 

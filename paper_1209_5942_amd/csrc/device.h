@@ -582,6 +582,8 @@ struct CgState {
     int cycle_end;    // the update kernel flags done when iter reaches it (reliable-update cycle cap)
     int done;         // 0 running, 1 reached stop_rr or cycle_end, 2 breakdown, 3 iteration cap
     int beta_pending; // the search-direction update used partial sums whose finish is still due
+    int x_pending;    // multi-RHS CG: this iteration's r update ran, x += alpha p is due (set by the
+                      // beta finish, done by the search-direction update, cleared by the next alpha finish)
     double result[4]; // scratch results of standalone reductions
 };
 enum { kDoneRunning = 0, kDoneStop = 1, kDoneBreakdown = 2, kDoneMaxIter = 3 };
@@ -704,6 +706,7 @@ __device__ __forceinline__ bool cg_finish_block(CgState* st, const double* parti
     if (threadIdx.x == 0) {
         stopped = st->done;
         skip = kind == 2 && !st->beta_pending;
+        if (kind == 0) st->x_pending = 0;   // the previous iteration's x update has run
     }
     __syncthreads();
     const bool before = stopped != 0, nothing = skip != 0;
@@ -715,6 +718,7 @@ __device__ __forceinline__ bool cg_finish_block(CgState* st, const double* parti
     if (threadIdx.x == 0) {
         cg_finish_update(st, tot[0], kind == 2 ? 1 : kind);
         if (kind == 2) st->beta_pending = 0;
+        if (kind == 1) st->x_pending = 1;
         stopped = st->done;
     }
     __syncthreads();

@@ -17,16 +17,15 @@ namespace {
 // column: columns whose solve has stopped are skipped (a column belongs to one
 // wave at a time, so the test is wave-uniform), and the epilogues of the CG
 // stages run per column: kEpiStoreNorm stores the output and sums its |out|^2,
-// kEpiCgUpdate updates x += alpha p, r -= alpha out and sums |r|^2; the sums of
-// a wave's 64 sites go to partials[column * tiles + tile] (no block-level step).
+// kEpiCgUpdate updates r -= alpha out and sums |r|^2 (x += alpha p is left to
+// the search-direction update, which reads p anyway); the sums of a wave's 64
+// sites go to partials[column * tiles + tile] (no block-level step).
 struct MrhsK {
     int nrhs, group, tiles;
     int64_t in_fstride, own_fstride, out_fstride;
     const CgState* st;       // per column, or nullptr outside CG
     double* partials;        // [nrhs][tiles]
-    char* x;                 // CG update: x, r (FP64), p; vector fields v_fstride apart
-    char* r;
-    const char* p;
+    char* r;                 // CG update: r (FP64), fields v_fstride apart
     int64_t v_fstride;
 };
 
@@ -124,19 +123,15 @@ __global__ __launch_bounds__(kBlock) void hop_mrhs_kernel(const HopK a, const Mr
             static_assert(P == TMQCD_F64, "the multi-RHS CG update runs in FP64");
             const T alpha = (T)m.st[r].alpha;
             const int64_t voff = two ? (int64_t)par * a.vhbytes : 0;
-            Spinor<T> pv, xv, rv;
-            SpinorIO<P>::load(pv, m.p + r * m.v_fstride + voff, a.stride, h);
-            SpinorIO<P>::load(xv, m.x + r * m.v_fstride + voff, a.stride, h);
+            Spinor<T> rv;
             SpinorIO<P>::load(rv, m.r + r * m.v_fstride + voff, a.stride, h);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
                     rv.s[s][c] = rv.s[s][c] - scale(alpha, acc.s[s][c]);
                     red += (double)norm2(rv.s[s][c]);
                 }
-            SpinorIO<P>::store(m.x + r * m.v_fstride + voff, a.stride, h, xv);
             SpinorIO<P>::store(m.r + r * m.v_fstride + voff, a.stride, h, rv);
         }
         }   // valid
@@ -158,9 +153,7 @@ hipError_t launch_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
     m.out_fstride = a.out_fstride;
     m.st = a.st;
     m.partials = a.partials;
-    m.x = static_cast<char*>(a.x);
     m.r = static_cast<char*>(a.r);
-    m.p = static_cast<const char*>(a.p);
     m.v_fstride = a.v_fstride;
     const bool own = a.own != nullptr;
     const dim3 grid(k.nblocks * ((m.nrhs + m.group - 1) / m.group)), block(kBlock);
@@ -176,7 +169,7 @@ hipError_t launch_mrhs(const HopParams& a, const HopK& k, hipStream_t s) {
         if (a.st == nullptr || a.partials == nullptr || !own) return hipErrorInvalidValue;
         if (a.epi == kEpiStoreNorm && !a.dag)
             hipLaunchKernelGGL((hop_mrhs_kernel<P, R, false, true, kEpiStoreNorm>), grid, block, 0, s, k, m);
-        else if (a.epi == kEpiCgUpdate && a.dag && a.x && a.r && a.p)
+        else if (a.epi == kEpiCgUpdate && a.dag && a.r)
             hipLaunchKernelGGL((hop_mrhs_kernel<P, R, true, true, kEpiCgUpdate>), grid, block, 0, s, k, m);
         else
             return hipErrorInvalidValue;

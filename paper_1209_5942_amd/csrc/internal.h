@@ -20,7 +20,8 @@ struct Cplx {
 enum HopEpilogue {
     kEpiStore = 0,      // out = own-term + hop-term
     kEpiStoreNorm = 1,  // ... and the partial sums of |out|^2 (then cg_finish: pAp, alpha)
-    kEpiCgUpdate = 2,   // out not stored: x += alpha p; r -= alpha out; partial sums of |r|^2 (cg_finish: rr, beta)
+    kEpiCgUpdate = 2,   // out not stored: r -= alpha out (and x += alpha p where x is given: the batched CG);
+                        // partial sums of |r|^2 (cg_finish: rr, beta)
 };
 
 // out_p = [c_own * own_p] + c_hop * (H in)_p, where c = diag(cu, cu, cd, cd) in
@@ -159,10 +160,12 @@ hipError_t launch_cg_finish(CgState* st, const double* partials, int n, int kind
 hipError_t launch_cg_finish_batch(CgState* const* st, const double* const* partials, const int* n, int count,
                                   int kind, hipStream_t s);
 // The multi-RHS CG: column c's reduction (tiles partials at partials + c * tiles) finished on st[c]
-// for c < ncol; p_c = r_c + beta_c p_c for the running columns (FP64 fields fstride bytes apart)
+// for c < ncol; x_c += alpha_c p_c for the columns whose r update ran in this iteration
+// (st[c].x_pending), then p_c = r_c + beta_c p_c for the running columns (FP64 fields fstride
+// bytes apart)
 hipError_t launch_cg_finish_cols(CgState* st, const double* partials, int tiles, int ncol, int kind, hipStream_t s);
-hipError_t launch_xpay_cols(const VecSpec& v, void* p, const void* r, int64_t fstride, int ncol, const CgState* st,
-                            hipStream_t s);
+hipError_t launch_xpay_cols(const VecSpec& v, void* p, const void* r, void* x, int64_t fstride, int ncol,
+                            const CgState* st, hipStream_t s);
 // st->rr = st->result[slot]; optionally stop_rr = factor * rr
 hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipStream_t s);
 
