@@ -96,7 +96,7 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
     std::vector<int> applies(n, 0), active(n, 1);
     std::vector<HopParams> k1(n), k2(n), k3(n), k4(n);
     std::vector<VecSpec> vs(n);
-    std::vector<void*> pp(n);
+    std::vector<void*> pp(n), xp(n);
     std::vector<const void*> rp(n);
     std::vector<CgState*> sp(n);
     const int check = o.check_every > 0 ? o.check_every : 8;
@@ -119,7 +119,8 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
         if (e == hipSuccess) e = launch_hop_batch(k3.data(), n, kPersistentGrid, s);
         if (e == hipSuccess) e = launch_hop_batch(k4.data(), n, kPersistentGrid, s, nb.data());
         if (e == hipSuccess) e = launch_cg_finish_batch(sp.data(), parts.data(), nb.data(), n, kFinishBeta, s);
-        if (e == hipSuccess) e = launch_xpay_batch(vs.data(), pp.data(), rp.data(), sp.data(), n, kPersistentGrid, s);
+        if (e == hipSuccess)
+            e = launch_xpay_batch(vs.data(), pp.data(), rp.data(), xp.data(), sp.data(), n, kPersistentGrid, s);
         return e;
     };
     // a stream that can be captured (the null stream cannot)
@@ -148,9 +149,11 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
                                 kOne);
         k3[i] = hp_schur_first(l.c, l.t2, l.t3, true, kOne);
         k3[i].st = l.st;
-        k4[i] = hp_schur_second(l.c, l.t3, l.t2, nullptr, true, kEpiCgUpdate, l.st, l.partials, x[i], l.r, l.p, kOne);
+        k4[i] = hp_schur_second(l.c, l.t3, l.t2, nullptr, true, kEpiCgUpdate, l.st, l.partials, nullptr, l.r, nullptr,
+                                kOne);
         parts[i] = l.partials;
         pp[i] = l.p;
+        xp[i] = x[i];
         rp[i] = l.r;
         sp[i] = l.st;
     }

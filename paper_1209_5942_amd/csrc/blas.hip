@@ -163,22 +163,39 @@ struct XpayBatch {
     VecK v[kMaxBatchVec];
     char* p[kMaxBatchVec];
     const char* r[kMaxBatchVec];
+    char* x[kMaxBatchVec];
     const CgState* st[kMaxBatchVec];
     int64_t bytes;
 };
 
-// p = r + beta p for several lattices (FP64), grid-stride over their tiles
+// For several lattices (FP64), grid-stride over their tiles: x += alpha p where the
+// lattice's r update ran in this iteration (also the one that stopped it), then
+// p = r + beta p while the lattice runs
 __global__ __launch_bounds__(kBlock) void xpay_batch_kernel(const XpayBatch b) {
     const int total = b.tile_start[b.n];
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         int i = 0;
         while (tile >= b.tile_start[i + 1]) ++i;
-        if (b.st[i]->done) continue;
+        const CgState* st = b.st[i];
+        const bool upd_x = st->x_pending != 0, upd_p = st->done == 0;
+        if (!upd_x && !upd_p) continue;
         int half, h;
         if (!site_of(b.v[i], (tile - b.tile_start[i]) * kBlock + threadIdx.x, half, h)) continue;
-        const double beta = b.st[i]->beta;
-        Spinor<double> pv, rv;
+        Spinor<double> pv;
         SpinorIO<TMQCD_F64>::load(pv, b.p[i] + half * b.bytes, b.v[i].stride, h);
+        if (upd_x) {
+            const double alpha = st->alpha;
+            Spinor<double> xv;
+            SpinorIO<TMQCD_F64>::load(xv, b.x[i] + half * b.bytes, b.v[i].stride, h);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
+            SpinorIO<TMQCD_F64>::store(b.x[i] + half * b.bytes, b.v[i].stride, h, xv);
+        }
+        if (!upd_p) continue;
+        const double beta = st->beta;
+        Spinor<double> rv;
         SpinorIO<TMQCD_F64>::load(rv, b.r[i] + half * b.bytes, b.v[i].stride, h);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -510,8 +527,8 @@ hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* const* r, CgState* const* st, int n,
-                             int max_grid, hipStream_t s) {
+hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* const* r, void* const* x,
+                             CgState* const* st, int n, int max_grid, hipStream_t s) {
     if (n < 1 || n > kMaxBatchVec) return hipErrorInvalidValue;
     XpayBatch b;
     b.n = n;
@@ -521,6 +538,7 @@ hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* cons
         b.v[i] = make_veck(vs[i]);
         b.p[i] = static_cast<char*>(p[i]);
         b.r[i] = static_cast<const char*>(r[i]);
+        b.x[i] = static_cast<char*>(x[i]);
         b.st[i] = st[i];
         b.tile_start[i + 1] = b.tile_start[i] + b.v[i].nblocks;
     }

@@ -61,9 +61,7 @@ struct HopK {
     const char* in;
     const char* own;
     char* out;
-    char* x;
-    char* r;
-    const char* p;
+    char* r;                 // CG update: the residual, r -= alpha (A p)
     CgState* st;
     double* partials;
     int64_t stride, gstride, hbytes, vhbytes;
@@ -304,22 +302,12 @@ __device__ __forceinline__ double hop_site(const HopK& a, int par, int h) {
                 for (int c = 0; c < 3; ++c) red += (double)norm2(acc.s[s][c]);
         }
     } else {
-        // r -= alpha (A p), and x += alpha p unless x is null (the single-lattice CG
-        // updates x in its p = r + beta p launch, which reads p anyway)
+        // r -= alpha (A p); the CG solvers update x in their p = r + beta p launch,
+        // which reads p anyway
         const T alpha = (T)a.st->alpha;
         const int64_t voff = two ? (int64_t)par * a.vhbytes : 0;
         Spinor<T> rv;
         SpinorIO<PV>::load(rv, a.r + voff, a.stride, h);
-        if (a.x != nullptr) {
-            Spinor<T> pv, xv;
-            SpinorIO<P>::load(pv, a.p + hoff, a.stride, h);
-            SpinorIO<PV>::load(xv, a.x + voff, a.stride, h);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
-            SpinorIO<PV>::store(a.x + voff, a.stride, h, xv);
-        }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -376,9 +364,7 @@ inline HopK make_hopk(const HopParams& a, int w) {
     k.in = static_cast<const char*>(a.in);
     k.own = static_cast<const char*>(a.own);
     k.out = static_cast<char*>(a.out);
-    k.x = static_cast<char*>(a.x);
     k.r = static_cast<char*>(a.r);
-    k.p = static_cast<const char*>(a.p);
     k.st = a.st;
     k.partials = a.partials;
     k.stride = a.g.stride;
