@@ -3,8 +3,9 @@
 // a CG iteration on Mhat^+ Mhat is a single grid-stride launch over the tiles
 // of all lattices, every lattice with its own solver state; lattices that have
 // converged are skipped inside the launches.  An iteration is 4 hop launches
-// (the first tile of a lattice finishing its alpha reduction in the third), a
-// one-block-per-lattice finish of beta and the search-direction update; the
+// (the first tile of a lattice finishing the previous beta in the first and its
+// alpha reduction in the third) and the search-direction update, which forms
+// beta itself and leaves the state's beta finish pending; the
 // iterations queued between two host checks can be captured once in a
 // hipGraph and replayed with one launch, which removes the per-kernel launch
 // cost of the host at these volumes.
@@ -109,6 +110,11 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
     std::vector<const double*> parts(n);
     std::vector<int> nb(n);
     auto iteration = [&]() -> hipError_t {
+        for (int i = 0; i < n; ++i) {   // each lattice's first tile finishes the previous beta, if pending
+            k1[i].fin_partials = parts[i];
+            k1[i].fin_n = nb[i];
+            k1[i].fin_kind = kFinishBetaPending;
+        }
         hipError_t e = launch_hop_batch(k1.data(), n, kPersistentGrid, s);
         if (e == hipSuccess) e = launch_hop_batch(k2.data(), n, kPersistentGrid, s, nb.data());
         for (int i = 0; i < n; ++i) {   // each lattice's first tile of the next stage finishes alpha
@@ -118,10 +124,16 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
         }
         if (e == hipSuccess) e = launch_hop_batch(k3.data(), n, kPersistentGrid, s);
         if (e == hipSuccess) e = launch_hop_batch(k4.data(), n, kPersistentGrid, s, nb.data());
-        if (e == hipSuccess) e = launch_cg_finish_batch(sp.data(), parts.data(), nb.data(), n, kFinishBeta, s);
+        // x += alpha p and p = r + beta p, beta formed from the update's partials; the beta finish is pending
         if (e == hipSuccess)
-            e = launch_xpay_batch(vs.data(), pp.data(), rp.data(), xp.data(), sp.data(), n, kPersistentGrid, s);
+            e = launch_xpay_batch(vs.data(), pp.data(), rp.data(), xp.data(), sp.data(), parts.data(), nb.data(), n,
+                                  kPersistentGrid, s);
         return e;
+    };
+    // the pending beta finish of the last iteration queued (before the host reads the states)
+    auto finish_pending = [&]() -> hipError_t {
+        return nb[0] > 0 ? launch_cg_finish_batch(sp.data(), parts.data(), nb.data(), n, kFinishBetaPending, s)
+                         : hipSuccess;
     };
     // a stream that can be captured (the null stream cannot)
     if (use_graph && s == nullptr) {
@@ -182,6 +194,7 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
         TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipError_t ec = hipSuccess;
         for (int k = 0; k < check && ec == hipSuccess; ++k) ec = iteration();
+        if (ec == hipSuccess) ec = finish_pending();   // each replay ends finished
         const hipError_t ee = hipStreamEndCapture(s, &graph);
         TRY(ec);
         TRY(ee);
@@ -193,9 +206,12 @@ int run_cg_batch(int n, const tmqcd_problem* probs, const void* const* gauge, co
         if (!any) break;
         // iterate until every active lattice has stopped
         for (;;) {
-            if (use_graph) TRY(hipGraphLaunch(exec, s));
-            else
+            if (use_graph) {
+                TRY(hipGraphLaunch(exec, s));
+            } else {
                 for (int k = 0; k < check; ++k) TRY(iteration());
+                TRY(finish_pending());
+            }
             TRY(read_states());
             bool running = false;
             for (int i = 0; i < n; ++i) running = running || (active[i] && hs[i].done == kDoneRunning);

@@ -164,37 +164,42 @@ struct XpayBatch {
     char* p[kMaxBatchVec];
     const char* r[kMaxBatchVec];
     char* x[kMaxBatchVec];
-    const CgState* st[kMaxBatchVec];
+    CgState* st[kMaxBatchVec];
+    const double* partials[kMaxBatchVec];   // the update hop's |r|^2 partials of each lattice
+    int np[kMaxBatchVec];
     int64_t bytes;
 };
 
-// For several lattices (FP64), grid-stride over their tiles: x += alpha p where the
-// lattice's r update ran in this iteration (also the one that stopped it), then
-// p = r + beta p while the lattice runs
+// The batched CG's search-direction update, as xpay_fused_kernel for several lattices
+// (FP64), grid-stride over their tiles: every tile forms its lattice's beta from the
+// update hop's partials, x += alpha p, and p = r + beta p unless the pending finish will
+// stop the lattice at this iteration; the lattice's first tile marks that finish
+// pending (the next iteration's first hop, or the finish before the host reads, does it).
 __global__ __launch_bounds__(kBlock) void xpay_batch_kernel(const XpayBatch b) {
     const int total = b.tile_start[b.n];
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         int i = 0;
         while (tile >= b.tile_start[i + 1]) ++i;
-        const CgState* st = b.st[i];
-        const bool upd_x = st->x_pending != 0, upd_p = st->done == 0;
-        if (!upd_x && !upd_p) continue;
+        CgState* st = b.st[i];
+        if (block_stopped(st)) continue;   // block-uniform
+        double tot[1];
+        sum_partials<1>(b.partials[i], b.np[i], tot);
+        const double beta = tot[0] / st->rr;
+        if (tile == b.tile_start[i] && threadIdx.x == 0) st->beta_pending = 1;
+        const int it = st->iter + 1;
+        const bool stops = !isfinite(tot[0]) || tot[0] <= st->stop_rr || it >= st->cycle_end || it >= st->max_iter;
         int half, h;
         if (!site_of(b.v[i], (tile - b.tile_start[i]) * kBlock + threadIdx.x, half, h)) continue;
-        Spinor<double> pv;
+        const double alpha = st->alpha;
+        Spinor<double> pv, xv;
         SpinorIO<TMQCD_F64>::load(pv, b.p[i] + half * b.bytes, b.v[i].stride, h);
-        if (upd_x) {
-            const double alpha = st->alpha;
-            Spinor<double> xv;
-            SpinorIO<TMQCD_F64>::load(xv, b.x[i] + half * b.bytes, b.v[i].stride, h);
+        SpinorIO<TMQCD_F64>::load(xv, b.x[i] + half * b.bytes, b.v[i].stride, h);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
-            SpinorIO<TMQCD_F64>::store(b.x[i] + half * b.bytes, b.v[i].stride, h, xv);
-        }
-        if (!upd_p) continue;
-        const double beta = st->beta;
+            for (int c = 0; c < 3; ++c) xv.s[s][c] = xv.s[s][c] + scale(alpha, pv.s[s][c]);
+        SpinorIO<TMQCD_F64>::store(b.x[i] + half * b.bytes, b.v[i].stride, h, xv);
+        if (stops) continue;
         Spinor<double> rv;
         SpinorIO<TMQCD_F64>::load(rv, b.r[i] + half * b.bytes, b.v[i].stride, h);
 #pragma unroll
@@ -528,7 +533,8 @@ hipError_t launch_rr_from_result(CgState* st, int slot, double stop_factor, hipS
 }
 
 hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* const* r, void* const* x,
-                             CgState* const* st, int n, int max_grid, hipStream_t s) {
+                             CgState* const* st, const double* const* partials, const int* np, int n, int max_grid,
+                             hipStream_t s) {
     if (n < 1 || n > kMaxBatchVec) return hipErrorInvalidValue;
     XpayBatch b;
     b.n = n;
@@ -540,6 +546,8 @@ hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* cons
         b.r[i] = static_cast<const char*>(r[i]);
         b.x[i] = static_cast<char*>(x[i]);
         b.st[i] = st[i];
+        b.partials[i] = partials[i];
+        b.np[i] = np[i];
         b.tile_start[i + 1] = b.tile_start[i] + b.v[i].nblocks;
     }
     for (int i = 0; i < n; ++i)

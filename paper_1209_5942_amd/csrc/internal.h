@@ -131,10 +131,12 @@ hipError_t launch_xpay(const VecSpec& v, void* p, int pp, const void* r, int pr,
 // (the partials of the update hop's |r|^2); sets st->beta_pending; nothing once st->done
 hipError_t launch_xpay_fused(const VecSpec& v, void* p, int pp, const void* r, int pr, void* x, CgState* st,
                              const double* partials, int n, hipStream_t s);
-// For n <= 8 lattices (FP64 even fields): x += alpha p for the lattices whose r update ran in this
-// iteration (st->x_pending), then p = r + beta p for those whose solve runs
+// For n <= 8 lattices (FP64 even fields), as launch_xpay_fused for each: beta from the np[i]
+// partials of the update hop, x += alpha p, p = r + beta p unless this iteration stops the
+// lattice; sets st[i]->beta_pending; nothing for a lattice whose solve has stopped
 hipError_t launch_xpay_batch(const VecSpec* vs, void* const* p, const void* const* r, void* const* x,
-                             CgState* const* st, int n, int max_grid, hipStream_t s);
+                             CgState* const* st, const double* const* partials, const int* np, int n, int max_grid,
+                             hipStream_t s);
 // x64 += xs (low precision), then xs = 0
 hipError_t launch_accumulate(const VecSpec& v, void* x64, void* xs, int ps, hipStream_t s);
 hipError_t launch_zero(const VecSpec& v, void* dst, int prec, hipStream_t s);
